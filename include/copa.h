@@ -1,0 +1,167 @@
+/*
+ * copa.h - C ABI of libcopa.so: COPA, constrained PARAFAC2 fitted by AO-ADMM, on one AMD GPU
+ * (gfx950 / MI355X).
+ *
+ * Model (Background, "Original PARAFAC2 model"; Section "General Framework", eq.
+ * PARAFAC2_obj_func): each subject k has a sparse count matrix X_k (I_k visits x J features) and
+ *     X_k ~= U_k S_k V^T,  U_k = Q_k H,  Q_k^T Q_k = I,  S_k = diag(W(k,:)),
+ * fitted by Algorithm 1 (COPA): per outer iteration a Procrustes step gives Q_k (eq. solv_Q),
+ * then one ADMM block per factor H, W, V (update rules after eq. Solve_W) with a proximity
+ * operator per factor (Section "Examples of useful constraints"). With temporal smoothing
+ * (Section "Smoothness on U_k") every subject's U_k lies in the span of a cubic spline basis
+ * M_k evaluated at its visit days; the fit then runs on C_k^T X_k with C_k an orthonormal basis
+ * of span(M_k), and U_k = C_k Q_k H.
+ *
+ * Conventions
+ *  - Every pointer named "device" is GPU memory on the current HIP device; "host" is CPU memory.
+ *  - Matrices are row-major: H is R x R, V is J x R, W is K x R, Qtilde is S x R (row i belongs
+ *    to visit row i of the input; U_k = Qtilde_k H).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream). All GPU work is
+ *    ordered on it. Calls return after enqueueing, except where a call says it synchronises.
+ *  - Errors: every call returns a copa_status and never aborts; copa_last_error() gives a
+ *    thread-local message for the last failure of the calling thread.
+ */
+#ifndef COPA_H
+#define COPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  COPA_OK = 0,
+  COPA_EINVAL = -1,        /* bad argument, shape or input content (checked before any update) */
+  COPA_ENOMEM = -2,        /* device allocation failed */
+  COPA_EDEVICE = -3,       /* a HIP runtime call failed */
+  COPA_ENUMERIC = -4,      /* non-finite value or failed Cholesky during the fit */
+  COPA_EUNSUPPORTED = -5   /* a size outside what this build supports (R, l) */
+} copa_status;
+
+/* Proximity operators (Section "Examples of useful constraints"). The prox argument is
+ * x = Z - D (Algorithm 1 inner loop) and rho is the mode's ADMM step size.
+ *   NONE       x                            (unconstrained)
+ *   NONNEG     max(0, x)                    (non-negativity)
+ *   L1         sign(x) max(|x| - lam/rho, 0)   (l1 sparsity, soft threshold)
+ *   L0         x if x*x > lam else 0        (l0 sparsity, hard threshold; lam plays mu)
+ *   NONNEG_L1  max(0, x - lam/rho)                                                         */
+typedef enum {
+  COPA_PROX_NONE = 0,
+  COPA_PROX_NONNEG = 1,
+  COPA_PROX_L1 = 2,
+  COPA_PROX_L0 = 3,
+  COPA_PROX_NONNEG_L1 = 4
+} copa_prox;
+
+/* The irregular tensor {X_k}: CSR by subject (Algorithm 1 input). All arrays are device memory
+ * owned by the caller; copa_plan_create copies what it needs, so they may be freed afterwards.
+ *   subj_ptr [K+1]  visit-row offsets: subject k owns rows [subj_ptr[k], subj_ptr[k+1]),
+ *                   subj_ptr[0] = 0, non-decreasing, subj_ptr[K] = S (a subject may have 0 rows)
+ *   row_ptr  [S+1]  nonzero offsets per visit row, row_ptr[0] = 0, row_ptr[S] = nnz
+ *   col      [nnz]  feature ids in [0, J), strictly increasing within a row
+ *   val      [nnz]  finite values (counts in the paper's use)
+ *   days     [S]    visit day of each row (finite), read only when l > 0
+ * Limits: S and nnz below 2^31; J below 2^31.                                              */
+typedef struct copa_tensor {
+  int64_t K, J, S, nnz;
+  const int64_t *subj_ptr;
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const float *val;
+  const double *days;
+  int32_t l; /* spline basis functions per subject; 0 = no smoothing; this build: 0 or 1..8 */
+} copa_tensor;
+
+/* Fit options. R: target rank (this build: 1..64 from the list copa_rank_supported accepts).
+ * inner_iters: ADMM steps per factor per outer iteration (>= 1). rank_rtol: Procrustes
+ * truncation - singular values of X_k' V S_k H^T at or below rank_rtol * sigma_1 are dropped
+ * (default 1e-6 when <= 0). basis_rtol: rank tolerance of the smoothing basis M_k (default 1e-10
+ * when <= 0). lambda_*: penalty weight of each factor's prox (see copa_prox).                */
+typedef struct copa_options {
+  int32_t R;
+  int32_t inner_iters;
+  int32_t prox_H, prox_W, prox_V;
+  double lambda_H, lambda_W, lambda_V;
+  double rank_rtol;
+  double basis_rtol;
+} copa_options;
+
+/* Fit state, device memory owned by the caller, FP32 row-major. In: the starting point
+ * (auxiliary variables Hbar = H, Wbar = W, Vbar = V and duals D_*; D_* = 0 for a fresh start).
+ * Out: the state after the last iteration (Algorithm 1 output H = Hbar_1, W = Hbar_2,
+ * V = Hbar_3); passing it back continues the fit exactly where it stopped.
+ *   H, D_H: R x R;  W, D_W: K x R;  V, D_V: J x R                                           */
+typedef struct copa_state {
+  float *H, *W, *V;
+  float *D_H, *D_W, *D_V;
+} copa_state;
+
+/* Fit report (host memory). fit_history / objective_history are optional host arrays of
+ * length `iters` (NULL to skip). FIT = 1 - sum_k ||X_k - U_k S_k V^T||^2 / sum_k ||X_k||^2
+ * (Section "Evaluation Metrics"); objective = 1/2 sum_k ||X_k - U_k S_k V^T||^2 plus the
+ * l1 penalties; sparsity_V = share of exact zeros in V (SPARSITY metric).
+ * rank_deficient: subjects whose Procrustes rank was below min(rows, R) in the last iteration
+ * (zero entries of W, rank-deficient smoothing bases, ...).                                  */
+typedef struct copa_report {
+  int32_t iters_done;
+  int32_t fail_iter; /* first iteration with a non-finite value or Cholesky failure, or -1 */
+  double fit;
+  double objective;
+  double sparsity_V;
+  int64_t rank_deficient;
+  double *fit_history;
+  double *objective_history;
+} copa_report;
+
+typedef struct copa_plan copa_plan;
+
+/* Validates the tensor (shapes on the host, CSR content on the device), packs it into the
+ * plan's device memory, builds the per-subject smoothing bases (l > 0) and allocates every
+ * buffer the fit needs. Allocates device memory (hipMalloc) and synchronises `stream`; nothing
+ * is allocated by later calls. Returns COPA_EINVAL for bad shapes or content,
+ * COPA_EUNSUPPORTED for R or l outside this build, COPA_ENOMEM when memory runs out.       */
+copa_status copa_plan_create(const copa_tensor *X, const copa_options *opt, void *stream,
+                             copa_plan **out);
+
+/* Runs `iters` outer iterations of Algorithm 1 from `state` (updated in place). Qtilde
+ * (device, S x R, may be NULL) receives C_k Q_k of the last iteration (Q_k without smoothing),
+ * so that U_k = Qtilde_k H. `rep` (host, may be NULL) receives the report. Synchronises
+ * `stream` once at the end to read the per-iteration scalars. Returns COPA_ENUMERIC (and sets
+ * rep->fail_iter) when a non-finite value or a Cholesky failure occurred; the state then holds
+ * the values of the last iteration. iters = 0 is valid and only refreshes Qtilde/rep if any. */
+copa_status copa_fit(copa_plan *plan, const copa_state *state, int32_t iters, float *Qtilde,
+                     copa_report *rep, void *stream);
+
+/* MTTKRPs of the last completed iteration (Algorithm 1, "F" of each mode): F_H (R x R),
+ * F_W (K x R), F_V (J x R), device, FP32; any may be NULL. Enqueued on `stream`.             */
+copa_status copa_mttkrp_last(copa_plan *plan, float *F_H, float *F_W, float *F_V, void *stream);
+
+/* The smoothing basis the plan built: C (device, S x l, FP32; row i of subject k holds row i
+ * of C_k, columns >= r_k are zero) and rank (device, K, int32: r_k). Only when l > 0.      */
+copa_status copa_plan_basis(copa_plan *plan, float *C, int32_t *rank, void *stream);
+
+/* Reconstruction loss of eq. Classic_PARAFAC2_obj_func with U_k = Qtilde_k H, Qtilde held fixed:
+ *   L = 1/2 sum_k ||X_k - Qtilde_k H S_k V^T||_F^2,  S_k = diag(W(k,:)),
+ * and its gradient: dH (R x R), dV (J x R), dW (K x R), optional dS (K x R x R, the full
+ * dL/dS_k; may be NULL). Inputs and outputs are device FP32; *loss is written to host memory
+ * (the call synchronises `stream`).                                                          */
+copa_status copa_loss_grad(copa_plan *plan, const float *H, const float *V, const float *W,
+                           const float *Qtilde, float *dH, float *dV, float *dW, float *dS,
+                           double *loss, void *stream);
+
+/* Frees every device buffer of the plan (synchronises its device first). NULL is a no-op.   */
+void copa_plan_destroy(copa_plan *plan);
+
+/* 1 if this build has kernels for rank R, else 0.                                           */
+int32_t copa_rank_supported(int32_t R);
+
+const char *copa_status_string(copa_status status);
+const char *copa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COPA_H */

@@ -1,0 +1,144 @@
+// Internal declarations shared by the HIP sources of libcopa.so (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/copa.h"
+
+namespace copa {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kLMax = 8;           // spline basis functions per subject (padded row width of C)
+constexpr int kNMax = 8;           // largest Procrustes eigenproblem handled one subject per lane
+constexpr int kHistCap = 1024;     // per-iteration scalars buffered on the device
+constexpr int kGramBlocks = 512;   // partial-sum blocks of the row-Gram reductions
+constexpr int kMaxR = 64;
+
+void set_error(const std::string &msg);
+
+#define COPA_HIP(call)                                                                         \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      ::copa::set_error(std::string(#call) + ": " + hipGetErrorString(e_));                    \
+      return COPA_EDEVICE;                                                                     \
+    }                                                                                          \
+  } while (0)
+
+// One entry of the per-pass wave work list: a wave takes `count` subjects of `order` starting at
+// `first`, G = 1 << lg lanes per subject (lanes of one subject are consecutive).
+struct WaveEntry {
+  int32_t first;
+  int32_t lg_count;  // lg | (count << 8)
+};
+
+// Scalars of one ADMM mode for one outer iteration, written by the single-block prep kernels.
+struct ModeParams {
+  double rho;
+  double L[kMaxR * kMaxR];  // Cholesky factor of G + rho I, row-major lower triangle
+};
+
+// Device-side scalars of the fit (one struct, zeroed per copa_fit call).
+struct FitScalars {
+  int32_t iter;            // iterations completed in this call
+  int32_t fail_iter;       // first failing iteration or INT_MAX
+  int32_t rank_deficient;  // subjects with truncated Procrustes rank (last iteration)
+  int32_t rank_def_cur;    // same, accumulating during the current iteration
+  double hist_fit[kHistCap];
+  double hist_obj[kHistCap];
+  double last_fit, last_obj, last_sparsity;
+};
+
+struct Tiles {
+  int nt;  // number of column tiles of R
+  int rt;  // tile width
+};
+
+}  // namespace copa
+
+struct copa_plan {
+  int device;
+  int64_t K, J, S, nnz;
+  int l;           // basis functions (0 = no smoothing)
+  int R;
+  int slot_rows;   // smoothed: l rows per subject; unsmoothed: rows follow the visit rows
+  int64_t rows_total;  // rows of the T/Q/M row spaces
+  copa_options opt;
+  copa::Tiles tiles;
+  int lds_limit;
+
+  // packed tensor
+  int32_t *subj = nullptr;   // [K+1]
+  int32_t *row = nullptr;    // [S+1]
+  int32_t *col = nullptr;    // [nnz]
+  float *val = nullptr;      // [nnz]
+  int32_t *rowsubj = nullptr;  // [S] subject of each visit row (unsmoothed only)
+  float *C = nullptr;        // [S x 8] smoothing basis rows (l > 0)
+  int32_t *rk = nullptr;     // [K] basis ranks (l > 0)
+  int32_t *order = nullptr;  // [K] subjects by decreasing visit count
+  copa::WaveEntry *waves = nullptr;
+  int32_t n_waves = 0;
+  int32_t n_big = 0;         // unsmoothed subjects whose eigenproblem exceeds kNMax
+  int32_t *big_list = nullptr;
+  double normX2 = 0.0;
+
+  // iteration buffers
+  float *T = nullptr;   // [rows_total x R]  X'_k V rows (Procrustes input)
+  float *Q = nullptr;   // [rows_total x R]  Q_k rows
+  float *M = nullptr;   // [rows_total x R]  Q_k H S_k rows
+  float *FW = nullptr;  // [K x R]
+  float *FV = nullptr;  // [J x R]
+  float *FVpart = nullptr;  // [n_fv_blocks x J x R] pass-2 partials (LDS path)
+  int n_fv_blocks = 0;
+  bool fv_lds = true;
+  double *gpart = nullptr;  // [kGramBlocks x R x R] scratch partials (row Grams)
+  double *gpart2 = nullptr; // second partial buffer
+  double *vpart = nullptr;  // [blocks x 4] V-ADMM scalar partials
+  int n_vblocks = 0;
+  double *wpart = nullptr;  // [ceil(K/64)] |W|_1 partials of the W update
+  double *small = nullptr;  // FH, HtH, WtW, VtV, Psi : 5 x R x R
+  copa::ModeParams *modes = nullptr;  // [3]
+  copa::FitScalars *scal = nullptr;
+  double *dloss = nullptr;  // loss/grad scalars
+  float *gradbuf = nullptr; // [rows_total x R] scratch for the adjoint
+};
+
+namespace copa {
+
+// ---------------------------------------------------------------- launchers (copa_iter.hip)
+copa_status launch_iteration(copa_plan *p, const copa_state *st, hipStream_t s);
+copa_status launch_init_grams(copa_plan *p, const copa_state *st, hipStream_t s);
+copa_status launch_qtilde(copa_plan *p, float *Qt, hipStream_t s);
+bool rank_supported(int R);
+Tiles choose_tiles(int R, int64_t J, int lds_limit);
+
+// ---------------------------------------------------------------- (copa_grad.hip)
+copa_status launch_loss_grad(copa_plan *p, const float *H, const float *V, const float *W,
+                             const float *Qt, float *dH, float *dV, float *dW, float *dS,
+                             hipStream_t s);
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ double prox_apply(double x, int kind, double lam, double rho) {
+  switch (kind) {
+    case COPA_PROX_NONNEG: return x > 0.0 ? x : 0.0;
+    case COPA_PROX_L1: {
+      double a = fabs(x) - lam / rho;
+      return a > 0.0 ? copysign(a, x) : 0.0;
+    }
+    case COPA_PROX_L0: return x * x > lam ? x : 0.0;
+    case COPA_PROX_NONNEG_L1: {
+      double a = x - lam / rho;
+      return a > 0.0 ? a : 0.0;
+    }
+    default: return x;
+  }
+}
+
+__device__ __forceinline__ float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, kWave); }
+
+}  // namespace copa

@@ -1,0 +1,581 @@
+// Plan creation for libcopa.so: argument and CSR validation, packing of the tensor into the plan's
+// device memory, per-subject smoothing bases and the wave work list of the streaming passes.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <numeric>
+
+#include "copa_common.h"
+
+namespace copa {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+// ------------------------------------------------------------------------------------ checks
+enum : int32_t {
+  kBadSubjPtr = 1, kBadRowPtr = 2, kBadCol = 4, kUnsortedCol = 8, kBadVal = 16, kBadDays = 32
+};
+
+__global__ void k_check_offsets(const int64_t *subj_ptr, const int64_t *row_ptr, int64_t K,
+                                int64_t S, int64_t nnz, int32_t *flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= K) {
+    int64_t v = subj_ptr[i];
+    bool bad = (i == 0 && v != 0) || (i == K && v != S) || (i < K && subj_ptr[i + 1] < v);
+    if (bad) atomicOr(flags, kBadSubjPtr);
+  }
+  if (i <= S) {
+    int64_t v = row_ptr[i];
+    bool bad = (i == 0 && v != 0) || (i == S && v != nnz) || (i < S && row_ptr[i + 1] < v);
+    if (bad) atomicOr(flags, kBadRowPtr);
+  }
+}
+
+// Thread per visit row: columns in range and strictly increasing, values finite, days finite.
+// Only launched once the offsets are known to be monotone and in range.
+__global__ void k_check_rows(const int64_t *row_ptr, const int32_t *col, const float *val,
+                             const double *days, int64_t S, int64_t J, int32_t *flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S) return;
+  int64_t a = row_ptr[i], b = row_ptr[i + 1];
+  int32_t f = 0;
+  int64_t prev = -1;
+  for (int64_t e = a; e < b; ++e) {
+    int64_t c = col[e];
+    if (c < 0 || c >= J) f |= kBadCol;
+    if (c <= prev) f |= kUnsortedCol;
+    prev = c;
+    if (!isfinite(val[e])) f |= kBadVal;
+  }
+  if (days && !isfinite(days[i])) f |= kBadDays;
+  if (f) atomicOr(flags, f);
+}
+
+__global__ void k_pack_offsets(const int64_t *src, int32_t *dst, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (int32_t)src[i];
+}
+
+__global__ void k_row_subject(const int32_t *subj, int32_t *rowsubj, int64_t K) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  for (int32_t i = subj[k]; i < subj[k + 1]; ++i) rowsubj[i] = (int32_t)k;
+}
+
+// sum of squares of the values, FP64, one partial per block then a single-block finish
+__global__ void k_sumsq(const float *val, int64_t n, double *part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = val[e];
+    acc += v * v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// ------------------------------------------------------------------------- smoothing basis
+// Cubic (degree min(3, L-1)) spline basis on the clamped knot vector of [t1, tn] with L-d-1
+// equally spaced interior knots, evaluated by the triangular recursion of the smoothness section
+// (degree-0 pieces are 1 on [b_i, b_{i+1}), the last nonempty piece also holds tn; a ratio with a
+// zero denominator counts as 0). Every index is a compile-time constant.
+template <int L>
+__device__ __forceinline__ void spline_row(double t, const double (&beta)[L + 4], double (&m)[L]) {
+  constexpr int d = L - 1 < 3 ? L - 1 : 3;
+  constexpr int NB = L + d;  // degree-0 pieces
+  double N[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    bool in = beta[i] <= t && t < beta[i + 1];
+    if (i == L - 1 && t == beta[L]) in = true;  // last nonempty piece is closed
+    N[i] = in ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int p = 1; p <= d; ++p) {
+#pragma unroll
+    for (int i = 0; i < NB - p; ++i) {
+      double den1 = beta[i + p] - beta[i];
+      double den2 = beta[i + p + 1] - beta[i + 1];
+      double a = den1 != 0.0 ? (t - beta[i]) / den1 * N[i] : 0.0;
+      double b = den2 != 0.0 ? (beta[i + p + 1] - t) / den2 * N[i + 1] : 0.0;
+      N[i] = a + b;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < L; ++i) m[i] = N[i];
+}
+
+// One subject per lane. Streams the basis rows through Givens rotations into an L x L upper
+// triangle R (M_k = Q_M R), takes the SVD of R by one-sided Jacobi (columns orthogonalised), sorts
+// the singular values, keeps sigma > rtol * sigma_1 and writes C_k = M_k V_r Sigma_r^{-1}, an
+// orthonormal basis of span(M_k), as FP32 rows of width kLMax.
+template <int L>
+__global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double *days, float *C,
+                                              int32_t *rk, int64_t K, double rtol) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int r0 = subj[k], r1 = subj[k + 1];
+  if (r1 == r0) {
+    rk[k] = 0;
+    return;
+  }
+  double t1 = days[r0], tn = days[r0];
+  for (int i = r0 + 1; i < r1; ++i) {
+    t1 = fmin(t1, days[i]);
+    tn = fmax(tn, days[i]);
+  }
+  if (t1 == tn) {  // no time span: the basis is the constant function
+    const float c0 = (float)(1.0 / sqrt((double)(r1 - r0)));
+    for (int i = r0; i < r1; ++i) {
+#pragma unroll
+      for (int a = 0; a < kLMax; ++a) C[(int64_t)i * kLMax + a] = a == 0 ? c0 : 0.0f;
+    }
+    rk[k] = 1;
+    return;
+  }
+  constexpr int d = L - 1 < 3 ? L - 1 : 3;
+  constexpr int ninner = L - d - 1;
+  double beta[L + 4];
+#pragma unroll
+  for (int i = 0; i < L + 4; ++i) beta[i] = tn;
+#pragma unroll
+  for (int i = 0; i <= d; ++i) beta[i] = t1;
+#pragma unroll
+  for (int j = 1; j <= ninner; ++j) beta[d + j] = t1 + (tn - t1) * j / (ninner + 1);
+
+  double R[L][L];
+#pragma unroll
+  for (int a = 0; a < L; ++a)
+#pragma unroll
+    for (int b = 0; b < L; ++b) R[a][b] = 0.0;
+  for (int i = r0; i < r1; ++i) {
+    double m[L];
+    spline_row<L>(days[i], beta, m);
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      if (m[j] != 0.0) {
+        double h = hypot(R[j][j], m[j]);
+        double c = R[j][j] / h, s = m[j] / h;
+#pragma unroll
+        for (int q = j; q < L; ++q) {
+          double x = R[j][q], y = m[q];
+          R[j][q] = c * x + s * y;
+          m[q] = -s * x + c * y;
+        }
+      }
+    }
+  }
+  double Vr[L][L];
+#pragma unroll
+  for (int a = 0; a < L; ++a)
+#pragma unroll
+    for (int b = 0; b < L; ++b) Vr[a][b] = a == b ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    bool rotated = false;
+#pragma unroll
+    for (int p = 0; p < L - 1; ++p) {
+#pragma unroll
+      for (int q = p + 1; q < L; ++q) {
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+          al += R[i][p] * R[i][p];
+          be += R[i][q] * R[i][q];
+          ga += R[i][p] * R[i][q];
+        }
+        if (fabs(ga) > 1e-15 * sqrt(al * be) && ga != 0.0) {
+          rotated = true;
+          double zeta = (be - al) / (2.0 * ga);
+          double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+#pragma unroll
+          for (int i = 0; i < L; ++i) {
+            double x = R[i][p], y = R[i][q];
+            R[i][p] = c * x - s * y;
+            R[i][q] = s * x + c * y;
+            double u = Vr[i][p], v = Vr[i][q];
+            Vr[i][p] = c * u - s * v;
+            Vr[i][q] = s * u + c * v;
+          }
+        }
+      }
+    }
+    if (!rotated) break;
+  }
+  double sig[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) s2 += R[i][j] * R[i][j];
+    sig[j] = sqrt(s2);
+  }
+  // sort columns by decreasing sigma (exchange network on compile-time indices)
+#pragma unroll
+  for (int a = 0; a < L; ++a) {
+#pragma unroll
+    for (int b = 0; b < L - 1 - a; ++b) {
+      if (sig[b] < sig[b + 1]) {
+        double t = sig[b];
+        sig[b] = sig[b + 1];
+        sig[b + 1] = t;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+          double u = Vr[i][b];
+          Vr[i][b] = Vr[i][b + 1];
+          Vr[i][b + 1] = u;
+        }
+      }
+    }
+  }
+  int r = 0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) r += (sig[0] > 0.0 && sig[j] > rtol * sig[0]) ? 1 : 0;
+  // E = V_r Sigma_r^{-1}
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    double inv = j < r ? 1.0 / sig[j] : 0.0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) Vr[i][j] *= inv;
+  }
+  for (int i = r0; i < r1; ++i) {
+    double m[L];
+    spline_row<L>(days[i], beta, m);
+#pragma unroll
+    for (int j = 0; j < kLMax; ++j) {
+      double c = 0.0;
+      if (j < L) {
+#pragma unroll
+        for (int a = 0; a < L; ++a) c += m[a] * Vr[a][j < L ? j : 0];
+      }
+      C[(int64_t)i * kLMax + j] = (float)c;
+    }
+  }
+  rk[k] = r;
+}
+
+static copa_status launch_basis(int l, const int32_t *subj, const double *days, float *C,
+                                int32_t *rk, int64_t K, double rtol, hipStream_t s) {
+  dim3 g((unsigned)((K + 63) / 64)), b(64);
+  switch (l) {
+#define CASE(Lv) \
+  case Lv: k_basis<Lv><<<g, b, 0, s>>>(subj, days, C, rk, K, rtol); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: set_error("l outside 0..8"); return COPA_EUNSUPPORTED;
+  }
+  COPA_HIP(hipGetLastError());
+  return COPA_OK;
+}
+
+template <typename T>
+static copa_status dalloc(T **ptr, size_t count) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void **)ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    set_error(std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes: " +
+              hipGetErrorString(e));
+    return COPA_ENOMEM;
+  }
+  return COPA_OK;
+}
+
+#define COPA_TRY(x)                   \
+  do {                                \
+    copa_status st_ = (x);            \
+    if (st_ != COPA_OK) return st_;   \
+  } while (0)
+
+static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hipStream_t s,
+                              copa_plan *p) {
+  p->K = X->K;
+  p->J = X->J;
+  p->S = X->S;
+  p->nnz = X->nnz;
+  p->l = X->l;
+  p->R = opt->R;
+  p->opt = *opt;
+  if (p->opt.rank_rtol <= 0.0) p->opt.rank_rtol = 1e-6;
+  if (p->opt.basis_rtol <= 0.0) p->opt.basis_rtol = 1e-10;
+  COPA_HIP(hipGetDevice(&p->device));
+  int lds = 0;
+  COPA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+  p->lds_limit = std::min(lds, 65536);
+
+  const int64_t K = p->K, S = p->S, nnz = p->nnz;
+  // ---- content checks on the device
+  int32_t *flags = nullptr;
+  COPA_TRY(dalloc(&flags, 1));
+  COPA_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), s));
+  {
+    int64_t n = std::max(K, S) + 1;
+    k_check_offsets<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(X->subj_ptr, X->row_ptr, K, S,
+                                                                 nnz, flags);
+    COPA_HIP(hipGetLastError());
+  }
+  int32_t hflags = 0;
+  COPA_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipStreamSynchronize(s));
+  if (hflags == 0 && S > 0) {
+    k_check_rows<<<(unsigned)((S + 255) / 256), 256, 0, s>>>(X->row_ptr, X->col, X->val,
+                                                              p->l > 0 ? X->days : nullptr, S,
+                                                              p->J, flags);
+    COPA_HIP(hipGetLastError());
+    COPA_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    COPA_HIP(hipStreamSynchronize(s));
+  }
+  (void)hipFree(flags);
+  if (hflags) {
+    std::string m = "invalid tensor:";
+    if (hflags & kBadSubjPtr) m += " subj_ptr not 0..S non-decreasing;";
+    if (hflags & kBadRowPtr) m += " row_ptr not 0..nnz non-decreasing;";
+    if (hflags & kBadCol) m += " column id outside [0,J);";
+    if (hflags & kUnsortedCol) m += " columns not strictly increasing within a row;";
+    if (hflags & kBadVal) m += " non-finite value;";
+    if (hflags & kBadDays) m += " non-finite visit day;";
+    set_error(m);
+    return COPA_EINVAL;
+  }
+
+  // ---- packing
+  COPA_TRY(dalloc(&p->subj, K + 1));
+  COPA_TRY(dalloc(&p->row, S + 1));
+  COPA_TRY(dalloc(&p->col, nnz));
+  COPA_TRY(dalloc(&p->val, nnz));
+  k_pack_offsets<<<(unsigned)((K + 1 + 255) / 256), 256, 0, s>>>(X->subj_ptr, p->subj, K + 1);
+  k_pack_offsets<<<(unsigned)((S + 1 + 255) / 256), 256, 0, s>>>(X->row_ptr, p->row, S + 1);
+  COPA_HIP(hipGetLastError());
+  if (nnz > 0) {
+    COPA_HIP(hipMemcpyAsync(p->col, X->col, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    COPA_HIP(hipMemcpyAsync(p->val, X->val, nnz * sizeof(float), hipMemcpyDeviceToDevice, s));
+  }
+  {
+    constexpr int nb = 512;
+    double *part = nullptr;
+    COPA_TRY(dalloc(&part, nb));
+    k_sumsq<<<nb, 256, 0, s>>>(p->val, nnz, part);
+    COPA_HIP(hipGetLastError());
+    std::vector<double> h(nb);
+    COPA_HIP(hipMemcpyAsync(h.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    COPA_HIP(hipStreamSynchronize(s));
+    (void)hipFree(part);
+    p->normX2 = 0.0;
+    for (double v : h) p->normX2 += v;
+  }
+
+  // ---- subject order and wave work list (host): subjects by decreasing visit count; a wave
+  // gives G = 2^lg lanes to each subject with G ~ I_max / 4 rows per lane
+  std::vector<int64_t> hs(K + 1);
+  COPA_HIP(hipMemcpyAsync(hs.data(), X->subj_ptr, (K + 1) * sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> ord(K);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+    return hs[a + 1] - hs[a] > hs[b + 1] - hs[b];
+  });
+  std::vector<WaveEntry> waves;
+  for (int64_t i = 0; i < K;) {
+    int64_t ik = hs[ord[i] + 1] - hs[ord[i]];
+    int lg = 0;
+    while ((1 << lg) < kWave && (int64_t)(1 << lg) * 4 < ik) ++lg;
+    int cnt = (int)std::min<int64_t>(kWave >> lg, K - i);
+    waves.push_back(WaveEntry{(int32_t)i, lg | (cnt << 8)});
+    i += cnt;
+  }
+  p->n_waves = (int32_t)waves.size();
+  COPA_TRY(dalloc(&p->order, K));
+  COPA_TRY(dalloc(&p->waves, waves.size()));
+  if (K > 0)
+    COPA_HIP(hipMemcpyAsync(p->order, ord.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (!waves.empty())
+    COPA_HIP(hipMemcpyAsync(p->waves, waves.data(), waves.size() * sizeof(WaveEntry),
+                            hipMemcpyHostToDevice, s));
+
+  COPA_TRY(dalloc(&p->rowsubj, S));
+  if (K > 0) {
+    k_row_subject<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(p->subj, p->rowsubj, K);
+    COPA_HIP(hipGetLastError());
+  }
+  // ---- smoothing basis
+  if (p->l > 0) {
+    p->slot_rows = p->l;
+    p->rows_total = K * p->l;
+    COPA_TRY(dalloc(&p->C, S * kLMax));
+    COPA_TRY(dalloc(&p->rk, K));
+    if (K > 0) COPA_TRY(launch_basis(p->l, p->subj, X->days, p->C, p->rk, K, p->opt.basis_rtol, s));
+  } else {
+    p->slot_rows = 0;
+    p->rows_total = S;
+    // subjects whose eigenproblem min(I_k, R) is larger than a lane can hold
+    std::vector<int32_t> big;
+    for (int64_t k = 0; k < K; ++k)
+      if (std::min<int64_t>(hs[k + 1] - hs[k], p->R) > kNMax) big.push_back((int32_t)k);
+    p->n_big = (int32_t)big.size();
+    COPA_TRY(dalloc(&p->big_list, big.size()));
+    if (!big.empty())
+      COPA_HIP(hipMemcpyAsync(p->big_list, big.data(), big.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+  }
+
+  // ---- iteration buffers
+  const int R = p->R;
+  p->tiles = choose_tiles(R, p->J, p->lds_limit);
+  if ((int64_t)p->J * ((p->tiles.rt + 3) & ~3) * 4 > p->lds_limit) {
+    set_error("J too large for the LDS-staged factor tile of this build");
+    return COPA_EUNSUPPORTED;
+  }
+  COPA_TRY(dalloc(&p->T, p->rows_total * R));
+  COPA_TRY(dalloc(&p->Q, p->rows_total * R));
+  COPA_TRY(dalloc(&p->M, p->rows_total * R));
+  COPA_TRY(dalloc(&p->FW, K * R));
+  COPA_TRY(dalloc(&p->FV, p->J * R));
+  p->fv_lds = (int64_t)p->J * p->tiles.rt * 4 <= p->lds_limit;
+  p->n_fv_blocks = 256;
+  if (p->fv_lds) COPA_TRY(dalloc(&p->FVpart, (size_t)p->n_fv_blocks * p->J * R));
+  COPA_TRY(dalloc(&p->gpart, (size_t)kGramBlocks * R * R));
+  COPA_TRY(dalloc(&p->gpart2, (size_t)kGramBlocks * R * R));
+  p->n_vblocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (p->J + 255) / 256));
+  COPA_TRY(dalloc(&p->vpart, (size_t)p->n_vblocks * 4));
+  COPA_TRY(dalloc(&p->wpart, (size_t)std::max<int64_t>(1, (K + 63) / 64)));
+  COPA_TRY(dalloc(&p->small, 8 * R * R));
+  COPA_TRY(dalloc(&p->modes, 3));
+  COPA_TRY(dalloc(&p->scal, 1));
+  COPA_TRY(dalloc(&p->dloss, 64));
+  COPA_HIP(hipMemsetAsync(p->T, 0, p->rows_total * R * sizeof(float), s));
+  COPA_HIP(hipMemsetAsync(p->Q, 0, p->rows_total * R * sizeof(float), s));
+  COPA_HIP(hipMemsetAsync(p->M, 0, p->rows_total * R * sizeof(float), s));
+  COPA_HIP(hipMemsetAsync(p->FW, 0, K * R * sizeof(float), s));
+  COPA_HIP(hipMemsetAsync(p->FV, 0, p->J * R * sizeof(float), s));
+  COPA_HIP(hipMemsetAsync(p->small, 0, 8 * R * R * sizeof(double), s));
+  COPA_HIP(hipStreamSynchronize(s));
+  return COPA_OK;
+}
+
+}  // namespace copa
+
+using namespace copa;
+
+static void free_plan(copa_plan *p) {
+  void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->C, p->rk, p->order, p->waves,
+                  p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->FVpart, p->gpart, p->gpart2,
+                  p->vpart, p->wpart, p->small, p->modes, p->scal, p->dloss, p->gradbuf};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  delete p;
+}
+
+extern "C" {
+
+const char *copa_last_error(void) { return g_last_error.c_str(); }
+
+const char *copa_status_string(copa_status st) {
+  switch (st) {
+    case COPA_OK: return "COPA_OK";
+    case COPA_EINVAL: return "COPA_EINVAL";
+    case COPA_ENOMEM: return "COPA_ENOMEM";
+    case COPA_EDEVICE: return "COPA_EDEVICE";
+    case COPA_ENUMERIC: return "COPA_ENUMERIC";
+    case COPA_EUNSUPPORTED: return "COPA_EUNSUPPORTED";
+  }
+  return "COPA_UNKNOWN";
+}
+
+int32_t copa_rank_supported(int32_t R) { return rank_supported(R) ? 1 : 0; }
+
+copa_status copa_plan_create(const copa_tensor *X, const copa_options *opt, void *stream,
+                             copa_plan **out) {
+  if (!out) {
+    set_error("out is NULL");
+    return COPA_EINVAL;
+  }
+  *out = nullptr;
+  if (!X || !opt) {
+    set_error("tensor or options is NULL");
+    return COPA_EINVAL;
+  }
+  if (X->K < 0 || X->J < 1 || X->S < 0 || X->nnz < 0 || X->S >= INT32_MAX ||
+      X->nnz >= INT32_MAX || X->J >= INT32_MAX || X->K >= INT32_MAX) {
+    set_error("sizes must satisfy K >= 0, J >= 1, S >= 0, nnz >= 0, all below 2^31");
+    return COPA_EINVAL;
+  }
+  if (!X->subj_ptr || !X->row_ptr || (X->nnz > 0 && (!X->col || !X->val))) {
+    set_error("tensor array is NULL");
+    return COPA_EINVAL;
+  }
+  if (X->l < 0) {
+    set_error("l must be >= 0");
+    return COPA_EINVAL;
+  }
+  if (X->l > kLMax) {
+    set_error("l > 8 spline basis functions is not supported by this build");
+    return COPA_EUNSUPPORTED;
+  }
+  if (X->l > 0 && X->S > 0 && !X->days) {
+    set_error("days is NULL with l > 0");
+    return COPA_EINVAL;
+  }
+  if (opt->R < 1 || opt->inner_iters < 1) {
+    set_error("R and inner_iters must be >= 1");
+    return COPA_EINVAL;
+  }
+  for (int32_t k : {opt->prox_H, opt->prox_W, opt->prox_V})
+    if (k < COPA_PROX_NONE || k > COPA_PROX_NONNEG_L1) {
+      set_error("unknown prox kind");
+      return COPA_EINVAL;
+    }
+  if (!(opt->lambda_H >= 0.0 && opt->lambda_W >= 0.0 && opt->lambda_V >= 0.0)) {
+    set_error("lambda must be finite and >= 0");
+    return COPA_EINVAL;
+  }
+  if (!rank_supported(opt->R)) {
+    set_error("rank R=" + std::to_string(opt->R) + " has no kernels in this build");
+    return COPA_EUNSUPPORTED;
+  }
+  copa_plan *p = new copa_plan();
+  copa_status st = build_plan(X, opt, (hipStream_t)stream, p);
+  if (st == COPA_OK && p->n_big > 0) {
+    set_error("unsmoothed subjects with min(I_k, R) > 8 need the wave Procrustes kernel");
+    st = COPA_EUNSUPPORTED;
+  }
+  if (st != COPA_OK) {
+    (void)hipDeviceSynchronize();
+    free_plan(p);
+    return st;
+  }
+  *out = p;
+  return COPA_OK;
+}
+
+copa_status copa_plan_basis(copa_plan *p, float *C, int32_t *rank, void *stream) {
+  if (!p || p->l == 0) {
+    set_error("plan is NULL or has no smoothing basis");
+    return COPA_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (C) {
+    // the plan keeps rows of width 8; hand out rows of width l
+    COPA_HIP(hipMemcpy2DAsync(C, p->l * sizeof(float), p->C, kLMax * sizeof(float),
+                              p->l * sizeof(float), p->S, hipMemcpyDeviceToDevice, s));
+  }
+  if (rank && p->K > 0)
+    COPA_HIP(hipMemcpyAsync(rank, p->rk, p->K * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  return COPA_OK;
+}
+
+void copa_plan_destroy(copa_plan *p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  free_plan(p);
+}
+
+}  // extern "C"
