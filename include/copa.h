@@ -154,6 +154,17 @@ copa_status copa_loss_grad(copa_plan *plan, const float *H, const float *V, cons
 /* Frees every device buffer of the plan (synchronises its device first). NULL is a no-op.   */
 void copa_plan_destroy(copa_plan *plan);
 
+/* Per-kernel GPU timing of copa_fit for benchmarking. copa_set_timing(plan, 1) makes later
+ * copa_fit calls record a HIP event pair on `stream` around every kernel launch (events are
+ * created here, once per plan; copa_fit then synchronises every 64 iterations to read them).
+ * copa_read_timing writes, per kernel id in [0, COPA_NUM_KERNELS), the summed milliseconds
+ * (`ms`, host) and launch counts (`launches`, host) since the previous read, then resets them.
+ * copa_kernel_name(id) names the kernel.                                                     */
+#define COPA_NUM_KERNELS 13
+copa_status copa_set_timing(copa_plan *plan, int32_t enable);
+copa_status copa_read_timing(copa_plan *plan, double *ms, int64_t *launches);
+const char *copa_kernel_name(int32_t id);
+
 /* 1 if this build has kernels for rank R, else 0.                                           */
 int32_t copa_rank_supported(int32_t R);
 

@@ -22,7 +22,8 @@ PROX_NONE, PROX_NONNEG, PROX_L1, PROX_L0, PROX_NONNEG_L1 = 0, 1, 2, 3, 4
 # every function declared in include/copa.h
 SYMBOLS = ("copa_plan_create", "copa_fit", "copa_mttkrp_last", "copa_plan_basis",
            "copa_loss_grad", "copa_plan_destroy", "copa_rank_supported", "copa_status_string",
-           "copa_last_error")
+           "copa_last_error", "copa_set_timing", "copa_read_timing", "copa_kernel_name")
+NUM_KERNELS = 13
 
 
 class CopaTensor(ctypes.Structure):
@@ -80,8 +81,13 @@ def lib():
         L.copa_status_string.argtypes = [c_int32]
         L.copa_status_string.restype = ctypes.c_char_p
         L.copa_last_error.restype = ctypes.c_char_p
+        L.copa_set_timing.argtypes = [c_void_p, c_int32]
+        L.copa_read_timing.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
+        L.copa_kernel_name.argtypes = [c_int32]
+        L.copa_kernel_name.restype = ctypes.c_char_p
         for name in ("copa_plan_create", "copa_fit", "copa_mttkrp_last", "copa_plan_basis",
-                     "copa_loss_grad", "copa_rank_supported"):
+                     "copa_loss_grad", "copa_rank_supported", "copa_set_timing",
+                     "copa_read_timing"):
             getattr(L, name).restype = c_int32
         _lib = L
     return _lib
@@ -214,6 +220,16 @@ class Plan:
                                     _ptr(dV), _ptr(dW), _ptr(dS), ctypes.byref(loss), _stream()),
                "copa_loss_grad")
         return loss.value, dH, dV, dW, dS
+
+    def set_timing(self, enable=True):
+        _check(lib().copa_set_timing(self._h, int(bool(enable))), "copa_set_timing")
+
+    def read_timing(self):
+        """{kernel name: (summed ms, launches)} since the previous read."""
+        ms = (c_double * NUM_KERNELS)()
+        n = (c_int64 * NUM_KERNELS)()
+        _check(lib().copa_read_timing(self._h, ms, n), "copa_read_timing")
+        return {lib().copa_kernel_name(i).decode(): (ms[i], n[i]) for i in range(NUM_KERNELS)}
 
     def close(self):
         if getattr(self, "_h", None):

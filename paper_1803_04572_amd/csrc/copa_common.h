@@ -16,8 +16,11 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kLMax = 8;           // spline basis functions per subject (padded row width of C)
 constexpr int kNMax = 8;           // largest Procrustes eigenproblem handled one subject per lane
 constexpr int kHistCap = 1024;     // per-iteration scalars buffered on the device
-constexpr int kGramBlocks = 512;   // partial-sum blocks of the row-Gram reductions
+constexpr int kGramBlocks = 128;   // partial-sum blocks of the row-Gram reductions
+constexpr int kChunkRows = 512;    // visit rows per chunk of the feature-sorted pass-2 layout
 constexpr int kMaxR = 64;
+constexpr int kNumKernels = 13;    // kernels of one outer iteration (see kernel_names)
+constexpr int kTimingChunk = 64;   // iterations between event harvests when timing
 
 void set_error(const std::string &msg);
 
@@ -92,12 +95,18 @@ struct copa_plan {
   float *Q = nullptr;   // [rows_total x R]  Q_k rows
   float *M = nullptr;   // [rows_total x R]  Q_k H S_k rows
   float *FW = nullptr;  // [K x R]
+  float *Vp = nullptr;  // [nt x J x RTP] V in padded column tiles (pass-1 LDS image)
   float *FV = nullptr;  // [J x R]
-  float *FVpart = nullptr;  // [n_fv_blocks x J x R] pass-2 partials (LDS path)
-  int n_fv_blocks = 0;
-  bool fv_lds = true;
+  // pass-2 layout: per chunk of kChunkRows visit rows, nonzeros sorted by feature
+  bool p2c = false;
+  int nchunks = 0;
+  int32_t *cptr = nullptr;   // [nchunks+1] nonzero offsets of the chunks
+  int32_t *wsplit = nullptr; // [nchunks x 9] per-wave slices of each chunk (feature boundaries)
+  uint32_t *pkey = nullptr;  // [nnz] feature << 16 | row within chunk
+  float *pval = nullptr;     // [nnz]
+  int n_cu = 0;
   double *gpart = nullptr;  // [kGramBlocks x R x R] scratch partials (row Grams)
-  double *gpart2 = nullptr; // second partial buffer
+  int32_t *gcount = nullptr;  // [8] last-block counters of the row Grams
   double *vpart = nullptr;  // [blocks x 4] V-ADMM scalar partials
   int n_vblocks = 0;
   double *wpart = nullptr;  // [ceil(K/64)] |W|_1 partials of the W update
@@ -105,6 +114,13 @@ struct copa_plan {
   copa::ModeParams *modes = nullptr;  // [3]
   copa::FitScalars *scal = nullptr;
   double *dloss = nullptr;  // loss/grad scalars
+  // optional per-kernel event timing of copa_fit
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kid;
+  int ev_used = 0;
+  double t_ms[copa::kNumKernels] = {};
+  int64_t t_cnt[copa::kNumKernels] = {};
   float *gradbuf = nullptr; // [rows_total x R] scratch for the adjoint
 };
 
@@ -114,6 +130,8 @@ namespace copa {
 copa_status launch_iteration(copa_plan *p, const copa_state *st, hipStream_t s);
 copa_status launch_init_grams(copa_plan *p, const copa_state *st, hipStream_t s);
 copa_status launch_qtilde(copa_plan *p, float *Qt, hipStream_t s);
+copa_status harvest_timing(copa_plan *p);
+extern const char *const kernel_names[kNumKernels];
 bool rank_supported(int R);
 Tiles choose_tiles(int R, int64_t J, int lds_limit);
 

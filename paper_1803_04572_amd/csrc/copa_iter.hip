@@ -49,104 +49,115 @@ Tiles choose_tiles(int R, int64_t J, int lds_limit) {
 enum { kFH = 0, kHtH = 1, kWtW = 2, kVtV = 3, kPsi = 4 };
 
 // ======================================================================= streaming pass 1
-// Wave list: each wave takes `cnt` subjects; G lanes per subject stride over its visit rows.
+// Persistent blocks of 4 waves; each block stages one column tile of V (kept padded to RTP
+// columns per row by the V update) in LDS once, then its waves walk the wave list: each wave takes
+// `cnt` subjects and G lanes per subject stride over the subject's visit rows.
 template <int RT, bool SMOOTH>
 __global__ void __launch_bounds__(256)
     k_pass1(const WaveEntry *__restrict__ waves, int n_waves, const int32_t *__restrict__ order,
             const int32_t *__restrict__ subj, const int32_t *__restrict__ row,
             const int32_t *__restrict__ col, const float *__restrict__ val,
-            const float *__restrict__ C, const float *__restrict__ V, int64_t J, int R, int l,
+            const float *__restrict__ C, const float *__restrict__ Vp, int64_t J, int R, int l,
             float *__restrict__ T) {
   constexpr int RTP = (RT + 3) & ~3;
   extern __shared__ float4 smem4[];
-  float *sV = reinterpret_cast<float *>(smem4);
-  const int c0 = blockIdx.y * RT;
-  for (int64_t e = threadIdx.x; e < J * RTP; e += blockDim.x) {
-    int64_t j = e / RTP;
-    int r = (int)(e - j * RTP);
-    sV[e] = (r < RT && c0 + r < R) ? V[j * R + c0 + r] : 0.0f;
+  {
+    const float4 *src = reinterpret_cast<const float4 *>(Vp + (int64_t)blockIdx.y * J * RTP);
+    const int64_t n4 = J * RTP / 4;
+    for (int64_t e = threadIdx.x; e < n4; e += blockDim.x) smem4[e] = src[e];
   }
   __syncthreads();
-  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wv >= n_waves) return;
+  const float *sV = reinterpret_cast<const float *>(smem4);
+  const int c0 = blockIdx.y * RT;
   const int lane = threadIdx.x & 63;
-  const WaveEntry we = waves[wv];
-  const int lg = we.lg_count & 255, cnt = we.lg_count >> 8;
-  const int G = 1 << lg, sidx = lane >> lg, sub = lane & (G - 1);
-  const bool active = sidx < cnt;
-  const int k = active ? order[we.first + sidx] : 0;
-  const int r0 = active ? subj[k] : 0, r1 = active ? subj[k + 1] : 0;
-
-  if constexpr (SMOOTH) {
-    float acc[kLMax][RT];
+  for (int wv = blockIdx.x * 4 + (threadIdx.x >> 6); wv < n_waves; wv += gridDim.x * 4) {
+    const WaveEntry we = waves[wv];
+    const int lg = we.lg_count & 255, cnt = we.lg_count >> 8;
+    const int G = 1 << lg, sidx = lane >> lg, sub = lane & (G - 1);
+    const bool active = sidx < cnt;
+    const int k = active ? order[we.first + sidx] : 0;
+    const int r0 = active ? subj[k] : 0, r1 = active ? subj[k + 1] : 0;
+    if constexpr (SMOOTH) {
+      float acc[kLMax][RT];
 #pragma unroll
-    for (int a = 0; a < kLMax; ++a)
+      for (int a = 0; a < kLMax; ++a)
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[a][r] = 0.0f;
-    for (int i = r0 + sub; i < r1; i += G) {
-      float t[RTP];
+        for (int r = 0; r < RT; ++r) acc[a][r] = 0.0f;
+      for (int i = r0 + sub; i < r1; i += G) {
+        float t[RTP];
 #pragma unroll
-      for (int r = 0; r < RTP; ++r) t[r] = 0.0f;
-      const int e1 = row[i + 1];
-      for (int e = row[i]; e < e1; ++e) {
-        const float x = val[e];
-        const float4 *v4 = reinterpret_cast<const float4 *>(sV + (int64_t)col[e] * RTP);
+        for (int r = 0; r < RTP; ++r) t[r] = 0.0f;
+        const int e1 = row[i + 1];
+        for (int e = row[i]; e < e1; ++e) {
+          const float x = val[e];
+          const float4 *v4 = reinterpret_cast<const float4 *>(sV + (int64_t)col[e] * RTP);
 #pragma unroll
-        for (int q = 0; q < RTP / 4; ++q) {
-          float4 v = v4[q];
-          t[4 * q + 0] += x * v.x;
-          t[4 * q + 1] += x * v.y;
-          t[4 * q + 2] += x * v.z;
-          t[4 * q + 3] += x * v.w;
+          for (int q = 0; q < RTP / 4; ++q) {
+            const float4 v = v4[q];
+            t[4 * q + 0] += x * v.x;
+            t[4 * q + 1] += x * v.y;
+            t[4 * q + 2] += x * v.z;
+            t[4 * q + 3] += x * v.w;
+          }
         }
+        const float4 *c4 = reinterpret_cast<const float4 *>(C + (int64_t)i * kLMax);
+        const float4 ca = c4[0], cb = c4[1];
+        const float c[kLMax] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+#pragma unroll
+        for (int a = 0; a < kLMax; ++a)
+#pragma unroll
+          for (int r = 0; r < RT; ++r) acc[a][r] += c[a] * t[r];
       }
-      const float4 *c4 = reinterpret_cast<const float4 *>(C + (int64_t)i * kLMax);
-      float4 ca = c4[0], cb = c4[1];
-      float c[kLMax] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+      for (int m = 1; m < G; m <<= 1) {
 #pragma unroll
-      for (int a = 0; a < kLMax; ++a)
+        for (int a = 0; a < kLMax; ++a)
 #pragma unroll
-        for (int r = 0; r < RT; ++r) acc[a][r] += c[a] * t[r];
-    }
-    for (int m = 1; m < G; m <<= 1) {
+          for (int r = 0; r < RT; ++r) acc[a][r] += shfl_xor_f(acc[a][r], m);
+      }
+      if (active) {
+        float *dst = T + (int64_t)k * l * R + c0;
 #pragma unroll
-      for (int a = 0; a < kLMax; ++a)
+        for (int a = 0; a < kLMax; ++a)
 #pragma unroll
-        for (int r = 0; r < RT; ++r) acc[a][r] += shfl_xor_f(acc[a][r], m);
-    }
-    if (active) {
-      float *dst = T + (int64_t)k * l * R + c0;
+          for (int r = 0; r < RT; ++r)
+            if (a < l && c0 + r < R && ((a * RT + r) & (G - 1)) == sub) dst[a * R + r] = acc[a][r];
+      }
+    } else if (active) {
+      for (int i = r0 + sub; i < r1; i += G) {
+        float t[RTP];
 #pragma unroll
-      for (int a = 0; a < kLMax; ++a)
+        for (int r = 0; r < RTP; ++r) t[r] = 0.0f;
+        const int e1 = row[i + 1];
+        for (int e = row[i]; e < e1; ++e) {
+          const float x = val[e];
+          const float4 *v4 = reinterpret_cast<const float4 *>(sV + (int64_t)col[e] * RTP);
+#pragma unroll
+          for (int q = 0; q < RTP / 4; ++q) {
+            const float4 v = v4[q];
+            t[4 * q + 0] += x * v.x;
+            t[4 * q + 1] += x * v.y;
+            t[4 * q + 2] += x * v.z;
+            t[4 * q + 3] += x * v.w;
+          }
+        }
+        float *dst = T + (int64_t)i * R + c0;
 #pragma unroll
         for (int r = 0; r < RT; ++r)
-          if (a < l && c0 + r < R && ((a * RT + r) & (G - 1)) == sub) dst[a * R + r] = acc[a][r];
-    }
-  } else {
-    if (!active) return;
-    for (int i = r0 + sub; i < r1; i += G) {
-      float t[RTP];
-#pragma unroll
-      for (int r = 0; r < RTP; ++r) t[r] = 0.0f;
-      const int e1 = row[i + 1];
-      for (int e = row[i]; e < e1; ++e) {
-        const float x = val[e];
-        const float4 *v4 = reinterpret_cast<const float4 *>(sV + (int64_t)col[e] * RTP);
-#pragma unroll
-        for (int q = 0; q < RTP / 4; ++q) {
-          float4 v = v4[q];
-          t[4 * q + 0] += x * v.x;
-          t[4 * q + 1] += x * v.y;
-          t[4 * q + 2] += x * v.z;
-          t[4 * q + 3] += x * v.w;
-        }
+          if (c0 + r < R) dst[r] = t[r];
       }
-      float *dst = T + (int64_t)i * R + c0;
-#pragma unroll
-      for (int r = 0; r < RT; ++r)
-        if (c0 + r < R) dst[r] = t[r];
     }
   }
+}
+
+// V (J x R) -> padded column tiles Vp[tile][j][0..RTP) (padding stays zero)
+template <int R>
+__global__ void k_pad_V(const float *__restrict__ V, float *__restrict__ Vp, int64_t J, int rt,
+                        int rtp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= J * R) return;
+  const int64_t j = e / R;
+  const int c = (int)(e - j * R);
+  Vp[((int64_t)(c / rt) * J + j) * rtp + c % rt] = V[e];
 }
 
 // ======================================================================= Procrustes
@@ -349,61 +360,110 @@ __global__ void __launch_bounds__(64)
 }
 
 // ======================================================================= row Gram reductions
-// part[b] = sum over rows of block b of A_row^T (B_row * w_subj(row)) (FP64, R x R).
+// dst = sum over rows of A_row^T (B_row * w_subj(row)) (R x R, FP64), a dense contraction over
+// the long row dimension done on the matrix cores: v_mfma_f64_16x16x4f64 takes 4 rows per
+// instruction, lane l holding A[row0 + l/16][16 ti + l%16] and B[row0 + l/16][16 tj + l%16].
 // wsel: 0 = no scaling; 1 = scale B by W[row / slot_rows]; 2 = scale by W[rowsubj[row]].
+// Every block writes its partial; the last block to finish adds the partials in block order (the
+// result does not depend on scheduling) into dst and resets the counter.
+typedef double dbl4_t __attribute__((ext_vector_type(4)));
+
 template <int R>
 __global__ void __launch_bounds__(256)
     k_rows_gram(const float *__restrict__ A, const float *__restrict__ B, int64_t rows,
                 const float *__restrict__ W, int wsel, int slot_rows,
-                const int32_t *__restrict__ rowsubj, double *__restrict__ part) {
-  constexpr int CH = 64;
-  constexpr int E = (R * R + 255) / 256;
-  __shared__ float sA[CH * R];
-  __shared__ float sB[CH * R];
-  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+                const int32_t *__restrict__ rowsubj, double *__restrict__ part,
+                double *__restrict__ dst, int32_t *counter) {
+  constexpr int NT = (R + 15) / 16;
+  constexpr int RP = NT * 16;
+  constexpr int RR = R * R;
+  __shared__ double sacc[RP * RP];
+  __shared__ int last;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int m = lane & 15, kk = lane >> 4;
+  for (int e = t; e < RP * RP; e += blockDim.x) sacc[e] = 0.0;
+  const int64_t per = ((rows + gridDim.x - 1) / gridDim.x + 15) & ~(int64_t)15;
   const int64_t lo = blockIdx.x * per;
   const int64_t hi = lo + per < rows ? lo + per : rows;
-  double acc[E];
+  dbl4_t acc[NT][NT];
 #pragma unroll
-  for (int s = 0; s < E; ++s) acc[s] = 0.0;
-  for (int64_t c0 = lo; c0 < hi; c0 += CH) {
-    const int n = (int)((hi - c0) < CH ? (hi - c0) : CH);
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * R; e += blockDim.x) {
-      const int64_t rr = c0 + e / R;
-      const int c = e % R;
-      sA[e] = A[rr * R + c];
-      float bv = B[rr * R + c];
-      if (wsel == 1) bv *= W[(rr / slot_rows) * R + c];
-      else if (wsel == 2) bv *= W[(int64_t)rowsubj[rr] * R + c];
-      sB[e] = bv;
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int64_t r0 = lo + 4 * wave; r0 < hi; r0 += 16) {
+    const int64_t rr = r0 + kk;
+    const bool ok = rr < hi;
+    double av[NT], bv[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int c = q * 16 + m;
+      const bool in = ok && c < R;
+      av[q] = in ? (double)A[rr * R + c] : 0.0;
+      double b = in ? (double)B[rr * R + c] : 0.0;
+      if (in && wsel == 1) b *= (double)W[(rr / slot_rows) * R + c];
+      else if (in && wsel == 2) b *= (double)W[(int64_t)rowsubj[rr] * R + c];
+      bv[q] = b;
+    }
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+  }
+  __syncthreads();
+  // D[ii][jj] of a 16 x 16 FP64 block: lane jj + 16 (ii % 4), element ii / 4
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ii = i * 16 + 4 * v + (lane >> 4), jj = j * 16 + (lane & 15);
+            sacc[ii * RP + jj] += acc[i][j][v];
+          }
     }
     __syncthreads();
+  }
+  for (int e = t; e < RR; e += blockDim.x)
+    part[(int64_t)blockIdx.x * RR + e] = sacc[(e / R) * RP + e % R];
+  __threadfence();
+  __syncthreads();
+  if (t == 0) last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int nb = gridDim.x;
+  constexpr int G2 = RR >= 256 ? 1 : 256 / RR;
+  double *sred = sacc;  // reuse (RP*RP >= 256 doubles)
+  for (int e0 = 0; e0 < RR; e0 += 256 / G2) {
+    const int e = e0 + t % (256 / G2 < RR ? 256 / G2 : RR);
+    const int g = t / (256 / G2 < RR ? 256 / G2 : RR);
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (e < RR && g < G2) {
+      int b = g;
+      for (; b + 7 * G2 < nb; b += 8 * G2) {
 #pragma unroll
-    for (int s = 0; s < E; ++s) {
-      const int e = threadIdx.x + s * 256;
-      if (e < R * R) {
-        const int a = e / R, b = e % R;
-        double v = 0.0;
-        for (int rr = 0; rr < n; ++rr) v += (double)sA[rr * R + a] * (double)sB[rr * R + b];
-        acc[s] += v;
+        for (int u = 0; u < 8; ++u)
+          s[u] += __hip_atomic_load(&part[(int64_t)(b + u * G2) * RR + e], __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
       }
+      for (; b < nb; b += G2)
+        s[0] += __hip_atomic_load(&part[(int64_t)b * RR + e], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    sred[t] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    __syncthreads();
+    if (t < (256 / G2 < RR ? 256 / G2 : RR) && e0 + t < RR) {
+      double v = 0.0;
+      for (int q = 0; q < G2; ++q) v += sred[q * (256 / G2 < RR ? 256 / G2 : RR) + t];
+      dst[e0 + t] = v;
     }
   }
-#pragma unroll
-  for (int s = 0; s < E; ++s) {
-    const int e = threadIdx.x + s * 256;
-    if (e < R * R) part[(int64_t)blockIdx.x * R * R + e] = acc[s];
-  }
-}
-
-// dst = sum_b part[b] in fixed order
-__device__ void reduce_parts(const double *part, int nb, int RR, double *dst) {
-  for (int e = threadIdx.x; e < RR; e += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * RR + e];
-    dst[e] = s;
-  }
+  if (t == 0) *counter = 0;
 }
 
 // ======================================================================= ADMM helpers
@@ -499,13 +559,12 @@ __device__ __forceinline__ void admm_row(const double (&F)[R], float (&Zb)[R], f
 // ======================================================================= mode H (one block)
 template <int R>
 __global__ void __launch_bounds__(256)
-    k_mode_H(const double *__restrict__ part, int nb, double *small, ModeParams *modes,
-             FitScalars *sc, float *H, float *DH, int kind, double lam, int iters) {
+    k_mode_H(double *small, ModeParams *modes, FitScalars *sc, float *H, float *DH, int kind,
+             double lam, int iters) {
   __shared__ double sFH[R * R];
   __shared__ double sL[R * R];
-  reduce_parts(part, nb, R * R, sFH);
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sFH[e] = small[kFH * R * R + e];
   __syncthreads();
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) small[kFH * R * R + e] = sFH[e];
   mode_prepare<R>(small + kWtW * R * R, small + kVtV * R * R, &modes[0], sc);
   __syncthreads();
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = modes[0].L[e];
@@ -629,78 +688,172 @@ __global__ void __launch_bounds__(64)
 }
 
 // ======================================================================= streaming pass 2
-// F_V += x_ij * u_i with u_i = c_i M_k (smoothed) or the M row of visit i. LDS-private F_V tile
-// per block (flushed as a per-block partial), or global atomics when the tile does not fit.
-template <int RT, bool SMOOTH, bool LDSACC>
-__global__ void __launch_bounds__(1024)
+// F_V(j,:) += x_ij * u_i with u_i = c_i M_k (smoothed: basis row times Q_k H S_k) or the M row of
+// visit i (plain). Chunked form: for every block of kChunkRows visit rows the plan stores the
+// chunk's nonzeros sorted by feature (key = feature << 16 | row in chunk) and 9 split points
+// that cut the sorted list into 8 slices on feature boundaries, one per wave. A block puts the
+// chunk's u rows in LDS; each lane sums a contiguous run of its wave's slice feature by feature;
+// a segmented scan over the lanes joins runs that share a feature, so every feature is added to
+// the block's LDS copy of F_V by exactly one lane - no LDS atomics. The block's F_V tile goes to
+// the global F_V with one atomic add per entry at the end.
+template <int RT, bool SMOOTH>
+__global__ void __launch_bounds__(512)
+    k_pass2c(int nchunks, int64_t S, const int32_t *__restrict__ wsplit,
+             const uint32_t *__restrict__ pkey, const float *__restrict__ pval,
+             const int32_t *__restrict__ rowsubj, const float *__restrict__ C,
+             const float *__restrict__ M, int64_t J, int R, int l, float *__restrict__ FV) {
+  extern __shared__ float4 smem4[];
+  float *sF = reinterpret_cast<float *>(smem4);
+  float *sU = sF + J * RT;
+  const int c0 = blockIdx.y * RT;
+  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wave = t >> 6;
+  for (int64_t e = t; e < J * RT; e += nt) sF[e] = 0.0f;
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int64_t r0 = (int64_t)c * kChunkRows;
+    const int n = (int)((S - r0) < kChunkRows ? (S - r0) : kChunkRows);
+    __syncthreads();
+    for (int q = t; q < n; q += nt) {
+      const int64_t i = r0 + q;
+      float u[RT];
+      if constexpr (SMOOTH) {
+        const int64_t k = rowsubj[i];
+        const float4 *c4 = reinterpret_cast<const float4 *>(C + i * kLMax);
+        const float4 ca = c4[0], cb = c4[1];
+        const float cr[kLMax] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+#pragma unroll
+        for (int r = 0; r < RT; ++r) u[r] = 0.0f;
+#pragma unroll
+        for (int a = 0; a < kLMax; ++a) {
+          if (a < l) {
+            const float *mr = M + (k * l + a) * R + c0;
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+              if (c0 + r < R) u[r] += cr[a] * mr[r];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) u[r] = (c0 + r < R) ? M[i * R + c0 + r] : 0.0f;
+      }
+#pragma unroll
+      for (int r = 0; r < RT; ++r) sU[q * RT + r] = u[r];
+    }
+    __syncthreads();
+    const int s0 = wsplit[c * 9 + wave], s1 = wsplit[c * 9 + wave + 1];
+    const int per = (s1 - s0 + 63) >> 6;
+    const int a = s0 + lane * per;
+    const int b = a + per < s1 ? a + per : s1;
+    float acc[RT], head[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      acc[r] = 0.0f;
+      head[r] = 0.0f;
+    }
+    int cur = -1, hkey = -1, nseg = 0;
+    for (int e = a; e < b; ++e) {
+      const uint32_t key = pkey[e];
+      const int j = (int)(key >> 16);
+      const float x = pval[e];
+      const float *ur = sU + (key & 0xffffu) * RT;
+      if (j != cur) {
+        if (nseg == 1) {
+          hkey = cur;
+#pragma unroll
+          for (int r = 0; r < RT; ++r) head[r] = acc[r];
+        } else if (nseg > 1) {
+          // a segment that starts and ends inside this lane's run: no other lane has it
+#pragma unroll
+          for (int r = 0; r < RT; ++r) sF[cur * RT + r] += acc[r];
+        }
+        cur = j;
+        ++nseg;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
+      }
+#pragma unroll
+      for (int r = 0; r < RT; ++r) acc[r] += x * ur[r];
+    }
+    // tail segment (cur, acc); the first key of this lane's run is hkey (several segments) or cur
+    const int first = nseg > 1 ? hkey : cur;
+    // inclusive segmented scan of the tails over lanes (keys are non-decreasing along lanes)
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int kprev = __shfl_up(cur, d, 64);
+      float vprev[RT];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) vprev[r] = __shfl_up(acc[r], d, 64);
+      if (lane >= d && cur >= 0 && kprev == cur) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[r] += vprev[r];
+      }
+    }
+    const int knext = __shfl_down(first, 1, 64);
+    const int kprev1 = __shfl_up(cur, 1, 64);
+    float carry[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) carry[r] = __shfl_up(acc[r], 1, 64);
+    if (nseg > 1) {
+      // head segment: complete once the previous lane's tail (if same feature) is added
+      const bool join = lane > 0 && kprev1 == hkey;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) sF[hkey * RT + r] += head[r] + (join ? carry[r] : 0.0f);
+    }
+    if (cur >= 0) {
+      // tail: flushed unless the next lane's run starts with the same feature
+      const bool cont = lane < 63 && knext == cur;
+      if (!cont) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) sF[cur * RT + r] += acc[r];
+      }
+    }
+  }
+  __syncthreads();
+  for (int64_t e = t; e < J * RT; e += nt) {
+    const int64_t j = e / RT;
+    const int r = (int)(e - j * RT);
+    const float v = sF[e];
+    if (c0 + r < R && v != 0.0f) unsafeAtomicAdd(&FV[j * R + c0 + r], v);
+  }
+}
+
+// Unchunked fallback (features >= 2^16): global atomics per nonzero.
+template <int RT, bool SMOOTH>
+__global__ void __launch_bounds__(256)
     k_pass2(const WaveEntry *__restrict__ waves, int n_waves, const int32_t *__restrict__ order,
             const int32_t *__restrict__ subj, const int32_t *__restrict__ row,
             const int32_t *__restrict__ col, const float *__restrict__ val,
             const float *__restrict__ C, const float *__restrict__ M, int64_t J, int R, int l,
-            float *__restrict__ FVpart, float *__restrict__ FV) {
-  extern __shared__ float4 smem4[];
-  float *sF = reinterpret_cast<float *>(smem4);
-  const int c0 = blockIdx.y * RT;
-  if constexpr (LDSACC) {
-    for (int64_t e = threadIdx.x; e < J * RT; e += blockDim.x) sF[e] = 0.0f;
-    __syncthreads();
-  }
+            float *__restrict__ FV) {
   const int lane = threadIdx.x & 63;
-  const int nwb = blockDim.x >> 6;
-  for (int wv = blockIdx.x * nwb + (threadIdx.x >> 6); wv < n_waves; wv += gridDim.x * nwb) {
-    const WaveEntry we = waves[wv];
-    const int lg = we.lg_count & 255, cnt = we.lg_count >> 8;
-    const int G = 1 << lg, sidx = lane >> lg, sub = lane & (G - 1);
-    if (sidx >= cnt) continue;
-    const int k = order[we.first + sidx];
-    const int r0 = subj[k], r1 = subj[k + 1];
-    float mk[SMOOTH ? kLMax : 1][RT];
+  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wv >= n_waves) return;
+  const int c0 = blockIdx.y * RT;
+  const WaveEntry we = waves[wv];
+  const int lg = we.lg_count & 255, cnt = we.lg_count >> 8;
+  const int G = 1 << lg, sidx = lane >> lg, sub = lane & (G - 1);
+  if (sidx >= cnt) return;
+  const int k = order[we.first + sidx];
+  const int r0 = subj[k], r1 = subj[k + 1];
+  for (int i = r0 + sub; i < r1; i += G) {
+    float u[RT];
     if constexpr (SMOOTH) {
 #pragma unroll
-      for (int a = 0; a < kLMax; ++a)
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-          mk[a][r] = (a < l && c0 + r < R) ? M[((int64_t)k * l + a) * R + c0 + r] : 0.0f;
-    }
-    for (int i = r0 + sub; i < r1; i += G) {
-      float u[RT];
-      if constexpr (SMOOTH) {
-        const float4 *c4 = reinterpret_cast<const float4 *>(C + (int64_t)i * kLMax);
-        float4 ca = c4[0], cb = c4[1];
-        float c[kLMax] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
-#pragma unroll
-        for (int r = 0; r < RT; ++r) {
-          float s = 0.0f;
-#pragma unroll
-          for (int a = 0; a < kLMax; ++a) s += c[a] * mk[a][r];
-          u[r] = s;
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < RT; ++r) u[r] = (c0 + r < R) ? M[(int64_t)i * R + c0 + r] : 0.0f;
+      for (int r = 0; r < RT; ++r) {
+        float s = 0.0f;
+        for (int a = 0; a < l; ++a)
+          if (c0 + r < R) s += C[(int64_t)i * kLMax + a] * M[((int64_t)k * l + a) * R + c0 + r];
+        u[r] = s;
       }
-      const int e1 = row[i + 1];
-      for (int e = row[i]; e < e1; ++e) {
-        const float x = val[e];
-        const int64_t j = col[e];
-        if constexpr (LDSACC) {
+    } else {
 #pragma unroll
-          for (int r = 0; r < RT; ++r) atomicAdd(&sF[j * RT + r], x * u[r]);
-        } else {
-#pragma unroll
-          for (int r = 0; r < RT; ++r)
-            if (c0 + r < R) atomicAdd(&FV[j * R + c0 + r], x * u[r]);
-        }
-      }
+      for (int r = 0; r < RT; ++r) u[r] = (c0 + r < R) ? M[(int64_t)i * R + c0 + r] : 0.0f;
     }
-  }
-  if constexpr (LDSACC) {
-    __syncthreads();
-    float *dst = FVpart + (int64_t)blockIdx.x * J * R;
-    for (int64_t e = threadIdx.x; e < J * RT; e += blockDim.x) {
-      const int64_t j = e / RT;
-      const int r = (int)(e - j * RT);
-      if (c0 + r < R) dst[j * R + c0 + r] = sF[e];
+    for (int e = row[i]; e < row[i + 1]; ++e) {
+      const float x = val[e];
+      const int64_t j = col[e];
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        if (c0 + r < R) unsafeAtomicAdd(&FV[j * R + c0 + r], x * u[r]);
     }
   }
 }
@@ -708,20 +861,16 @@ __global__ void __launch_bounds__(1024)
 // ======================================================================= mode V
 template <int R>
 __global__ void __launch_bounds__(256)
-    k_mode_V_prep(const double *__restrict__ partW, const double *__restrict__ partPsi, int nb,
-                  double *small, ModeParams *modes, FitScalars *sc) {
-  reduce_parts(partW, nb, R * R, small + kWtW * R * R);
-  reduce_parts(partPsi, nb, R * R, small + kPsi * R * R);
-  __threadfence_block();
-  __syncthreads();
+    k_mode_V_prep(double *small, ModeParams *modes, FitScalars *sc) {
   mode_prepare<R>(small + kHtH * R * R, small + kWtW * R * R, &modes[2], sc);
 }
 
 template <int R>
 __global__ void __launch_bounds__(256)
-    k_v_admm(int64_t J, const float *__restrict__ FVpart, int nparts, float *__restrict__ FV,
-             float *__restrict__ V, float *__restrict__ DV, const ModeParams *__restrict__ modes,
-             int kind, double lam, int iters, double *__restrict__ vpart) {
+    k_v_admm(int64_t J, const float *__restrict__ FV, float *__restrict__ V,
+             float *__restrict__ DV, float *__restrict__ Vp, int rt, int rtp,
+             const ModeParams *__restrict__ modes, int kind, double lam, int iters,
+             double *__restrict__ vpart) {
   __shared__ double sL[R * R];
   __shared__ double sred[3][256];
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = modes[2].L[e];
@@ -731,20 +880,8 @@ __global__ void __launch_bounds__(256)
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < J;
        j += (int64_t)gridDim.x * blockDim.x) {
     double F[R];
-    if (FVpart) {
 #pragma unroll
-      for (int c = 0; c < R; ++c) F[c] = 0.0;
-      for (int b = 0; b < nparts; ++b) {
-        const float *src = FVpart + ((int64_t)b * J + j) * R;
-#pragma unroll
-        for (int c = 0; c < R; ++c) F[c] += (double)src[c];
-      }
-#pragma unroll
-      for (int c = 0; c < R; ++c) FV[j * R + c] = (float)F[c];
-    } else {
-#pragma unroll
-      for (int c = 0; c < R; ++c) F[c] = FV[j * R + c];
-    }
+    for (int c = 0; c < R; ++c) F[c] = FV[j * R + c];
     float Zb[R], D[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
@@ -756,6 +893,7 @@ __global__ void __launch_bounds__(256)
     for (int c = 0; c < R; ++c) {
       V[j * R + c] = Zb[c];
       DV[j * R + c] = D[c];
+      Vp[((int64_t)(c / rt) * J + j) * rtp + c % rt] = Zb[c];
       dot += F[c] * (double)Zb[c];
       l1 += fabs((double)Zb[c]);
       zeros += Zb[c] == 0.0f ? 1.0 : 0.0;
@@ -775,24 +913,40 @@ __global__ void __launch_bounds__(256)
 // ======================================================================= finalize
 template <int R>
 __global__ void __launch_bounds__(256)
-    k_finalize(const double *__restrict__ partV, int nb, const double *__restrict__ vpart,
-               int nvb, const double *__restrict__ wl1part, int nwb, double *small,
-               FitScalars *sc, const float *__restrict__ H, double normX2, int64_t J,
-               int proxH, double lamH, int proxW, double lamW, int proxV, double lamV) {
-  reduce_parts(partV, nb, R * R, small + kVtV * R * R);
-  __threadfence_block();
+    k_finalize(const double *__restrict__ vpart, int nvb, const double *__restrict__ wl1part,
+               int nwb, double *small, FitScalars *sc, const float *__restrict__ H, double normX2,
+               int64_t J, int proxH, double lamH, int proxW, double lamW, int proxV,
+               double lamV) {
+  __shared__ double red[5][256];
+  const int t = threadIdx.x;
+  double dot = 0.0, l1 = 0.0, zeros = 0.0, wl1 = 0.0, quad = 0.0;
+  for (int b = t; b < nvb; b += blockDim.x) {
+    dot += vpart[b * 4 + 0];
+    l1 += vpart[b * 4 + 1];
+    zeros += vpart[b * 4 + 2];
+  }
+  for (int b = t; b < nwb; b += blockDim.x) wl1 += wl1part[b];
+  for (int e = t; e < R * R; e += blockDim.x)
+    quad += small[kPsi * R * R + e] * small[kVtV * R * R + e];
+  red[0][t] = dot;
+  red[1][t] = l1;
+  red[2][t] = zeros;
+  red[3][t] = wl1;
+  red[4][t] = quad;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double dot = 0.0, l1 = 0.0, zeros = 0.0, wl1 = 0.0, hl1 = 0.0;
-    for (int b = 0; b < nvb; ++b) {
-      dot += vpart[b * 4 + 0];
-      l1 += vpart[b * 4 + 1];
-      zeros += vpart[b * 4 + 2];
-    }
-    for (int b = 0; b < nwb; ++b) wl1 += wl1part[b];
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int q = 0; q < 5; ++q) red[q][t] += red[q][t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    dot = red[0][0];
+    l1 = red[1][0];
+    zeros = red[2][0];
+    wl1 = red[3][0];
+    quad = red[4][0];
+    double hl1 = 0.0;
     for (int e = 0; e < R * R; ++e) hl1 += fabs((double)H[e]);
-    double quad = 0.0;
-    for (int e = 0; e < R * R; ++e) quad += small[kPsi * R * R + e] * small[kVtV * R * R + e];
     const double resid = normX2 - 2.0 * dot + quad;
     const double fit = normX2 > 0.0 ? 1.0 - resid / normX2 : 0.0;
     auto pen = [](int kind, double lam, double a) {
@@ -830,11 +984,6 @@ __global__ void k_reset_scalars(FitScalars *sc) {
   }
 }
 
-template <int R>
-__global__ void __launch_bounds__(256) k_reduce_into(const double *part, int nb, double *dst) {
-  reduce_parts(part, nb, R * R, dst);
-}
-
 // Qtilde rows: c_i Q_k (smoothed) or the Q row itself
 template <int R>
 __global__ void __launch_bounds__(256)
@@ -863,40 +1012,46 @@ __global__ void __launch_bounds__(256)
 
 // ======================================================================= host launchers
 template <int RT>
-static void launch_pass1_rt(copa_plan *p, const float *V, hipStream_t s) {
+static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
   constexpr int RTP = (RT + 3) & ~3;
-  dim3 grid((unsigned)((p->n_waves + 3) / 4), (unsigned)p->tiles.nt), block(256);
   size_t lds = (size_t)p->J * RTP * sizeof(float);
+  const int per_cu = std::max(1, std::min(4, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
+  const int nb = std::max(1, std::min((p->n_waves + 3) / 4, p->n_cu * per_cu));
+  dim3 grid((unsigned)nb, (unsigned)p->tiles.nt), block(256);
   if (p->l > 0)
     k_pass1<RT, true><<<grid, block, lds, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
-                                              p->col, p->val, p->C, V, p->J, p->R, p->l, p->T);
+                                              p->col, p->val, p->C, p->Vp, p->J, p->R, p->l,
+                                              p->T);
   else
     k_pass1<RT, false><<<grid, block, lds, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
-                                               p->col, p->val, p->C, V, p->J, p->R, p->l, p->T);
+                                               p->col, p->val, p->C, p->Vp, p->J, p->R, p->l,
+                                               p->T);
 }
 
 template <int RT>
 static void launch_pass2_rt(copa_plan *p, hipStream_t s) {
-  dim3 grid((unsigned)p->n_fv_blocks, (unsigned)p->tiles.nt), block(1024);
-  if (p->fv_lds) {
-    size_t lds = (size_t)p->J * RT * sizeof(float);
+  if (p->p2c) {
+    dim3 grid((unsigned)std::min(p->nchunks, std::max(1, p->n_cu)), (unsigned)p->tiles.nt),
+        block(512);
+    size_t lds = ((size_t)p->J * RT + (size_t)kChunkRows * RT) * sizeof(float);
     if (p->l > 0)
-      k_pass2<RT, true, true><<<grid, block, lds, s>>>(p->waves, p->n_waves, p->order, p->subj,
-                                                       p->row, p->col, p->val, p->C, p->M, p->J,
-                                                       p->R, p->l, p->FVpart, p->FV);
+      k_pass2c<RT, true><<<grid, block, lds, s>>>(p->nchunks, p->S, p->wsplit, p->pkey, p->pval,
+                                                  p->rowsubj, p->C, p->M, p->J, p->R, p->l,
+                                                  p->FV);
     else
-      k_pass2<RT, false, true><<<grid, block, lds, s>>>(p->waves, p->n_waves, p->order, p->subj,
-                                                        p->row, p->col, p->val, p->C, p->M,
-                                                        p->J, p->R, p->l, p->FVpart, p->FV);
+      k_pass2c<RT, false><<<grid, block, lds, s>>>(p->nchunks, p->S, p->wsplit, p->pkey, p->pval,
+                                                   p->rowsubj, p->C, p->M, p->J, p->R, p->l,
+                                                   p->FV);
   } else {
+    dim3 grid((unsigned)((p->n_waves + 3) / 4), (unsigned)p->tiles.nt), block(256);
     if (p->l > 0)
-      k_pass2<RT, true, false><<<grid, block, 0, s>>>(p->waves, p->n_waves, p->order, p->subj,
-                                                      p->row, p->col, p->val, p->C, p->M, p->J,
-                                                      p->R, p->l, p->FVpart, p->FV);
+      k_pass2<RT, true><<<grid, block, 0, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
+                                              p->col, p->val, p->C, p->M, p->J, p->R, p->l,
+                                              p->FV);
     else
-      k_pass2<RT, false, false><<<grid, block, 0, s>>>(p->waves, p->n_waves, p->order, p->subj,
-                                                       p->row, p->col, p->val, p->C, p->M, p->J,
-                                                       p->R, p->l, p->FVpart, p->FV);
+      k_pass2<RT, false><<<grid, block, 0, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
+                                               p->col, p->val, p->C, p->M, p->J, p->R, p->l,
+                                               p->FV);
   }
 }
 
@@ -915,50 +1070,108 @@ static void launch_pass2_rt(copa_plan *p, hipStream_t s) {
 
 template <int R>
 static void gram(copa_plan *p, const float *A, const float *B, int64_t rows, const float *W,
-                 int wsel, double *part, hipStream_t s) {
-  k_rows_gram<R><<<kGramBlocks, 256, 0, s>>>(A, B, rows, W, wsel, p->slot_rows > 0 ? p->slot_rows : 1,
-                                             p->rowsubj, part);
+                 int wsel, int slot, double *dst, hipStream_t s) {
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGramBlocks, (rows + 1023) / 1024));
+  k_rows_gram<R><<<nb, 256, 0, s>>>(A, B, rows, W, wsel,
+                                             p->slot_rows > 0 ? p->slot_rows : 1, p->rowsubj,
+                                             p->gpart, dst, p->gcount + slot);
+}
+
+const char *const kernel_names[kNumKernels] = {
+    "pass1", "procrustes", "gram_FH", "mode_H", "w_admm", "gram_W", "gram_M", "zero_FV",
+    "pass2", "mode_V_prep", "v_admm", "gram_V", "finalize"};
+
+enum { kidPass1, kidProcrustes, kidGramFH, kidModeH, kidWadmm, kidGramW, kidGramM, kidZeroFV,
+       kidPass2, kidModeVPrep, kidVadmm, kidGramV, kidFinalize };
+
+// Records a HIP event pair around one launch when the plan's timing is on.
+template <typename F>
+static inline void timed(copa_plan *p, hipStream_t s, int kid, F &&launch) {
+  if (p->timing && p->ev_used + 2 <= (int)p->ev_pool.size()) {
+    (void)hipEventRecord(p->ev_pool[p->ev_used], s);
+    launch();
+    (void)hipEventRecord(p->ev_pool[p->ev_used + 1], s);
+    p->ev_kid.push_back(kid);
+    p->ev_used += 2;
+  } else {
+    launch();
+  }
+}
+
+copa_status harvest_timing(copa_plan *p) {
+  for (size_t e = 0; e < p->ev_kid.size(); ++e) {
+    float ms = 0.0f;
+    COPA_HIP(hipEventElapsedTime(&ms, p->ev_pool[2 * e], p->ev_pool[2 * e + 1]));
+    p->t_ms[p->ev_kid[e]] += ms;
+    p->t_cnt[p->ev_kid[e]] += 1;
+  }
+  p->ev_kid.clear();
+  p->ev_used = 0;
+  return COPA_OK;
 }
 
 template <int R>
 static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   const copa_options &o = p->opt;
   const int64_t K = p->K;
-  RT_SWITCH(p->tiles.rt, launch_pass1_rt, p, st->V, s);
+  timed(p, s, kidPass1, [&] { RT_SWITCH(p->tiles.rt, launch_pass1_rt, p, st->V, s); });
   if (K > 0)
-    k_procrustes<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-        K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W, o.rank_rtol, &p->scal->rank_def_cur);
-  gram<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, p->gpart, s);
-  k_mode_H<R><<<1, 256, 0, s>>>(p->gpart, kGramBlocks, p->small, p->modes, p->scal, st->H,
-                                st->D_H, o.prox_H, o.lambda_H, o.inner_iters);
+    timed(p, s, kidProcrustes, [&] {
+      k_procrustes<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
+          K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W, o.rank_rtol,
+          &p->scal->rank_def_cur);
+    });
+  timed(p, s, kidGramFH,
+        [&] {
+          gram<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, 0,
+                  p->small + kFH * R * R, s);
+        });
+  timed(p, s, kidModeH, [&] {
+    k_mode_H<R><<<1, 256, 0, s>>>(p->small, p->modes, p->scal, st->H, st->D_H, o.prox_H,
+                                  o.lambda_H, o.inner_iters);
+  });
   const unsigned nwb = (unsigned)std::max<int64_t>(1, (K + 63) / 64);
-  k_w_admm<R><<<nwb, 64, 0, s>>>(K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W,
-                                 st->D_W, p->FW, p->modes, o.prox_W, o.lambda_W, o.inner_iters,
-                                 p->wpart);
-  gram<R>(p, st->W, st->W, K, nullptr, 0, p->gpart, s);
-  gram<R>(p, p->M, p->M, p->rows_total, nullptr, 0, p->gpart2, s);
-  if (!p->fv_lds)
-    k_zero<<<(unsigned)std::min<int64_t>(1024, (p->J * R + 255) / 256), 256, 0, s>>>(p->FV, p->J * R);
-  RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s);
-  k_mode_V_prep<R><<<1, 256, 0, s>>>(p->gpart, p->gpart2, kGramBlocks, p->small, p->modes,
-                                     p->scal);
-  k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(p->J, p->fv_lds ? p->FVpart : nullptr,
-                                           p->n_fv_blocks, p->FV, st->V, st->D_V, p->modes,
-                                           o.prox_V, o.lambda_V, o.inner_iters, p->vpart);
-  gram<R>(p, st->V, st->V, p->J, nullptr, 0, p->gpart, s);
-  k_finalize<R><<<1, 256, 0, s>>>(p->gpart, kGramBlocks, p->vpart, p->n_vblocks,
-                                  p->wpart, (int)nwb, p->small, p->scal,
-                                  st->H, p->normX2, p->J, o.prox_H, o.lambda_H, o.prox_W,
-                                  o.lambda_W, o.prox_V, o.lambda_V);
+  timed(p, s, kidWadmm, [&] {
+    k_w_admm<R><<<nwb, 64, 0, s>>>(K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W,
+                                   st->D_W, p->FW, p->modes, o.prox_W, o.lambda_W,
+                                   o.inner_iters, p->wpart);
+  });
+  timed(p, s, kidGramW,
+        [&] { gram<R>(p, st->W, st->W, K, nullptr, 0, 1, p->small + kWtW * R * R, s); });
+  timed(p, s, kidGramM, [&] {
+    gram<R>(p, p->M, p->M, p->rows_total, nullptr, 0, 2, p->small + kPsi * R * R, s);
+  });
+  timed(p, s, kidZeroFV, [&] {
+      k_zero<<<(unsigned)std::min<int64_t>(1024, (p->J * R + 255) / 256), 256, 0, s>>>(
+          p->FV, p->J * R);
+    });
+  timed(p, s, kidPass2, [&] { RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s); });
+  timed(p, s, kidModeVPrep, [&] {
+    k_mode_V_prep<R><<<1, 256, 0, s>>>(p->small, p->modes, p->scal);
+  });
+  timed(p, s, kidVadmm, [&] {
+    k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt,
+                                             (p->tiles.rt + 3) & ~3, p->modes, o.prox_V,
+                                             o.lambda_V, o.inner_iters, p->vpart);
+  });
+  timed(p, s, kidGramV,
+        [&] { gram<R>(p, st->V, st->V, p->J, nullptr, 0, 3, p->small + kVtV * R * R, s); });
+  timed(p, s, kidFinalize, [&] {
+    k_finalize<R><<<1, 256, 0, s>>>(p->vpart, p->n_vblocks, p->wpart, (int)nwb, p->small,
+                                   p->scal, st->H, p->normX2, p->J,
+                                    o.prox_H, o.lambda_H, o.prox_W, o.lambda_W, o.prox_V,
+                                    o.lambda_V);
+  });
 }
 
 template <int R>
 static void init_grams_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   k_reset_scalars<<<1, 64, 0, s>>>(p->scal);
-  gram<R>(p, st->W, st->W, p->K, nullptr, 0, p->gpart, s);
-  k_reduce_into<R><<<1, 256, 0, s>>>(p->gpart, kGramBlocks, p->small + kWtW * R * R);
-  gram<R>(p, st->V, st->V, p->J, nullptr, 0, p->gpart2, s);
-  k_reduce_into<R><<<1, 256, 0, s>>>(p->gpart2, kGramBlocks, p->small + kVtV * R * R);
+  if (p->J > 0)
+    k_pad_V<R><<<(unsigned)((p->J * R + 255) / 256), 256, 0, s>>>(
+        st->V, p->Vp, p->J, p->tiles.rt, (p->tiles.rt + 3) & ~3);
+  gram<R>(p, st->W, st->W, p->K, nullptr, 0, 4, p->small + kWtW * R * R, s);
+  gram<R>(p, st->V, st->V, p->J, nullptr, 0, 5, p->small + kVtV * R * R, s);
 }
 
 copa_status launch_iteration(copa_plan *p, const copa_state *st, hipStream_t s) {
@@ -1023,7 +1236,7 @@ copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Q
   FitScalars hs;
   int done = 0, chunk_start = 0, fail = -1;
   while (done < iters) {
-    const int chunk = std::min(iters - done, kHistCap);
+    const int chunk = std::min(iters - done, p->timing ? kTimingChunk : kHistCap);
     if (done > 0) k_reset_scalars<<<1, 64, 0, s>>>(p->scal);
     for (int t = 0; t < chunk; ++t) {
       cs = launch_iteration(p, st, s);
@@ -1031,6 +1244,10 @@ copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Q
     }
     COPA_HIP(hipMemcpyAsync(&hs, p->scal, sizeof(FitScalars), hipMemcpyDeviceToHost, s));
     COPA_HIP(hipStreamSynchronize(s));
+    if (p->timing) {
+      cs = harvest_timing(p);
+      if (cs != COPA_OK) return cs;
+    }
     hf.insert(hf.end(), hs.hist_fit, hs.hist_fit + chunk);
     ho.insert(ho.end(), hs.hist_obj, hs.hist_obj + chunk);
     chunk_start = done;
@@ -1065,6 +1282,38 @@ copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Q
     return COPA_ENUMERIC;
   }
   return COPA_OK;
+}
+
+copa_status copa_set_timing(copa_plan *p, int32_t enable) {
+  if (!p) {
+    set_error("plan is NULL");
+    return COPA_EINVAL;
+  }
+  COPA_HIP(hipSetDevice(p->device));
+  if (enable && p->ev_pool.empty()) {
+    p->ev_pool.resize((size_t)kTimingChunk * kNumKernels * 2);
+    for (auto &e : p->ev_pool) COPA_HIP(hipEventCreate(&e));
+  }
+  p->timing = enable != 0;
+  return COPA_OK;
+}
+
+copa_status copa_read_timing(copa_plan *p, double *ms, int64_t *launches) {
+  if (!p) {
+    set_error("plan is NULL");
+    return COPA_EINVAL;
+  }
+  for (int k = 0; k < kNumKernels; ++k) {
+    if (ms) ms[k] = p->t_ms[k];
+    if (launches) launches[k] = p->t_cnt[k];
+    p->t_ms[k] = 0.0;
+    p->t_cnt[k] = 0;
+  }
+  return COPA_OK;
+}
+
+const char *copa_kernel_name(int32_t id) {
+  return (id >= 0 && id < kNumKernels) ? kernel_names[id] : "unknown";
 }
 
 copa_status copa_mttkrp_last(copa_plan *p, float *F_H, float *F_W, float *F_V, void *stream) {

@@ -4,6 +4,7 @@
 #include <climits>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "copa_common.h"
 
@@ -275,6 +276,12 @@ static copa_status launch_basis(int l, const int32_t *subj, const double *days, 
   return COPA_OK;
 }
 
+#define COPA_TRY(x)                   \
+  do {                                \
+    copa_status st_ = (x);            \
+    if (st_ != COPA_OK) return st_;   \
+  } while (0)
+
 template <typename T>
 static copa_status dalloc(T **ptr, size_t count) {
   if (count == 0) count = 1;
@@ -288,11 +295,73 @@ static copa_status dalloc(T **ptr, size_t count) {
   return COPA_OK;
 }
 
-#define COPA_TRY(x)                   \
-  do {                                \
-    copa_status st_ = (x);            \
-    if (st_ != COPA_OK) return st_;   \
-  } while (0)
+// Host-side build of the pass-2 layout: for every chunk of kChunkRows visit rows, the chunk's
+// nonzeros ordered by (feature, row), keyed as feature << 16 | row within the chunk.
+static copa_status build_sorted_chunks(const copa_tensor *X, copa_plan *p, hipStream_t s) {
+  const int64_t S = p->S, nnz = p->nnz;
+  std::vector<int64_t> rp(S + 1);
+  std::vector<int32_t> cl(nnz);
+  std::vector<float> vl(nnz);
+  COPA_HIP(hipMemcpyAsync(rp.data(), X->row_ptr, (S + 1) * sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipMemcpyAsync(cl.data(), X->col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipMemcpyAsync(vl.data(), X->val, nnz * sizeof(float), hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipStreamSynchronize(s));
+  const int nch = (int)((S + kChunkRows - 1) / kChunkRows);
+  std::vector<int32_t> cp(nch + 1);
+  for (int c = 0; c <= nch; ++c) cp[c] = (int32_t)rp[std::min<int64_t>((int64_t)c * kChunkRows, S)];
+  std::vector<uint32_t> key(nnz);
+  std::vector<float> sv(nnz);
+  const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (unsigned w = 0; w < nthreads; ++w) {
+    pool.emplace_back([&, w]() {
+      std::vector<uint64_t> tmp;
+      for (int c = (int)w; c < nch; c += (int)nthreads) {
+        const int64_t r0 = (int64_t)c * kChunkRows, r1 = std::min<int64_t>(r0 + kChunkRows, S);
+        const int64_t e0 = rp[r0];
+        tmp.clear();
+        for (int64_t i = r0; i < r1; ++i)
+          for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const uint64_t k = ((uint64_t)cl[e] << 16) | (uint64_t)(i - r0);
+            tmp.push_back((k << 32) | (uint64_t)(e - e0));
+          }
+        std::sort(tmp.begin(), tmp.end());
+        for (size_t q = 0; q < tmp.size(); ++q) {
+          key[e0 + q] = (uint32_t)(tmp[q] >> 32);
+          sv[e0 + q] = vl[e0 + (int64_t)(tmp[q] & 0xffffffffu)];
+        }
+      }
+    });
+  }
+  for (auto &t : pool) t.join();
+  // 8 wave slices per chunk, cut on feature boundaries near equal shares
+  std::vector<int32_t> ws((size_t)nch * 9);
+  for (int c = 0; c < nch; ++c) {
+    const int32_t e0 = cp[c], e1 = cp[c + 1];
+    ws[c * 9] = e0;
+    int32_t pos = e0;
+    for (int w = 1; w < 8; ++w) {
+      int32_t target = e0 + (int32_t)(((int64_t)(e1 - e0) * w) / 8);
+      if (target < pos) target = pos;
+      while (target > e0 && target < e1 && (key[target] >> 16) == (key[target - 1] >> 16)) ++target;
+      pos = target;
+      ws[c * 9 + w] = pos;
+    }
+    ws[c * 9 + 8] = e1;
+  }
+  p->nchunks = nch;
+  COPA_TRY(dalloc(&p->wsplit, (size_t)nch * 9));
+  COPA_HIP(hipMemcpyAsync(p->wsplit, ws.data(), ws.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  COPA_TRY(dalloc(&p->cptr, nch + 1));
+  COPA_TRY(dalloc(&p->pkey, nnz));
+  COPA_TRY(dalloc(&p->pval, nnz));
+  COPA_HIP(hipMemcpyAsync(p->cptr, cp.data(), (nch + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  COPA_HIP(hipMemcpyAsync(p->pkey, key.data(), nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  COPA_HIP(hipMemcpyAsync(p->pval, sv.data(), nnz * sizeof(float), hipMemcpyHostToDevice, s));
+  COPA_HIP(hipStreamSynchronize(s));
+  return COPA_OK;
+}
 
 static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hipStream_t s,
                               copa_plan *p) {
@@ -438,11 +507,20 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   COPA_TRY(dalloc(&p->M, p->rows_total * R));
   COPA_TRY(dalloc(&p->FW, K * R));
   COPA_TRY(dalloc(&p->FV, p->J * R));
-  p->fv_lds = (int64_t)p->J * p->tiles.rt * 4 <= p->lds_limit;
-  p->n_fv_blocks = 256;
-  if (p->fv_lds) COPA_TRY(dalloc(&p->FVpart, (size_t)p->n_fv_blocks * p->J * R));
+  {
+    const int rtp = (p->tiles.rt + 3) & ~3;
+    COPA_TRY(dalloc(&p->Vp, (size_t)p->tiles.nt * p->J * rtp));
+    COPA_HIP(hipMemsetAsync(p->Vp, 0, (size_t)p->tiles.nt * p->J * rtp * sizeof(float), s));
+  }
   COPA_TRY(dalloc(&p->gpart, (size_t)kGramBlocks * R * R));
-  COPA_TRY(dalloc(&p->gpart2, (size_t)kGramBlocks * R * R));
+  COPA_TRY(dalloc(&p->gcount, 8));
+  COPA_HIP(hipMemsetAsync(p->gcount, 0, 8 * sizeof(int32_t), s));
+  COPA_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
+  // ---- feature-sorted chunks for pass 2 (features < 2^16 and the F_V tile plus one chunk of
+  // u rows fit in LDS)
+  p->p2c = p->J <= 65536 && nnz > 0 &&
+           ((int64_t)p->J * p->tiles.rt + (int64_t)kChunkRows * p->tiles.rt) * 4 <= p->lds_limit;
+  if (p->p2c) COPA_TRY(build_sorted_chunks(X, p, s));
   p->n_vblocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (p->J + 255) / 256));
   COPA_TRY(dalloc(&p->vpart, (size_t)p->n_vblocks * 4));
   COPA_TRY(dalloc(&p->wpart, (size_t)std::max<int64_t>(1, (K + 63) / 64)));
@@ -465,8 +543,10 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
 using namespace copa;
 
 static void free_plan(copa_plan *p) {
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->C, p->rk, p->order, p->waves,
-                  p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->FVpart, p->gpart, p->gpart2,
+                  p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->cptr, p->wsplit, p->pkey, p->pval, p->Vp,
+                  p->gpart, p->gcount,
                   p->vpart, p->wpart, p->small, p->modes, p->scal, p->dloss, p->gradbuf};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
