@@ -119,8 +119,8 @@ typedef struct copa_plan copa_plan;
 
 /* Validates the tensor (shapes on the host, CSR content on the device), packs it into the
  * plan's device memory, builds the per-subject smoothing bases (l > 0) and allocates every
- * buffer the fit needs. Allocates device memory (hipMalloc) and synchronises `stream`; nothing
- * is allocated by later calls. Returns COPA_EINVAL for bad shapes or content,
+ * buffer the fit needs. Allocates device memory (hipMalloc) and synchronises `stream`; copa_fit
+ * allocates nothing (copa_loss_grad allocates its own buffers once, see below). Returns COPA_EINVAL for bad shapes or content,
  * COPA_EUNSUPPORTED for R or l outside this build, COPA_ENOMEM when memory runs out.       */
 copa_status copa_plan_create(const copa_tensor *X, const copa_options *opt, void *stream,
                              copa_plan **out);
@@ -146,7 +146,8 @@ copa_status copa_plan_basis(copa_plan *plan, float *C, int32_t *rank, void *stre
  *   L = 1/2 sum_k ||X_k - Qtilde_k H S_k V^T||_F^2,  S_k = diag(W(k,:)),
  * and its gradient: dH (R x R), dV (J x R), dW (K x R), optional dS (K x R x R, the full
  * dL/dS_k; may be NULL). Inputs and outputs are device FP32; *loss is written to host memory
- * (the call synchronises `stream`).                                                          */
+ * (the call synchronises `stream`). The first call on a plan allocates its work buffers
+ * (2 S R + J R floats), which the plan keeps until copa_plan_destroy.                       */
 copa_status copa_loss_grad(copa_plan *plan, const float *H, const float *V, const float *W,
                            const float *Qtilde, float *dH, float *dV, float *dW, float *dS,
                            double *loss, void *stream);
@@ -160,7 +161,7 @@ void copa_plan_destroy(copa_plan *plan);
  * copa_read_timing writes, per kernel id in [0, COPA_NUM_KERNELS), the summed milliseconds
  * (`ms`, host) and launch counts (`launches`, host) since the previous read, then resets them.
  * copa_kernel_name(id) names the kernel.                                                     */
-#define COPA_NUM_KERNELS 13
+#define COPA_NUM_KERNELS 8
 copa_status copa_set_timing(copa_plan *plan, int32_t enable);
 copa_status copa_read_timing(copa_plan *plan, double *ms, int64_t *launches);
 const char *copa_kernel_name(int32_t id);

@@ -16,10 +16,10 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kLMax = 8;           // spline basis functions per subject (padded row width of C)
 constexpr int kNMax = 8;           // largest Procrustes eigenproblem handled one subject per lane
 constexpr int kHistCap = 1024;     // per-iteration scalars buffered on the device
-constexpr int kGramBlocks = 128;   // partial-sum blocks of the row-Gram reductions
+constexpr int kGramBlocks = 64;    // partial-sum blocks of the row-Gram reductions
 constexpr int kChunkRows = 512;    // visit rows per chunk of the feature-sorted pass-2 layout
 constexpr int kMaxR = 64;
-constexpr int kNumKernels = 13;    // kernels of one outer iteration (see kernel_names)
+constexpr int kNumKernels = 8;     // kernels of one outer iteration (see kernel_names)
 constexpr int kTimingChunk = 64;   // iterations between event harvests when timing
 
 void set_error(const std::string &msg);
@@ -105,7 +105,7 @@ struct copa_plan {
   uint32_t *pkey = nullptr;  // [nnz] feature << 16 | row within chunk
   float *pval = nullptr;     // [nnz]
   int n_cu = 0;
-  double *gpart = nullptr;  // [kGramBlocks x R x R] scratch partials (row Grams)
+  double *gpart = nullptr;  // [4 x kGramBlocks x R x R] Gram partials: F_H, W^TW, Psi, V^TV
   int32_t *gcount = nullptr;  // [8] last-block counters of the row Grams
   double *vpart = nullptr;  // [blocks x 4] V-ADMM scalar partials
   int n_vblocks = 0;
@@ -121,7 +121,8 @@ struct copa_plan {
   int ev_used = 0;
   double t_ms[copa::kNumKernels] = {};
   int64_t t_cnt[copa::kNumKernels] = {};
-  float *gradbuf = nullptr; // [rows_total x R] scratch for the adjoint
+  float *gradbuf = nullptr; // [2 x S x R] U and D rows of the adjoint (allocated on first use)
+  double *lpart = nullptr;  // per-block loss partials of the adjoint
 };
 
 namespace copa {

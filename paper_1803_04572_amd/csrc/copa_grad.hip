@@ -1,12 +1,328 @@
-// Reconstruction loss and its gradient (copa_loss_grad).
+// Reconstruction loss of the PARAFAC2 model and its hand-written adjoint (copa_loss_grad).
+//
+//   L = 1/2 sum_k ||X_k - Qt_k H S_k V^T||^2,  S_k = diag(W(k,:)),  Qt held fixed
+//     (eq. Classic_PARAFAC2_obj_func with U_k = Qt_k H).
+// With G = V^T V and, per visit row i of subject k,
+//   t_i = x_i V,  a_i = qt_i H,  u_i = a_i * w_k (= qt_i H S_k),  z_i = u_i G,
+// the terms of the loss and of its gradient are sums over rows:
+//   <X_k, Qt_k H S_k V^T> = sum_i <u_i, t_i>,   ||Qt_k H S_k V^T||^2 = sum_i <z_i, u_i>,
+//   dL/dH    = sum_i qt_i^T ((z_i - t_i) * w_k)                    (-P_k S_k + Pi_k H S_k G S_k)
+//   dL/dV    = -sum_i x_i^T u_i + V sum_i u_i^T u_i                 (-X^T U + V Psi')
+//   dL/dS_k  = sum_{i in k} a_i^T (z_i - t_i)                       (-H^T P_k + H^T Pi_k H S_k G)
+//   dL/dW(k,r) = [dL/dS_k]_rr.
+#include <climits>
+
 #include "copa_common.h"
+#include "copa_kernels.h"
 
 namespace copa {
-copa_status launch_loss_grad(copa_plan *, const float *, const float *, const float *,
-                             const float *, float *, float *, float *, float *, hipStream_t) {
-  set_error("copa_loss_grad is not built yet");
-  return COPA_EUNSUPPORTED;
+
+// Rows pass: U and D rows, dW (reduced over the lanes of each subject) and the two loss sums.
+template <int R>
+__global__ void __launch_bounds__(256)
+    k_grad_rows(const WaveEntry *__restrict__ waves, int n_waves, const int32_t *__restrict__ order,
+                const int32_t *__restrict__ subj, const int32_t *__restrict__ row,
+                const int32_t *__restrict__ col, const float *__restrict__ val,
+                const float *__restrict__ V, const float *__restrict__ H,
+                const float *__restrict__ W, const float *__restrict__ Qt,
+                const double *__restrict__ Gm, float *__restrict__ U, float *__restrict__ D,
+                float *__restrict__ dW, double *__restrict__ lpart) {
+  __shared__ float sH[R * R];
+  __shared__ double sG[R * R];
+  __shared__ double red[2][256];
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    sH[e] = H[e];
+    sG[e] = Gm[e];
+  }
+  __syncthreads();
+  double lut = 0.0, lzu = 0.0;
+  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wv < n_waves) {
+    const int lane = threadIdx.x & 63;
+    const WaveEntry we = waves[wv];
+    const int lg = we.lg_count & 255, cnt = we.lg_count >> 8;
+    const int G = 1 << lg, sidx = lane >> lg, sub = lane & (G - 1);
+    const bool active = sidx < cnt;
+    const int k = active ? order[we.first + sidx] : 0;
+    const int r0 = active ? subj[k] : 0, r1 = active ? subj[k + 1] : 0;
+    float w[R], dw[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      w[r] = active ? W[(int64_t)k * R + r] : 0.0f;
+      dw[r] = 0.0f;
+    }
+    for (int i = r0 + sub; i < r1; i += G) {
+      float t[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) t[r] = 0.0f;
+      const int e0 = row[i], e1 = row[i + 1];
+      for (int eb = e0; eb < e1; eb += 4) {
+        int cj[4];
+        float xv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool ok = eb + q < e1;
+          const int ec = ok ? eb + q : e0;
+          cj[q] = col[ec];
+          const float x = val[ec];
+          xv[q] = ok ? x : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float *vr = V + (int64_t)cj[q] * R;
+#pragma unroll
+          for (int r = 0; r < R; ++r) t[r] += xv[q] * vr[r];
+        }
+      }
+      float qv[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) qv[r] = Qt[(int64_t)i * R + r];
+      float a[R], u[R];
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) s += (double)qv[r] * (double)sH[r * R + c];
+        a[c] = (float)s;
+        u[c] = (float)(s * (double)w[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        double z = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) z += (double)u[r] * sG[r * R + c];
+        const double d = z - (double)t[c];
+        U[(int64_t)i * R + c] = u[c];
+        D[(int64_t)i * R + c] = (float)(d * (double)w[c]);
+        dw[c] += (float)((double)a[c] * d);
+        lut += (double)u[c] * (double)t[c];
+        lzu += z * (double)u[c];
+      }
+    }
+    for (int m = 1; m < G; m <<= 1) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) dw[r] += shfl_xor_f(dw[r], m);
+    }
+    if (active && sub == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) dW[(int64_t)k * R + r] = dw[r];
+    }
+  }
+  red[0][threadIdx.x] = lut;
+  red[1][threadIdx.x] = lzu;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 2) lpart[blockIdx.x * 2 + threadIdx.x] = red[threadIdx.x][0];
 }
+
+// dV = -F + V Psi' (one row per thread); block 0 also writes dH and the loss.
+template <int R>
+__global__ void __launch_bounds__(256)
+    k_grad_finish(int64_t J, const float *__restrict__ F, const float *__restrict__ V,
+                  const double *__restrict__ partH, const double *__restrict__ partPsi, int nbp,
+                  const double *__restrict__ lpart, int nlp, double normX2,
+                  float *__restrict__ dV, float *__restrict__ dH, double *__restrict__ loss) {
+  __shared__ double sPsi[R * R];
+  __shared__ double sH[R * R];
+  __shared__ double scratch[256];
+  block_reduce_parts<R * R>(partPsi, nbp, sPsi, scratch);
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < J) {
+    float v[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) v[c] = V[j * R + c];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      double s = -(double)F[j * R + c];
+#pragma unroll
+      for (int r = 0; r < R; ++r) s += (double)v[r] * sPsi[r * R + c];
+      dV[j * R + c] = (float)s;
+    }
+  }
+  if (blockIdx.x == 0) {
+    block_reduce_parts<R * R>(partH, nbp, sH, scratch);
+    for (int e = threadIdx.x; e < R * R; e += blockDim.x) dH[e] = (float)sH[e];
+    if (threadIdx.x == 0) {
+      double ut = 0.0, zu = 0.0;
+      for (int b = 0; b < nlp; ++b) {
+        ut += lpart[2 * b];
+        zu += lpart[2 * b + 1];
+      }
+      *loss = 0.5 * (normX2 - 2.0 * ut + zu);
+    }
+  }
+}
+
+// Full dL/dS_k (optional): thread per (subject, slice of output rows); rows a in
+// [a0, a0 + AR) of dS_k accumulated in registers over the subject's visit rows.
+template <int R>
+__global__ void __launch_bounds__(64)
+    k_grad_dS(int64_t K, const int32_t *__restrict__ subj, const int32_t *__restrict__ row,
+              const int32_t *__restrict__ col, const float *__restrict__ val,
+              const float *__restrict__ V, const float *__restrict__ H,
+              const float *__restrict__ W, const float *__restrict__ Qt,
+              const double *__restrict__ Gm, float *__restrict__ dS) {
+  constexpr int AR = R <= 12 ? R : (128 / R > 0 ? 128 / R : 1);
+  constexpr int NP = (R + AR - 1) / AR;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= K * NP) return;
+  const int64_t k = gid / NP;
+  const int a0 = (int)(gid - k * NP) * AR;
+  float w[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) w[r] = W[k * R + r];
+  float acc[AR][R];
+#pragma unroll
+  for (int a = 0; a < AR; ++a)
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[a][c] = 0.0f;
+  for (int i = subj[k]; i < subj[k + 1]; ++i) {
+    float t[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) t[r] = 0.0f;
+    for (int e = row[i]; e < row[i + 1]; ++e) {
+      const float x = val[e];
+      const float *vr = V + (int64_t)col[e] * R;
+#pragma unroll
+      for (int r = 0; r < R; ++r) t[r] += x * vr[r];
+    }
+    float aa[R], e_[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) s += (double)Qt[(int64_t)i * R + r] * (double)H[r * R + c];
+      aa[c] = (float)s;
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      double z = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) z += (double)aa[r] * (double)w[r] * Gm[r * R + c];
+      e_[c] = (float)(z - (double)t[c]);
+    }
+#pragma unroll
+    for (int a = 0; a < AR; ++a) {
+      const float av = (a0 + a < R) ? aa[a0 + a < R ? a0 + a : 0] : 0.0f;
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc[a][c] += av * e_[c];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < AR; ++a)
+    if (a0 + a < R)
+#pragma unroll
+      for (int c = 0; c < R; ++c) dS[(k * R + a0 + a) * R + c] = acc[a][c];
+}
+
+template <int R>
+__global__ void __launch_bounds__(256)
+    k_grad_reduce(const double *__restrict__ part, int nb, double *dst) {
+  __shared__ double scratch[256];
+  block_reduce_parts<R * R>(part, nb, dst, scratch);
+}
+
+__global__ void k_zero_f(float *x, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    x[e] = 0.0f;
+}
+
+// F += X^T U with U given per visit row (the plain-rows mode of the streaming scatter).
+template <int RT>
+static void scatter_rt(copa_plan *p, const float *U, float *F, hipStream_t s) {
+  if (p->p2c) {
+    dim3 grid((unsigned)std::min(p->nchunks, 2 * std::max(1, p->n_cu)), (unsigned)p->tiles.nt),
+        block(512);
+    size_t lds = ((size_t)p->J * RT + (size_t)kChunkRows * RT) * sizeof(float);
+    k_pass2c<RT, false><<<grid, block, lds, s>>>(p->nchunks, p->S, p->wsplit, p->pkey, p->pval,
+                                                 p->rowsubj, p->C, U, p->J, p->R, 0, F);
+  } else {
+    dim3 grid((unsigned)((p->n_waves + 3) / 4), (unsigned)p->tiles.nt), block(256);
+    k_pass2<RT, false><<<grid, block, 0, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
+                                              p->col, p->val, p->C, U, p->J, p->R, 0, F);
+  }
+}
+
+template <int R>
+static void launch_scatter_rows(copa_plan *p, const float *U, float *F, hipStream_t s) {
+  switch (p->tiles.rt) {
+#define CASE(rt) \
+  case rt: scatter_rt<rt>(p, U, F, s); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11)
+    CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
+#undef CASE
+    default: break;
+  }
+}
+
+template <int R>
+static copa_status loss_grad_r(copa_plan *p, const float *H, const float *V, const float *W,
+                               const float *Qt, float *dH, float *dV, float *dW, float *dS,
+                               hipStream_t s) {
+  constexpr int RR = R * R;
+  double *partA = p->gpart;
+  double *partB = p->gpart + (size_t)kGramBlocks * RR;
+  double *Gm = p->small + 5 * RR;
+  float *U = p->gradbuf;
+  float *D = p->gradbuf + (size_t)p->S * R;
+  // G = V^T V
+  k_rows_gram<R><<<dim3(kGramBlocks, 1), 1024, 0, s>>>(V, V, p->J, nullptr, 0, 1, nullptr, partA,
+                                                       nullptr, 0, nullptr);
+  k_grad_reduce<R><<<1, 256, 0, s>>>(partA, kGramBlocks, Gm);
+  const int nb = std::max(1, (p->n_waves + 3) / 4);
+  k_grad_rows<R><<<nb, 256, 0, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row, p->col,
+                                    p->val, V, H, W, Qt, Gm, U, D, dW, p->lpart);
+  // dL/dH = Qt^T D and Psi' = U^T U in one launch
+  k_rows_gram<R><<<dim3(kGramBlocks, 2), 1024, 0, s>>>(Qt, D, p->S, nullptr, 0, 1, nullptr,
+                                                       partA, U, p->S, partB);
+  // F = X^T U through the feature-sorted scatter
+  float *F = p->gradbuf + (size_t)2 * p->S * R;
+  k_zero_f<<<(unsigned)std::min<int64_t>(1024, (p->J * R + 255) / 256), 256, 0, s>>>(F, p->J * R);
+  launch_scatter_rows<R>(p, U, F, s);
+  k_grad_finish<R><<<(unsigned)std::max<int64_t>(1, (p->J + 255) / 256), 256, 0, s>>>(
+      p->J, F, V, partA, partB, kGramBlocks, p->lpart, nb, p->normX2, dV, dH, p->dloss);
+  if (dS && p->K > 0) {
+    constexpr int AR = R <= 12 ? R : (128 / R > 0 ? 128 / R : 1);
+    constexpr int NP = (R + AR - 1) / AR;
+    k_grad_dS<R><<<(unsigned)((p->K * NP + 63) / 64), 64, 0, s>>>(
+        p->K, p->subj, p->row, p->col, p->val, V, H, W, Qt, Gm, dS);
+  }
+  COPA_HIP(hipGetLastError());
+  return COPA_OK;
+}
+
+copa_status launch_loss_grad(copa_plan *p, const float *H, const float *V, const float *W,
+                             const float *Qt, float *dH, float *dV, float *dW, float *dS,
+                             hipStream_t s) {
+  if (!p->gradbuf) {
+    // first use: U and D rows (2 S R floats), F (J R) and the per-block loss partials
+    const size_t n = std::max<size_t>(1, (size_t)2 * p->S * p->R + (size_t)p->J * p->R);
+    hipError_t e = hipMalloc((void **)&p->gradbuf, n * sizeof(float));
+    if (e == hipSuccess)
+      e = hipMalloc((void **)&p->lpart,
+                    (size_t)2 * std::max(1, (p->n_waves + 3) / 4) * sizeof(double));
+    if (e != hipSuccess) {
+      set_error(std::string("hipMalloc for the gradient buffers: ") + hipGetErrorString(e));
+      return COPA_ENOMEM;
+    }
+  }
+  switch (p->R) {
+#define CASE(r) \
+  case r: return loss_grad_r<r>(p, H, V, W, Qt, dH, dV, dW, dS, s);
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(10) CASE(12) CASE(15)
+    CASE(16) CASE(20) CASE(24) CASE(32) CASE(40)
+#undef CASE
+    default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
+  }
+}
+
 }  // namespace copa
 
 using namespace copa;
@@ -14,9 +330,15 @@ using namespace copa;
 extern "C" copa_status copa_loss_grad(copa_plan *p, const float *H, const float *V, const float *W,
                                       const float *Qt, float *dH, float *dV, float *dW, float *dS,
                                       double *loss, void *stream) {
-  if (!p || !H || !V || !W || !Qt || !dH || !dV || !dW || !loss) {
+  if (!p || !H || !V || !Qt || !dH || !dV || !loss || (p->K > 0 && (!W || !dW))) {
     set_error("NULL argument");
     return COPA_EINVAL;
   }
-  return launch_loss_grad(p, H, V, W, Qt, dH, dV, dW, dS, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  COPA_HIP(hipSetDevice(p->device));
+  copa_status st = launch_loss_grad(p, H, V, W, Qt, dH, dV, dW, dS, s);
+  if (st != COPA_OK) return st;
+  COPA_HIP(hipMemcpyAsync(loss, p->dloss, sizeof(double), hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipStreamSynchronize(s));
+  return COPA_OK;
 }

@@ -20,6 +20,7 @@
 #include <climits>
 
 #include "copa_common.h"
+#include "copa_kernels.h"
 
 namespace copa {
 
@@ -62,9 +63,22 @@ __global__ void __launch_bounds__(256)
   constexpr int RTP = (RT + 3) & ~3;
   extern __shared__ float4 smem4[];
   {
+    // stage the tile with 8 loads in flight per thread
     const float4 *src = reinterpret_cast<const float4 *>(Vp + (int64_t)blockIdx.y * J * RTP);
     const int64_t n4 = J * RTP / 4;
-    for (int64_t e = threadIdx.x; e < n4; e += blockDim.x) smem4[e] = src[e];
+    for (int64_t e0 = 0; e0 < n4; e0 += 8 * (int64_t)blockDim.x) {
+      float4 tmp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t e = e0 + u * blockDim.x + threadIdx.x;
+        tmp[u] = src[e < n4 ? e : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t e = e0 + u * blockDim.x + threadIdx.x;
+        if (e < n4) smem4[e] = tmp[u];
+      }
+    }
   }
   __syncthreads();
   const float *sV = reinterpret_cast<const float *>(smem4);
@@ -84,24 +98,37 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int r = 0; r < RT; ++r) acc[a][r] = 0.0f;
       for (int i = r0 + sub; i < r1; i += G) {
+        const float4 *c4 = reinterpret_cast<const float4 *>(C + (int64_t)i * kLMax);
+        const float4 ca = c4[0], cb = c4[1];
         float t[RTP];
 #pragma unroll
         for (int r = 0; r < RTP; ++r) t[r] = 0.0f;
-        const int e1 = row[i + 1];
-        for (int e = row[i]; e < e1; ++e) {
-          const float x = val[e];
-          const float4 *v4 = reinterpret_cast<const float4 *>(sV + (int64_t)col[e] * RTP);
+        const int e0 = row[i], e1 = row[i + 1];
+        for (int eb = e0; eb < e1; eb += 8) {
+          int cj[8];
+          float xv[8];
 #pragma unroll
-          for (int q = 0; q < RTP / 4; ++q) {
-            const float4 v = v4[q];
-            t[4 * q + 0] += x * v.x;
-            t[4 * q + 1] += x * v.y;
-            t[4 * q + 2] += x * v.z;
-            t[4 * q + 3] += x * v.w;
+          for (int u = 0; u < 8; ++u) {
+            const bool ok = eb + u < e1;
+            const int ec = ok ? eb + u : e0;
+            cj[u] = col[ec];
+            const float x = val[ec];
+            xv[u] = ok ? x : 0.0f;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const float x = xv[u];
+            const float4 *v4 = reinterpret_cast<const float4 *>(sV + (int64_t)cj[u] * RTP);
+#pragma unroll
+            for (int q = 0; q < RTP / 4; ++q) {
+              const float4 v = v4[q];
+              t[4 * q + 0] += x * v.x;
+              t[4 * q + 1] += x * v.y;
+              t[4 * q + 2] += x * v.z;
+              t[4 * q + 3] += x * v.w;
+            }
           }
         }
-        const float4 *c4 = reinterpret_cast<const float4 *>(C + (int64_t)i * kLMax);
-        const float4 ca = c4[0], cb = c4[1];
         const float c[kLMax] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
 #pragma unroll
         for (int a = 0; a < kLMax; ++a)
@@ -127,17 +154,30 @@ __global__ void __launch_bounds__(256)
         float t[RTP];
 #pragma unroll
         for (int r = 0; r < RTP; ++r) t[r] = 0.0f;
-        const int e1 = row[i + 1];
-        for (int e = row[i]; e < e1; ++e) {
-          const float x = val[e];
-          const float4 *v4 = reinterpret_cast<const float4 *>(sV + (int64_t)col[e] * RTP);
+        const int e0 = row[i], e1 = row[i + 1];
+        for (int eb = e0; eb < e1; eb += 8) {
+          int cj[8];
+          float xv[8];
 #pragma unroll
-          for (int q = 0; q < RTP / 4; ++q) {
-            const float4 v = v4[q];
-            t[4 * q + 0] += x * v.x;
-            t[4 * q + 1] += x * v.y;
-            t[4 * q + 2] += x * v.z;
-            t[4 * q + 3] += x * v.w;
+          for (int u = 0; u < 8; ++u) {
+            const bool ok = eb + u < e1;
+            const int ec = ok ? eb + u : e0;
+            cj[u] = col[ec];
+            const float x = val[ec];
+            xv[u] = ok ? x : 0.0f;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const float x = xv[u];
+            const float4 *v4 = reinterpret_cast<const float4 *>(sV + (int64_t)cj[u] * RTP);
+#pragma unroll
+            for (int q = 0; q < RTP / 4; ++q) {
+              const float4 v = v4[q];
+              t[4 * q + 0] += x * v.x;
+              t[4 * q + 1] += x * v.y;
+              t[4 * q + 2] += x * v.z;
+              t[4 * q + 3] += x * v.w;
+            }
           }
         }
         float *dst = T + (int64_t)i * R + c0;
@@ -212,6 +252,55 @@ __device__ __forceinline__ void jacobi8(double (&A)[kNMax][kNMax], double (&V)[k
   }
 }
 
+// Same eigensolver on a packed upper triangle (36 values), for the register-resident path.
+__host__ __device__ constexpr int tri8(int i, int j) {
+  return i <= j ? 8 * i - (i * (i - 1)) / 2 + (j - i) : 8 * j - (j * (j - 1)) / 2 + (i - j);
+}
+
+__device__ __forceinline__ void jacobi8_tri(double (&A)[36], double (&V)[kNMax][kNMax]) {
+#pragma unroll
+  for (int i = 0; i < kNMax; ++i)
+#pragma unroll
+    for (int j = 0; j < kNMax; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+  double scale = 0.0;
+#pragma unroll
+  for (int i = 0; i < kNMax; ++i) scale += fabs(A[tri8(i, i)]);
+  const double tiny = 1e-300 + 1e-17 * scale;
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    bool rotated = false;
+#pragma unroll
+    for (int p = 0; p < kNMax - 1; ++p) {
+#pragma unroll
+      for (int q = p + 1; q < kNMax; ++q) {
+        const double apq = A[tri8(p, q)];
+        if (fabs(apq) > tiny) {
+          rotated = true;
+          const double tau = (A[tri8(q, q)] - A[tri8(p, p)]) / (2.0 * apq);
+          const double t = copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+#pragma unroll
+          for (int k = 0; k < kNMax; ++k) {
+            if (k == p || k == q) continue;
+            const double akp = A[tri8(k, p)], akq = A[tri8(k, q)];
+            A[tri8(k, p)] = c * akp - s * akq;
+            A[tri8(k, q)] = s * akp + c * akq;
+          }
+          A[tri8(p, p)] -= t * apq;
+          A[tri8(q, q)] += t * apq;
+          A[tri8(p, q)] = 0.0;
+#pragma unroll
+          for (int k = 0; k < kNMax; ++k) {
+            const double vkp = V[k][p], vkq = V[k][q];
+            V[k][p] = c * vkp - s * vkq;
+            V[k][q] = s * vkp + c * vkq;
+          }
+        }
+      }
+    }
+    if (!rotated) break;
+  }
+}
+
 // One subject per lane, eigenproblem size n = min(m, R) <= kNMax.
 // A rows a_i = (t_i * w) H^T are computed in FP64 and kept as FP32 in the M buffer (free until
 // the W update). Rows side (m <= R): Gram A A^T, Q = (A A^T)^{+1/2} A. Columns side (m > R):
@@ -238,6 +327,7 @@ __global__ void __launch_bounds__(64)
     m = subj[k + 1] - subj[k];
     meff = m;
   }
+  if ((m < R ? m : R) > kNMax) return;  // one wavefront per subject handles these
   float w[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) w[r] = W[k * R + r];
@@ -359,170 +449,326 @@ __global__ void __launch_bounds__(64)
   if (rank < (meff < R ? meff : R)) atomicAdd(rank_def, 1);
 }
 
-// ======================================================================= row Gram reductions
-// dst = sum over rows of A_row^T (B_row * w_subj(row)) (R x R, FP64), a dense contraction over
-// the long row dimension done on the matrix cores: v_mfma_f64_16x16x4f64 takes 4 rows per
-// instruction, lane l holding A[row0 + l/16][16 ti + l%16] and B[row0 + l/16][16 tj + l%16].
-// wsel: 0 = no scaling; 1 = scale B by W[row / slot_rows]; 2 = scale by W[rowsubj[row]].
-// Every block writes its partial; the last block to finish adds the partials in block order (the
-// result does not depend on scheduling) into dst and resets the counter.
-typedef double dbl4_t __attribute__((ext_vector_type(4)));
-
+// Unsmoothed subjects whose eigenproblem n = min(I_k, R) exceeds what a lane holds: one
+// wavefront per subject, n x n Gram and eigenvectors in LDS (FP64), cyclic Jacobi with every lane
+// updating one row/column per rotation. Rows side (I_k <= R): A = T S H^T (I_k x R) in LDS,
+// Gram A A^T, Q = B A. Columns side (I_k > R): Gamma = sum_i t_i^T t_i streamed, Gram
+// H S Gamma S H^T, N = S H^T B and Q rows q_i = t_i N.
 template <int R>
-__global__ void __launch_bounds__(256)
-    k_rows_gram(const float *__restrict__ A, const float *__restrict__ B, int64_t rows,
-                const float *__restrict__ W, int wsel, int slot_rows,
-                const int32_t *__restrict__ rowsubj, double *__restrict__ part,
-                double *__restrict__ dst, int32_t *counter) {
-  constexpr int NT = (R + 15) / 16;
-  constexpr int RP = NT * 16;
-  constexpr int RR = R * R;
-  __shared__ double sacc[RP * RP];
-  __shared__ int last;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int m = lane & 15, kk = lane >> 4;
-  for (int e = t; e < RP * RP; e += blockDim.x) sacc[e] = 0.0;
-  const int64_t per = ((rows + gridDim.x - 1) / gridDim.x + 15) & ~(int64_t)15;
-  const int64_t lo = blockIdx.x * per;
-  const int64_t hi = lo + per < rows ? lo + per : rows;
-  dbl4_t acc[NT][NT];
-#pragma unroll
-  for (int i = 0; i < NT; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[i][j] = dbl4_t{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int64_t r0 = lo + 4 * wave; r0 < hi; r0 += 16) {
-    const int64_t rr = r0 + kk;
-    const bool ok = rr < hi;
-    double av[NT], bv[NT];
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      const int c = q * 16 + m;
-      const bool in = ok && c < R;
-      av[q] = in ? (double)A[rr * R + c] : 0.0;
-      double b = in ? (double)B[rr * R + c] : 0.0;
-      if (in && wsel == 1) b *= (double)W[(rr / slot_rows) * R + c];
-      else if (in && wsel == 2) b *= (double)W[(int64_t)rowsubj[rr] * R + c];
-      bv[q] = b;
+__global__ void __launch_bounds__(64)
+    k_procrustes_wave(const int32_t *__restrict__ list, int nlist,
+                      const int32_t *__restrict__ subj, const float *__restrict__ T,
+                      float *__restrict__ Q, const float *__restrict__ H,
+                      const float *__restrict__ W, double rtol, int32_t *rank_def) {
+  __shared__ double sG[R * R];
+  __shared__ double sE[R * R];
+  __shared__ double sA[R * R];  // A (rows side) or Gamma, then N (columns side)
+  __shared__ double sw[R];
+  __shared__ double sf[R];
+  __shared__ float sH[R * R];
+  const int lane = threadIdx.x;
+  if ((int)blockIdx.x >= nlist) return;
+  const int k = list[blockIdx.x];
+  const int r0 = subj[k], m = subj[k + 1] - r0;
+  const bool rows_side = m <= R;
+  const int n = rows_side ? m : R;
+  for (int e = lane; e < R * R; e += 64) sH[e] = H[e];
+  for (int e = lane; e < R; e += 64) sw[e] = W[(int64_t)k * R + e];
+  __syncthreads();
+  if (rows_side) {
+    // A(i, c) = sum_r t_i[r] w_r H(c, r)
+    for (int e = lane; e < m * R; e += 64) {
+      const int i = e / R, c = e % R;
+      const float *t = T + (int64_t)(r0 + i) * R;
+      double s = 0.0;
+      for (int r = 0; r < R; ++r) s += (double)t[r] * sw[r] * (double)sH[c * R + r];
+      sA[i * R + c] = (double)(float)s;
     }
+    __syncthreads();
+    for (int e = lane; e < n * n; e += 64) {
+      const int p = e / n, q = e % n;
+      double s = 0.0;
+      for (int c = 0; c < R; ++c) s += sA[p * R + c] * sA[q * R + c];
+      sG[p * n + q] = s;
+    }
+  } else {
+    // Gamma = T^T T (lane a owns row a), then Z = Gamma o (w w^T) and G = H Z H^T
+    double acc[R];
+    for (int b = 0; b < R; ++b) acc[b] = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const float *t = T + (int64_t)(r0 + i) * R;
+      const double ta = lane < R ? (double)t[lane] : 0.0;
 #pragma unroll
-    for (int i = 0; i < NT; ++i)
-#pragma unroll
-      for (int j = 0; j < NT; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+      for (int b = 0; b < R; ++b) acc[b] += ta * (double)t[b];
+    }
+    if (lane < R)
+      for (int b = 0; b < R; ++b) sA[lane * R + b] = acc[b] * sw[lane] * sw[b];
+    __syncthreads();
+    // sE <- H Z
+    for (int e = lane; e < R * R; e += 64) {
+      const int a = e / R, b = e % R;
+      double s = 0.0;
+      for (int c = 0; c < R; ++c) s += (double)sH[a * R + c] * sA[c * R + b];
+      sE[e] = s;
+    }
+    __syncthreads();
+    for (int e = lane; e < R * R; e += 64) {
+      const int a = e / R, b = e % R;
+      double s = 0.0;
+      for (int c = 0; c < R; ++c) s += sE[a * R + c] * (double)sH[b * R + c];
+      sG[a * R + b] = s;
+    }
   }
   __syncthreads();
-  // D[ii][jj] of a 16 x 16 FP64 block: lane jj + 16 (ii % 4), element ii / 4
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int i = 0; i < NT; ++i)
-#pragma unroll
-        for (int j = 0; j < NT; ++j)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int ii = i * 16 + 4 * v + (lane >> 4), jj = j * 16 + (lane & 15);
-            sacc[ii * RP + jj] += acc[i][j][v];
+  for (int e = lane; e < n * n; e += 64) sE[e] = (e / n == e % n) ? 1.0 : 0.0;
+  double scale = 0.0;
+  for (int i = 0; i < n; ++i) scale += fabs(sG[i * n + i]);
+  const double tiny = 1e-300 + 1e-17 * scale;
+  __syncthreads();
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < n - 1; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = sG[p * n + q];
+        if (fabs(apq) > tiny) {
+          rotated = true;
+          const double app = sG[p * n + p], aqq = sG[q * n + q];
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+          __syncthreads();
+          if (lane < n && lane != p && lane != q) {
+            const double gkp = sG[lane * n + p], gkq = sG[lane * n + q];
+            const double np_ = c * gkp - s * gkq, nq_ = s * gkp + c * gkq;
+            sG[lane * n + p] = np_;
+            sG[p * n + lane] = np_;
+            sG[lane * n + q] = nq_;
+            sG[q * n + lane] = nq_;
           }
-    }
-    __syncthreads();
-  }
-  for (int e = t; e < RR; e += blockDim.x)
-    part[(int64_t)blockIdx.x * RR + e] = sacc[(e / R) * RP + e % R];
-  __threadfence();
-  __syncthreads();
-  if (t == 0) last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const int nb = gridDim.x;
-  constexpr int G2 = RR >= 256 ? 1 : 256 / RR;
-  double *sred = sacc;  // reuse (RP*RP >= 256 doubles)
-  for (int e0 = 0; e0 < RR; e0 += 256 / G2) {
-    const int e = e0 + t % (256 / G2 < RR ? 256 / G2 : RR);
-    const int g = t / (256 / G2 < RR ? 256 / G2 : RR);
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (e < RR && g < G2) {
-      int b = g;
-      for (; b + 7 * G2 < nb; b += 8 * G2) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          s[u] += __hip_atomic_load(&part[(int64_t)(b + u * G2) * RR + e], __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
+          if (lane < n) {
+            const double vkp = sE[lane * n + p], vkq = sE[lane * n + q];
+            sE[lane * n + p] = c * vkp - s * vkq;
+            sE[lane * n + q] = s * vkp + c * vkq;
+          }
+          if (lane == 0) {
+            sG[p * n + p] = app - t * apq;
+            sG[q * n + q] = aqq + t * apq;
+            sG[p * n + q] = 0.0;
+            sG[q * n + p] = 0.0;
+          }
+          __syncthreads();
+        }
       }
-      for (; b < nb; b += G2)
-        s[0] += __hip_atomic_load(&part[(int64_t)b * RR + e], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!rotated) break;
+  }
+  double lmax = 0.0;
+  for (int j = 0; j < n; ++j) lmax = fmax(lmax, sG[j * n + j]);
+  int rank = 0;
+  for (int j = 0; j < n; ++j) rank += (lmax > 0.0 && sG[j * n + j] > rtol * rtol * lmax) ? 1 : 0;
+  if (lane < n) {
+    const double lj = sG[lane * n + lane];
+    sf[lane] = (lmax > 0.0 && lj > rtol * rtol * lmax) ? 1.0 / sqrt(lj) : 0.0;
+  }
+  __syncthreads();
+  // B = E diag(f) E^T (n x n) into sG
+  for (int e = lane; e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    double s = 0.0;
+    for (int q = 0; q < n; ++q) s += sE[i * n + q] * sf[q] * sE[j * n + q];
+    sG[e] = s;
+  }
+  __syncthreads();
+  if (rows_side) {
+    // Q = B A
+    for (int e = lane; e < m * R; e += 64) {
+      const int i = e / R, c = e % R;
+      double s = 0.0;
+      for (int j = 0; j < m; ++j) s += sG[i * n + j] * sA[j * R + c];
+      Q[(int64_t)(r0 + i) * R + c] = (float)s;
+    }
+  } else {
+    // N = S H^T B (R x R) into sA, then q_i = t_i N
+    for (int e = lane; e < R * R; e += 64) {
+      const int a = e / R, b = e % R;
+      double s = 0.0;
+      for (int c = 0; c < R; ++c) s += (double)sH[c * R + a] * sG[c * R + b];
+      sA[e] = sw[a] * s;
     }
     __syncthreads();
-    sred[t] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-    __syncthreads();
-    if (t < (256 / G2 < RR ? 256 / G2 : RR) && e0 + t < RR) {
-      double v = 0.0;
-      for (int q = 0; q < G2; ++q) v += sred[q * (256 / G2 < RR ? 256 / G2 : RR) + t];
-      dst[e0 + t] = v;
+    for (int i = 0; i < m; ++i) {
+      const float *t = T + (int64_t)(r0 + i) * R;
+      if (lane < R) {
+        double s = 0.0;
+        for (int r = 0; r < R; ++r) s += (double)t[r] * sA[r * R + lane];
+        Q[(int64_t)(r0 + i) * R + lane] = (float)s;
+      }
     }
   }
-  if (t == 0) *counter = 0;
+  if (lane == 0 && rank < (m < R ? m : R)) atomicAdd(rank_def, 1);
+}
+
+// Smoothed subjects (l <= 8 projected rows) with R <= 16: the same computation with T and A held
+// in registers, rows unrolled to kLMax (rows at or past l are zero).
+template <int R>
+__global__ void __launch_bounds__(64)
+    k_procrustes_s(int64_t K, int l, const int32_t *__restrict__ rk, const float *__restrict__ T,
+                   float *__restrict__ Q, const float *__restrict__ H, const float *__restrict__ W,
+                   double rtol, int32_t *rank_def) {
+  __shared__ float sH[R * R];
+  __shared__ float sA[kLMax * R * 64];  // A of this lane's subject, element (i, c) at (i R + c) 64 + lane
+  const int lane = threadIdx.x;
+  for (int e = lane; e < R * R; e += blockDim.x) sH[e] = H[e];
+  __syncthreads();
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + lane;
+  if (k >= K) return;
+  const int64_t base = k * l;
+  {
+    float w[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) w[r] = W[k * R + r];
+#pragma unroll
+    for (int i = 0; i < kLMax; ++i) {
+      const float *t = T + (base + (i < l ? i : 0)) * R;
+      float z[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) z[r] = t[r] * w[r];
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) s += (double)z[r] * (double)sH[c * R + r];
+        sA[(i * R + c) * 64 + lane] = i < l ? (float)s : 0.0f;
+      }
+    }
+  }
+  auto Aat = [&](int i, int c) -> double { return (double)sA[(i * R + c) * 64 + lane]; };
+  const bool rows_side = l <= R;
+  double G[36];
+#pragma unroll
+  for (int p = 0; p < kNMax; ++p)
+#pragma unroll
+    for (int q = p; q < kNMax; ++q) {
+      double s = 0.0;
+      if (rows_side) {
+        for (int c = 0; c < R; ++c) s += Aat(p, c) * Aat(q, c);
+      } else if (p < R && q < R) {
+        for (int i = 0; i < kLMax; ++i) s += Aat(i, p) * Aat(i, q);
+      }
+      G[tri8(p, q)] = s;
+    }
+  double E[kNMax][kNMax];
+  jacobi8_tri(G, E);
+  double lmax = 0.0;
+#pragma unroll
+  for (int j = 0; j < kNMax; ++j) lmax = fmax(lmax, G[tri8(j, j)]);
+  double f[kNMax];
+  int rank = 0;
+#pragma unroll
+  for (int j = 0; j < kNMax; ++j) {
+    const double lj = G[tri8(j, j)];
+    const bool keep = lmax > 0.0 && lj > rtol * rtol * lmax;
+    f[j] = keep ? 1.0 / sqrt(lj) : 0.0;
+    rank += keep ? 1 : 0;
+  }
+  // B = E diag(f) E^T (symmetric) into the triangle
+#pragma unroll
+  for (int i = 0; i < kNMax; ++i)
+#pragma unroll
+    for (int j = i; j < kNMax; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < kNMax; ++q) s += E[i][q] * f[q] * E[j][q];
+      G[tri8(i, j)] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < kLMax; ++i) {
+    if (i < l) {
+      float *dst = Q + (base + i) * R;
+      for (int c = 0; c < R; ++c) {
+        double s = 0.0;
+        if (rows_side) {
+#pragma unroll
+          for (int j = 0; j < kLMax; ++j) s += G[tri8(i, j)] * Aat(j, c);
+        } else {
+#pragma unroll
+          for (int j = 0; j < kNMax; ++j)
+            if (j < R && c < kNMax) s += Aat(i, j) * G[tri8(j, c < kNMax ? c : 0)];
+        }
+        dst[c] = (float)s;
+      }
+    }
+  }
+  const int meff = rk[k];
+  if (rank < (meff < R ? meff : R)) atomicAdd(rank_def, 1);
 }
 
 // ======================================================================= ADMM helpers
-// Cholesky of G + rho I in shared memory (FP64, lower triangle, row-major). Returns false
-// (and leaves L = I) if a pivot is not positive and finite.
+// sL <- Cholesky factor of X * Y + rho I (Hadamard product, FP64, lower triangle, row-major),
+// rho = trace(X * Y) / R (Algorithm 1). Whole block; one thread for R <= 16. Returns false (and
+// leaves L = I, rho = 1) when a pivot is not positive and finite.
 template <int R>
-__device__ bool block_cholesky(double *sL, int *sflag) {
-  if (threadIdx.x == 0) *sflag = 0;
+__device__ bool build_system(const double *__restrict__ X, const double *__restrict__ Y,
+                             double *sL, double *srho, int *sflag) {
+  const int t = threadIdx.x;
+  for (int e = t; e < R * R; e += blockDim.x) sL[e] = X[e] * Y[e];
   __syncthreads();
-  for (int j = 0; j < R; ++j) {
-    if (threadIdx.x == 0) {
-      double d = sL[j * R + j];
-      if (!(d > 0.0) || !isfinite(d)) {
-        *sflag = 1;
-        d = 1.0;
+  if (t == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < R; ++i) tr += sL[i * R + i];
+    const double rho = tr / R;
+    *srho = rho;
+    *sflag = (isfinite(rho) && rho > 0.0) ? 0 : 1;
+    for (int i = 0; i < R; ++i) sL[i * R + i] += rho;
+  }
+  __syncthreads();
+  if constexpr (R <= 16) {
+    if (t == 0) {
+      for (int j = 0; j < R; ++j) {
+        double d = sL[j * R + j];
+        for (int k = 0; k < j; ++k) d -= sL[j * R + k] * sL[j * R + k];
+        if (!(d > 0.0) || !isfinite(d)) {
+          *sflag = 1;
+          d = 1.0;
+        }
+        const double ljj = sqrt(d);
+        sL[j * R + j] = ljj;
+        for (int i = j + 1; i < R; ++i) {
+          double v = sL[i * R + j];
+          for (int k = 0; k < j; ++k) v -= sL[i * R + k] * sL[j * R + k];
+          sL[i * R + j] = v / ljj;
+        }
       }
-      sL[j * R + j] = sqrt(d);
     }
     __syncthreads();
-    const double djj = sL[j * R + j];
-    for (int i = j + 1 + threadIdx.x; i < R; i += blockDim.x) sL[i * R + j] /= djj;
-    __syncthreads();
-    for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
-      const int i = e / R, c = e % R;
-      if (i > j && c > j && c <= i) sL[i * R + c] -= sL[i * R + j] * sL[c * R + j];
+  } else {
+    for (int j = 0; j < R; ++j) {
+      if (t == 0) {
+        double d = sL[j * R + j];
+        if (!(d > 0.0) || !isfinite(d)) {
+          *sflag = 1;
+          d = 1.0;
+        }
+        sL[j * R + j] = sqrt(d);
+      }
+      __syncthreads();
+      const double djj = sL[j * R + j];
+      for (int i = j + 1 + t; i < R; i += blockDim.x) sL[i * R + j] /= djj;
+      __syncthreads();
+      for (int e = t; e < R * R; e += blockDim.x) {
+        const int i = e / R, c = e % R;
+        if (i > j && c > j && c <= i) sL[i * R + c] -= sL[i * R + j] * sL[c * R + j];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   const bool ok = *sflag == 0;
   if (!ok) {
-    for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = (e / R == e % R) ? 1.0 : 0.0;
+    for (int e = t; e < R * R; e += blockDim.x) sL[e] = (e / R == e % R) ? 1.0 : 0.0;
+    if (t == 0) *srho = 1.0;
   }
   __syncthreads();
   return ok;
-}
-
-// Builds G = X * Y (Hadamard), rho = tr(G)/R and its Cholesky into `mp`; flags failure.
-template <int R>
-__device__ void mode_prepare(const double *X, const double *Y, ModeParams *mp, FitScalars *sc) {
-  __shared__ double sL[R * R];
-  __shared__ double srho;
-  __shared__ int sflag;
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = X[e] * Y[e];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double tr = 0.0;
-    for (int i = 0; i < R; ++i) tr += sL[i * R + i];
-    srho = tr / R;
-  }
-  __syncthreads();
-  const double rho = srho;
-  for (int i = threadIdx.x; i < R; i += blockDim.x) sL[i * R + i] += rho;
-  __syncthreads();
-  const bool ok = block_cholesky<R>(sL, &sflag) && isfinite(rho) && rho > 0.0;
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) mp->L[e] = sL[e];
-  if (threadIdx.x == 0) {
-    mp->rho = rho > 0.0 && isfinite(rho) ? rho : 1.0;
-    if (!ok) atomicMin(&sc->fail_iter, sc->iter);
-  }
 }
 
 // Inner ADMM steps on one row (Algorithm 1 inner loop):
@@ -557,47 +803,53 @@ __device__ __forceinline__ void admm_row(const double (&F)[R], float (&Zb)[R], f
 }
 
 // ======================================================================= mode H (one block)
+// F_H from the Gram partials; G_H = W^TW * V^TV, rho, Cholesky; inner ADMM on the R rows of H;
+// H^T H; then the W-mode system G_W = H^TH * V^TV for the W update. Also clears F_V for pass 2.
 template <int R>
 __global__ void __launch_bounds__(256)
-    k_mode_H(double *small, ModeParams *modes, FitScalars *sc, float *H, float *DH, int kind,
-             double lam, int iters) {
+    k_mode_H(const double *__restrict__ partFH, int nb, double *small, ModeParams *modes,
+             FitScalars *sc, float *H, float *DH, int kind, double lam, int iters,
+             float *__restrict__ FV, int64_t nFV) {
   __shared__ double sFH[R * R];
   __shared__ double sL[R * R];
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sFH[e] = small[kFH * R * R + e];
-  __syncthreads();
-  mode_prepare<R>(small + kWtW * R * R, small + kVtV * R * R, &modes[0], sc);
-  __syncthreads();
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = modes[0].L[e];
-  __syncthreads();
-  const double rho = modes[0].rho;
-  if (threadIdx.x < R) {
-    const int i = threadIdx.x;
+  __shared__ double scratch[256];
+  __shared__ double srho;
+  __shared__ int sflag;
+  const int t = threadIdx.x;
+  for (int64_t e = t; e < nFV; e += blockDim.x) FV[e] = 0.0f;
+  block_reduce_parts<R * R>(partFH, nb, sFH, scratch);
+  for (int e = t; e < R * R; e += blockDim.x) small[kFH * R * R + e] = sFH[e];
+  bool ok = build_system<R>(small + kWtW * R * R, small + kVtV * R * R, sL, &srho, &sflag);
+  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->iter);
+  const double rho = srho;
+  if (t < R) {
     double F[R];
     float Zb[R], D[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
-      F[c] = sFH[i * R + c];
-      Zb[c] = H[i * R + c];
-      D[c] = DH[i * R + c];
+      F[c] = sFH[t * R + c];
+      Zb[c] = H[t * R + c];
+      D[c] = DH[t * R + c];
     }
     admm_row<R>(F, Zb, D, sL, rho, kind, lam, iters);
 #pragma unroll
     for (int c = 0; c < R; ++c) {
-      H[i * R + c] = Zb[c];
-      DH[i * R + c] = D[c];
+      H[t * R + c] = Zb[c];
+      DH[t * R + c] = D[c];
     }
   }
-  __threadfence_block();
   __syncthreads();
-  // H^T H from the stored FP32 values, then the W-mode system G_W = H^TH * V^TV
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+  for (int e = t; e < R * R; e += blockDim.x) {
     const int a = e / R, b = e % R;
-    double s = 0.0;
-    for (int i = 0; i < R; ++i) s += (double)H[i * R + a] * (double)H[i * R + b];
-    small[kHtH * R * R + e] = s;
+    double v = 0.0;
+    for (int i = 0; i < R; ++i) v += (double)H[i * R + a] * (double)H[i * R + b];
+    small[kHtH * R * R + e] = v;
   }
   __syncthreads();
-  mode_prepare<R>(small + kHtH * R * R, small + kVtV * R * R, &modes[1], sc);
+  ok = build_system<R>(small + kHtH * R * R, small + kVtV * R * R, sL, &srho, &sflag);
+  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->iter);
+  for (int e = t; e < R * R; e += blockDim.x) modes[1].L[e] = sL[e];
+  if (t == 0) modes[1].rho = srho;
 }
 
 // ======================================================================= mode W (lane/subject)
@@ -687,198 +939,49 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// ======================================================================= streaming pass 2
-// F_V(j,:) += x_ij * u_i with u_i = c_i M_k (smoothed: basis row times Q_k H S_k) or the M row of
-// visit i (plain). Chunked form: for every block of kChunkRows visit rows the plan stores the
-// chunk's nonzeros sorted by feature (key = feature << 16 | row in chunk) and 9 split points
-// that cut the sorted list into 8 slices on feature boundaries, one per wave. A block puts the
-// chunk's u rows in LDS; each lane sums a contiguous run of its wave's slice feature by feature;
-// a segmented scan over the lanes joins runs that share a feature, so every feature is added to
-// the block's LDS copy of F_V by exactly one lane - no LDS atomics. The block's F_V tile goes to
-// the global F_V with one atomic add per entry at the end.
-template <int RT, bool SMOOTH>
-__global__ void __launch_bounds__(512)
-    k_pass2c(int nchunks, int64_t S, const int32_t *__restrict__ wsplit,
-             const uint32_t *__restrict__ pkey, const float *__restrict__ pval,
-             const int32_t *__restrict__ rowsubj, const float *__restrict__ C,
-             const float *__restrict__ M, int64_t J, int R, int l, float *__restrict__ FV) {
-  extern __shared__ float4 smem4[];
-  float *sF = reinterpret_cast<float *>(smem4);
-  float *sU = sF + J * RT;
-  const int c0 = blockIdx.y * RT;
-  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wave = t >> 6;
-  for (int64_t e = t; e < J * RT; e += nt) sF[e] = 0.0f;
-  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const int64_t r0 = (int64_t)c * kChunkRows;
-    const int n = (int)((S - r0) < kChunkRows ? (S - r0) : kChunkRows);
-    __syncthreads();
-    for (int q = t; q < n; q += nt) {
-      const int64_t i = r0 + q;
-      float u[RT];
-      if constexpr (SMOOTH) {
-        const int64_t k = rowsubj[i];
-        const float4 *c4 = reinterpret_cast<const float4 *>(C + i * kLMax);
-        const float4 ca = c4[0], cb = c4[1];
-        const float cr[kLMax] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
-#pragma unroll
-        for (int r = 0; r < RT; ++r) u[r] = 0.0f;
-#pragma unroll
-        for (int a = 0; a < kLMax; ++a) {
-          if (a < l) {
-            const float *mr = M + (k * l + a) * R + c0;
-#pragma unroll
-            for (int r = 0; r < RT; ++r)
-              if (c0 + r < R) u[r] += cr[a] * mr[r];
-          }
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < RT; ++r) u[r] = (c0 + r < R) ? M[i * R + c0 + r] : 0.0f;
-      }
-#pragma unroll
-      for (int r = 0; r < RT; ++r) sU[q * RT + r] = u[r];
-    }
-    __syncthreads();
-    const int s0 = wsplit[c * 9 + wave], s1 = wsplit[c * 9 + wave + 1];
-    const int per = (s1 - s0 + 63) >> 6;
-    const int a = s0 + lane * per;
-    const int b = a + per < s1 ? a + per : s1;
-    float acc[RT], head[RT];
-#pragma unroll
-    for (int r = 0; r < RT; ++r) {
-      acc[r] = 0.0f;
-      head[r] = 0.0f;
-    }
-    int cur = -1, hkey = -1, nseg = 0;
-    for (int e = a; e < b; ++e) {
-      const uint32_t key = pkey[e];
-      const int j = (int)(key >> 16);
-      const float x = pval[e];
-      const float *ur = sU + (key & 0xffffu) * RT;
-      if (j != cur) {
-        if (nseg == 1) {
-          hkey = cur;
-#pragma unroll
-          for (int r = 0; r < RT; ++r) head[r] = acc[r];
-        } else if (nseg > 1) {
-          // a segment that starts and ends inside this lane's run: no other lane has it
-#pragma unroll
-          for (int r = 0; r < RT; ++r) sF[cur * RT + r] += acc[r];
-        }
-        cur = j;
-        ++nseg;
-#pragma unroll
-        for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
-      }
-#pragma unroll
-      for (int r = 0; r < RT; ++r) acc[r] += x * ur[r];
-    }
-    // tail segment (cur, acc); the first key of this lane's run is hkey (several segments) or cur
-    const int first = nseg > 1 ? hkey : cur;
-    // inclusive segmented scan of the tails over lanes (keys are non-decreasing along lanes)
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int kprev = __shfl_up(cur, d, 64);
-      float vprev[RT];
-#pragma unroll
-      for (int r = 0; r < RT; ++r) vprev[r] = __shfl_up(acc[r], d, 64);
-      if (lane >= d && cur >= 0 && kprev == cur) {
-#pragma unroll
-        for (int r = 0; r < RT; ++r) acc[r] += vprev[r];
-      }
-    }
-    const int knext = __shfl_down(first, 1, 64);
-    const int kprev1 = __shfl_up(cur, 1, 64);
-    float carry[RT];
-#pragma unroll
-    for (int r = 0; r < RT; ++r) carry[r] = __shfl_up(acc[r], 1, 64);
-    if (nseg > 1) {
-      // head segment: complete once the previous lane's tail (if same feature) is added
-      const bool join = lane > 0 && kprev1 == hkey;
-#pragma unroll
-      for (int r = 0; r < RT; ++r) sF[hkey * RT + r] += head[r] + (join ? carry[r] : 0.0f);
-    }
-    if (cur >= 0) {
-      // tail: flushed unless the next lane's run starts with the same feature
-      const bool cont = lane < 63 && knext == cur;
-      if (!cont) {
-#pragma unroll
-        for (int r = 0; r < RT; ++r) sF[cur * RT + r] += acc[r];
-      }
-    }
-  }
-  __syncthreads();
-  for (int64_t e = t; e < J * RT; e += nt) {
-    const int64_t j = e / RT;
-    const int r = (int)(e - j * RT);
-    const float v = sF[e];
-    if (c0 + r < R && v != 0.0f) unsafeAtomicAdd(&FV[j * R + c0 + r], v);
-  }
-}
-
-// Unchunked fallback (features >= 2^16): global atomics per nonzero.
-template <int RT, bool SMOOTH>
-__global__ void __launch_bounds__(256)
-    k_pass2(const WaveEntry *__restrict__ waves, int n_waves, const int32_t *__restrict__ order,
-            const int32_t *__restrict__ subj, const int32_t *__restrict__ row,
-            const int32_t *__restrict__ col, const float *__restrict__ val,
-            const float *__restrict__ C, const float *__restrict__ M, int64_t J, int R, int l,
-            float *__restrict__ FV) {
-  const int lane = threadIdx.x & 63;
-  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wv >= n_waves) return;
-  const int c0 = blockIdx.y * RT;
-  const WaveEntry we = waves[wv];
-  const int lg = we.lg_count & 255, cnt = we.lg_count >> 8;
-  const int G = 1 << lg, sidx = lane >> lg, sub = lane & (G - 1);
-  if (sidx >= cnt) return;
-  const int k = order[we.first + sidx];
-  const int r0 = subj[k], r1 = subj[k + 1];
-  for (int i = r0 + sub; i < r1; i += G) {
-    float u[RT];
-    if constexpr (SMOOTH) {
-#pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        float s = 0.0f;
-        for (int a = 0; a < l; ++a)
-          if (c0 + r < R) s += C[(int64_t)i * kLMax + a] * M[((int64_t)k * l + a) * R + c0 + r];
-        u[r] = s;
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < RT; ++r) u[r] = (c0 + r < R) ? M[(int64_t)i * R + c0 + r] : 0.0f;
-    }
-    for (int e = row[i]; e < row[i + 1]; ++e) {
-      const float x = val[e];
-      const int64_t j = col[e];
-#pragma unroll
-      for (int r = 0; r < RT; ++r)
-        if (c0 + r < R) unsafeAtomicAdd(&FV[j * R + c0 + r], x * u[r]);
-    }
-  }
-}
-
-// ======================================================================= mode V
-template <int R>
-__global__ void __launch_bounds__(256)
-    k_mode_V_prep(double *small, ModeParams *modes, FitScalars *sc) {
-  mode_prepare<R>(small + kHtH * R * R, small + kWtW * R * R, &modes[2], sc);
-}
-
+// ======================================================================= mode V (+ FIT)
+// Every block: W^T W and Psi from the Gram partials, G_V = H^TH * W^TW, rho, Cholesky; then one
+// V row per thread (inner ADMM, l1 prox), the padded V tile copy for the next pass 1, per-block
+// sums of <F_V, V>, |V|_1 and zeros, and the block's share of V^T V on the matrix cores. The last
+// block to finish adds the block results in block order and evaluates
+//   FIT = 1 - (|X|^2 - 2 <F_V, V> + <Psi, V^T V>) / |X|^2   (Section "Evaluation Metrics").
 template <int R>
 __global__ void __launch_bounds__(256)
     k_v_admm(int64_t J, const float *__restrict__ FV, float *__restrict__ V,
              float *__restrict__ DV, float *__restrict__ Vp, int rt, int rtp,
-             const ModeParams *__restrict__ modes, int kind, double lam, int iters,
-             double *__restrict__ vpart) {
-  __shared__ double sL[R * R];
-  __shared__ double sred[3][256];
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = modes[2].L[e];
-  __syncthreads();
-  const double rho = modes[2].rho;
+             const double *__restrict__ partW, const double *__restrict__ partM, int nbp,
+             double *small, FitScalars *sc, int kind, double lam, int iters,
+             double *__restrict__ vpart, double *__restrict__ vtvpart,
+             const double *__restrict__ wl1part, int nwb, const float *__restrict__ H,
+             double normX2, int proxH, double lamH, int proxW, double lamW, int32_t *counter) {
+  constexpr int RR = R * R;
+  constexpr int NT = (R + 15) / 16;
+  constexpr int RP = NT * 16;
+  __shared__ double sW[RR];
+  __shared__ double sPsi[RR];
+  __shared__ double sL[RR];
+  __shared__ double sacc[RP * RP];
+  __shared__ double scratch[256];
+  __shared__ double red[3][256];
+  __shared__ double srho;
+  __shared__ int sflag;
+  __shared__ int last;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  block_reduce_parts<RR>(partW, nbp, sW, scratch);
+  block_reduce_parts<RR>(partM, nbp, sPsi, scratch);
+  if (blockIdx.x == 0) {
+    for (int e = t; e < RR; e += blockDim.x) {
+      small[kWtW * RR + e] = sW[e];
+      small[kPsi * RR + e] = sPsi[e];
+    }
+  }
+  const bool ok = build_system<R>(small + kHtH * RR, sW, sL, &srho, &sflag);
+  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->iter);
+  const double rho = srho;
+  const int64_t j0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t j = j0 + t;
   double dot = 0.0, l1 = 0.0, zeros = 0.0;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < J;
-       j += (int64_t)gridDim.x * blockDim.x) {
+  if (j < J) {
     double F[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) F[c] = FV[j * R + c];
@@ -899,60 +1002,108 @@ __global__ void __launch_bounds__(256)
       zeros += Zb[c] == 0.0f ? 1.0 : 0.0;
     }
   }
-  sred[0][threadIdx.x] = dot;
-  sred[1][threadIdx.x] = l1;
-  sred[2][threadIdx.x] = zeros;
-  __syncthreads();
-  if (threadIdx.x < 3) {
-    double s = 0.0;
-    for (int i = 0; i < 256; ++i) s += sred[threadIdx.x][i];
-    vpart[blockIdx.x * 4 + threadIdx.x] = s;
-  }
-}
-
-// ======================================================================= finalize
-template <int R>
-__global__ void __launch_bounds__(256)
-    k_finalize(const double *__restrict__ vpart, int nvb, const double *__restrict__ wl1part,
-               int nwb, double *small, FitScalars *sc, const float *__restrict__ H, double normX2,
-               int64_t J, int proxH, double lamH, int proxW, double lamW, int proxV,
-               double lamV) {
-  __shared__ double red[5][256];
-  const int t = threadIdx.x;
-  double dot = 0.0, l1 = 0.0, zeros = 0.0, wl1 = 0.0, quad = 0.0;
-  for (int b = t; b < nvb; b += blockDim.x) {
-    dot += vpart[b * 4 + 0];
-    l1 += vpart[b * 4 + 1];
-    zeros += vpart[b * 4 + 2];
-  }
-  for (int b = t; b < nwb; b += blockDim.x) wl1 += wl1part[b];
-  for (int e = t; e < R * R; e += blockDim.x)
-    quad += small[kPsi * R * R + e] * small[kVtV * R * R + e];
   red[0][t] = dot;
   red[1][t] = l1;
   red[2][t] = zeros;
-  red[3][t] = wl1;
-  red[4][t] = quad;
+  for (int e = t; e < RP * RP; e += blockDim.x) sacc[e] = 0.0;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (t < w)
-      for (int q = 0; q < 5; ++q) red[q][t] += red[q][t + w];
+      for (int q = 0; q < 3; ++q) red[q][t] += red[q][t + w];
+    __syncthreads();
+  }
+  if (t < 3) vpart[blockIdx.x * 4 + t] = red[t][0];
+  // this block's rows of V^T V: 4 waves x 64 rows, 16 MFMA steps each, loads first
+  {
+    const int m = lane & 15, kk = lane >> 4;
+    dbl4_t acc[NT][NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int q = 0; q < NT; ++q) acc[i][q] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+    double av[16][NT];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int64_t rr = j0 + wave * 64 + 4 * s + kk;
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int c = q * 16 + m;
+        av[s][q] = (rr < J && c < R) ? (double)V[rr * R + c] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+#pragma unroll
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+          acc[i][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][i], av[s][q], acc[i][q], 0, 0, 0);
+    for (int w = 0; w < 4; ++w) {
+      if (wave == w) {
+#pragma unroll
+        for (int i = 0; i < NT; ++i)
+#pragma unroll
+          for (int q = 0; q < NT; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int ii = i * 16 + 4 * v + (lane >> 4), jj = q * 16 + (lane & 15);
+              sacc[ii * RP + jj] += acc[i][q][v];
+            }
+      }
+      __syncthreads();
+    }
+    for (int e = t; e < RR; e += blockDim.x)
+      vtvpart[(int64_t)blockIdx.x * RR + e] = sacc[(e / R) * RP + e % R];
+  }
+  __threadfence();
+  __syncthreads();
+  if (t == 0) last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int nb = gridDim.x;
+  // V^T V in block order
+  for (int e = t; e < RR; e += blockDim.x) {
+    double v = 0.0;
+    for (int b = 0; b < nb; ++b)
+      v += __hip_atomic_load(&vtvpart[(int64_t)b * RR + e], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    small[kVtV * RR + e] = v;
+  }
+  __syncthreads();
+  double quad = 0.0, wl1 = 0.0;
+  for (int e = t; e < RR; e += blockDim.x) quad += sPsi[e] * small[kVtV * RR + e];
+  for (int b = t; b < nwb; b += blockDim.x) wl1 += wl1part[b];
+  dot = l1 = zeros = 0.0;
+  for (int b = t; b < nb; b += blockDim.x) {
+    dot += __hip_atomic_load(&vpart[b * 4 + 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    l1 += __hip_atomic_load(&vpart[b * 4 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    zeros += __hip_atomic_load(&vpart[b * 4 + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  red[0][t] = dot;
+  red[1][t] = l1;
+  red[2][t] = zeros;
+  scratch[t] = quad;
+  sacc[t] = wl1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      for (int q = 0; q < 3; ++q) red[q][t] += red[q][t + w];
+      scratch[t] += scratch[t + w];
+      sacc[t] += sacc[t + w];
+    }
     __syncthreads();
   }
   if (t == 0) {
-    dot = red[0][0];
-    l1 = red[1][0];
-    zeros = red[2][0];
-    wl1 = red[3][0];
-    quad = red[4][0];
     double hl1 = 0.0;
-    for (int e = 0; e < R * R; ++e) hl1 += fabs((double)H[e]);
-    const double resid = normX2 - 2.0 * dot + quad;
+    for (int e = 0; e < RR; ++e) hl1 += fabs((double)H[e]);
+    const double resid = normX2 - 2.0 * red[0][0] + scratch[0];
     const double fit = normX2 > 0.0 ? 1.0 - resid / normX2 : 0.0;
-    auto pen = [](int kind, double lam, double a) {
-      return (kind == COPA_PROX_L1 || kind == COPA_PROX_NONNEG_L1) ? lam * a : 0.0;
+    auto pen = [](int k, double la, double v) {
+      return (k == COPA_PROX_L1 || k == COPA_PROX_NONNEG_L1) ? la * v : 0.0;
     };
-    const double obj = 0.5 * resid + pen(proxV, lamV, l1) + pen(proxW, lamW, wl1) +
+    const double obj = 0.5 * resid + pen(kind, lam, red[1][0]) + pen(proxW, lamW, sacc[0]) +
                        pen(proxH, lamH, hl1);
     const int it = sc->iter;
     if (!isfinite(fit) || !isfinite(obj)) atomicMin(&sc->fail_iter, it);
@@ -962,11 +1113,22 @@ __global__ void __launch_bounds__(256)
     }
     sc->last_fit = fit;
     sc->last_obj = obj;
-    sc->last_sparsity = J > 0 ? zeros / ((double)J * R) : 0.0;
+    sc->last_sparsity = J > 0 ? red[2][0] / ((double)J * R) : 0.0;
     sc->rank_deficient = sc->rank_def_cur;
     sc->rank_def_cur = 0;
     sc->iter = it + 1;
+    *counter = 0;
   }
+}
+
+// W^T W and V^T V of the starting point (copa_fit entry)
+template <int R>
+__global__ void __launch_bounds__(256)
+    k_init_small(const double *__restrict__ partW, const double *__restrict__ partV, int nb,
+                 double *small) {
+  __shared__ double scratch[256];
+  block_reduce_parts<R * R>(partW, nb, small + kWtW * R * R, scratch);
+  block_reduce_parts<R * R>(partV, nb, small + kVtV * R * R, scratch);
 }
 
 __global__ void k_zero(float *x, int64_t n) {
@@ -1031,7 +1193,7 @@ static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
 template <int RT>
 static void launch_pass2_rt(copa_plan *p, hipStream_t s) {
   if (p->p2c) {
-    dim3 grid((unsigned)std::min(p->nchunks, std::max(1, p->n_cu)), (unsigned)p->tiles.nt),
+    dim3 grid((unsigned)std::min(p->nchunks, 2 * std::max(1, p->n_cu)), (unsigned)p->tiles.nt),
         block(512);
     size_t lds = ((size_t)p->J * RT + (size_t)kChunkRows * RT) * sizeof(float);
     if (p->l > 0)
@@ -1070,19 +1232,18 @@ static void launch_pass2_rt(copa_plan *p, hipStream_t s) {
 
 template <int R>
 static void gram(copa_plan *p, const float *A, const float *B, int64_t rows, const float *W,
-                 int wsel, int slot, double *dst, hipStream_t s) {
-  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGramBlocks, (rows + 1023) / 1024));
-  k_rows_gram<R><<<nb, 256, 0, s>>>(A, B, rows, W, wsel,
-                                             p->slot_rows > 0 ? p->slot_rows : 1, p->rowsubj,
-                                             p->gpart, dst, p->gcount + slot);
+                 int wsel, double *part, const float *A2, int64_t rows2, double *part2,
+                 hipStream_t s) {
+  dim3 grid(kGramBlocks, A2 ? 2 : 1);
+  k_rows_gram<R><<<grid, 1024, 0, s>>>(A, B, rows, W, wsel,
+                                       p->slot_rows > 0 ? p->slot_rows : 1, p->rowsubj, part, A2,
+                                       rows2, part2);
 }
 
-const char *const kernel_names[kNumKernels] = {
-    "pass1", "procrustes", "gram_FH", "mode_H", "w_admm", "gram_W", "gram_M", "zero_FV",
-    "pass2", "mode_V_prep", "v_admm", "gram_V", "finalize"};
+const char *const kernel_names[kNumKernels] = {"pass1",  "procrustes", "gram_FH", "mode_H",
+                                               "w_admm", "gram_WM",    "pass2",   "v_admm"};
 
-enum { kidPass1, kidProcrustes, kidGramFH, kidModeH, kidWadmm, kidGramW, kidGramM, kidZeroFV,
-       kidPass2, kidModeVPrep, kidVadmm, kidGramV, kidFinalize };
+enum { kidPass1, kidProcrustes, kidGramFH, kidModeH, kidWadmm, kidGramWM, kidPass2, kidVadmm };
 
 // Records a HIP event pair around one launch when the plan's timing is on.
 template <typename F>
@@ -1114,21 +1275,33 @@ template <int R>
 static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   const copa_options &o = p->opt;
   const int64_t K = p->K;
+  constexpr int RR = R * R;
   timed(p, s, kidPass1, [&] { RT_SWITCH(p->tiles.rt, launch_pass1_rt, p, st->V, s); });
   if (K > 0)
     timed(p, s, kidProcrustes, [&] {
+      if constexpr (R <= 16) {
+        if (p->l > 0) {
+          k_procrustes_s<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
+              K, p->l, p->rk, p->T, p->Q, st->H, st->W, o.rank_rtol, &p->scal->rank_def_cur);
+          return;
+        }
+      }
       k_procrustes<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
           K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W, o.rank_rtol,
           &p->scal->rank_def_cur);
+      if (p->n_big > 0)
+        k_procrustes_wave<R><<<(unsigned)p->n_big, 64, 0, s>>>(
+            p->big_list, p->n_big, p->subj, p->T, p->Q, st->H, st->W, o.rank_rtol,
+            &p->scal->rank_def_cur);
     });
-  timed(p, s, kidGramFH,
-        [&] {
-          gram<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, 0,
-                  p->small + kFH * R * R, s);
-        });
+  timed(p, s, kidGramFH, [&] {
+    gram<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, p->gpart, nullptr, 0,
+            nullptr, s);
+  });
   timed(p, s, kidModeH, [&] {
-    k_mode_H<R><<<1, 256, 0, s>>>(p->small, p->modes, p->scal, st->H, st->D_H, o.prox_H,
-                                  o.lambda_H, o.inner_iters);
+    k_mode_H<R><<<1, 256, 0, s>>>(p->gpart, kGramBlocks, p->small, p->modes, p->scal, st->H,
+                                  st->D_H, o.prox_H, o.lambda_H, o.inner_iters, p->FV,
+                                  p->J * R);
   });
   const unsigned nwb = (unsigned)std::max<int64_t>(1, (K + 63) / 64);
   timed(p, s, kidWadmm, [&] {
@@ -1136,42 +1309,32 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
                                    st->D_W, p->FW, p->modes, o.prox_W, o.lambda_W,
                                    o.inner_iters, p->wpart);
   });
-  timed(p, s, kidGramW,
-        [&] { gram<R>(p, st->W, st->W, K, nullptr, 0, 1, p->small + kWtW * R * R, s); });
-  timed(p, s, kidGramM, [&] {
-    gram<R>(p, p->M, p->M, p->rows_total, nullptr, 0, 2, p->small + kPsi * R * R, s);
+  timed(p, s, kidGramWM, [&] {
+    gram<R>(p, st->W, st->W, K, nullptr, 0, p->gpart + (size_t)kGramBlocks * RR, p->M,
+            p->rows_total, p->gpart + (size_t)2 * kGramBlocks * RR, s);
   });
-  timed(p, s, kidZeroFV, [&] {
-      k_zero<<<(unsigned)std::min<int64_t>(1024, (p->J * R + 255) / 256), 256, 0, s>>>(
-          p->FV, p->J * R);
-    });
   timed(p, s, kidPass2, [&] { RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s); });
-  timed(p, s, kidModeVPrep, [&] {
-    k_mode_V_prep<R><<<1, 256, 0, s>>>(p->small, p->modes, p->scal);
-  });
   timed(p, s, kidVadmm, [&] {
-    k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt,
-                                             (p->tiles.rt + 3) & ~3, p->modes, o.prox_V,
-                                             o.lambda_V, o.inner_iters, p->vpart);
-  });
-  timed(p, s, kidGramV,
-        [&] { gram<R>(p, st->V, st->V, p->J, nullptr, 0, 3, p->small + kVtV * R * R, s); });
-  timed(p, s, kidFinalize, [&] {
-    k_finalize<R><<<1, 256, 0, s>>>(p->vpart, p->n_vblocks, p->wpart, (int)nwb, p->small,
-                                   p->scal, st->H, p->normX2, p->J,
-                                    o.prox_H, o.lambda_H, o.prox_W, o.lambda_W, o.prox_V,
-                                    o.lambda_V);
+    k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(
+        p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, (p->tiles.rt + 3) & ~3,
+        p->gpart + (size_t)kGramBlocks * RR, p->gpart + (size_t)2 * kGramBlocks * RR,
+        kGramBlocks, p->small, p->scal, o.prox_V, o.lambda_V, o.inner_iters, p->vpart,
+        p->gpart + (size_t)3 * kGramBlocks * RR, p->wpart, (int)nwb, st->H, p->normX2,
+        o.prox_H, o.lambda_H, o.prox_W, o.lambda_W, p->gcount + 6);
   });
 }
 
 template <int R>
 static void init_grams_r(copa_plan *p, const copa_state *st, hipStream_t s) {
+  constexpr int RR = R * R;
   k_reset_scalars<<<1, 64, 0, s>>>(p->scal);
   if (p->J > 0)
     k_pad_V<R><<<(unsigned)((p->J * R + 255) / 256), 256, 0, s>>>(
         st->V, p->Vp, p->J, p->tiles.rt, (p->tiles.rt + 3) & ~3);
-  gram<R>(p, st->W, st->W, p->K, nullptr, 0, 4, p->small + kWtW * R * R, s);
-  gram<R>(p, st->V, st->V, p->J, nullptr, 0, 5, p->small + kVtV * R * R, s);
+  gram<R>(p, st->W, st->W, p->K, nullptr, 0, p->gpart, st->V, p->J,
+          p->gpart + (size_t)kGramBlocks * RR, s);
+  k_init_small<R><<<1, 256, 0, s>>>(p->gpart, p->gpart + (size_t)kGramBlocks * RR, kGramBlocks,
+                                    p->small);
 }
 
 copa_status launch_iteration(copa_plan *p, const copa_state *st, hipStream_t s) {

@@ -1,0 +1,330 @@
+// Kernels shared by the fit (copa_iter.hip) and the adjoint (copa_grad.hip): the row-Gram
+// contraction on the matrix cores and the feature-sorted streaming scatter F += X^T U.
+#pragma once
+
+#include "copa_common.h"
+
+namespace copa {
+
+// ======================================================================= row Gram reductions
+// part[block] = sum over the block's rows of A_row^T (B_row * w_subj(row)) (R x R, FP64): a dense
+// contraction over the long row dimension on the matrix cores. v_mfma_f64_16x16x4f64 takes 4 rows
+// per instruction, lane l holding A[row0 + l/16][16 ti + l%16] and B[row0 + l/16][16 tj + l%16];
+// each wave loads 8 such steps (32 rows) before issuing their 8 instructions. blockIdx.y == 1
+// computes a second, unscaled Gram A2^T A2 into part2 in the same launch.
+// wsel: 0 = no scaling; 1 = scale B by W[row / slot_rows]; 2 = scale by W[rowsubj[row]].
+typedef double dbl4_t __attribute__((ext_vector_type(4)));
+
+template <int R>
+__global__ void __launch_bounds__(1024)
+    k_rows_gram(const float *__restrict__ A, const float *__restrict__ B, int64_t rows,
+                const float *__restrict__ W, int wsel, int slot_rows,
+                const int32_t *__restrict__ rowsubj, double *__restrict__ part,
+                const float *__restrict__ A2, int64_t rows2, double *__restrict__ part2) {
+  constexpr int NT = (R + 15) / 16;
+  constexpr int RP = NT * 16;
+  constexpr int RR = R * R;
+  constexpr int BATCH = 16;
+  __shared__ double sacc[RP * RP];
+  if (blockIdx.y == 1) {
+    A = A2;
+    B = A2;
+    rows = rows2;
+    wsel = 0;
+    part = part2;
+  }
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
+  const int m = lane & 15, kk = lane >> 4;
+  for (int e = t; e < RP * RP; e += blockDim.x) sacc[e] = 0.0;
+  const int64_t units = (rows + 4 * BATCH - 1) / (4 * BATCH);
+  const int64_t upb = (units + gridDim.x - 1) / gridDim.x;
+  const int64_t u0 = blockIdx.x * upb;
+  const int64_t u1 = u0 + upb < units ? u0 + upb : units;
+  dbl4_t acc[NT][NT], acc2[NT][NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      acc[i][j] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+      acc2[i][j] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+    }
+  for (int64_t u = u0 + wave; u < u1; u += nw) {
+    // loads from clamped (always valid) addresses, masked afterwards, so that they issue together
+    double av[BATCH][NT], bv[BATCH][NT];
+#pragma unroll
+    for (int s = 0; s < BATCH; ++s) {
+      const int64_t rr = u * (4 * BATCH) + 4 * s + kk;
+      const bool ok = rr < rows;
+      const int64_t rc = ok ? rr : rows - 1;
+      const int64_t wrow = wsel == 1 ? (int64_t)((uint32_t)rc / (uint32_t)slot_rows)
+                                     : (wsel == 2 ? (int64_t)rowsubj[rc] : 0);
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int c = q * 16 + m;
+        const bool in = ok && c < R;
+        const int cc = c < R ? c : R - 1;
+        const float a = A[rc * R + cc];
+        const float b = B[rc * R + cc];
+        const float w = wsel ? W[wrow * R + cc] : 1.0f;
+        av[s][q] = in ? (double)a : 0.0;
+        bv[s][q] = in ? (double)b * (double)w : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < BATCH; s += 2)
+#pragma unroll
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][i], bv[s][j], acc[i][j], 0, 0, 0);
+          acc2[i][j] =
+              __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1][i], bv[s + 1][j], acc2[i][j], 0, 0, 0);
+        }
+  }
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] += acc2[i][j];
+  __syncthreads();
+  // D[ii][jj] of a 16 x 16 FP64 block: lane jj + 16 (ii % 4), element ii / 4; waves add in order
+  for (int w = 0; w < nw; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ii = i * 16 + 4 * v + (lane >> 4), jj = j * 16 + (lane & 15);
+            sacc[ii * RP + jj] += acc[i][j][v];
+          }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < RR; e += blockDim.x)
+    part[(int64_t)blockIdx.x * RR + e] = sacc[(e / R) * RP + e % R];
+}
+
+// dst[e] = sum_b part[b * RR + e] over b = 0..nb-1 in a fixed order, using the whole block
+// (scratch: blockDim.x doubles of LDS). dst may be LDS or global memory.
+template <int RR>
+__device__ void block_reduce_parts(const double *__restrict__ part, int nb, double *dst,
+                                   double *scratch) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  if (RR <= nt) {
+    const int G = nt / RR;
+    const int e = t % RR, g = t / RR;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (g < G) {
+      int b = g;
+      for (; b + 7 * G < nb; b += 8 * G) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += part[(int64_t)(b + u * G) * RR + e];
+      }
+      for (; b < nb; b += G) s[0] += part[(int64_t)b * RR + e];
+    }
+    scratch[t] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    __syncthreads();
+    if (t < RR) {
+      double v = 0.0;
+      for (int q = 0; q < G; ++q) v += scratch[q * RR + t];
+      dst[t] = v;
+    }
+    __syncthreads();
+  } else {
+    for (int e = t; e < RR; e += nt) {
+      double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int b = 0;
+      for (; b + 8 <= nb; b += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += part[(int64_t)(b + u) * RR + e];
+      }
+      for (; b < nb; ++b) s[0] += part[(int64_t)b * RR + e];
+      dst[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    }
+    __syncthreads();
+  }
+}
+
+// ======================================================================= streaming pass 2
+// F_V(j,:) += x_ij * u_i with u_i = c_i M_k (smoothed: basis row times Q_k H S_k) or the M row of
+// visit i (plain). Chunked form: for every block of kChunkRows visit rows the plan stores the
+// chunk's nonzeros sorted by feature (key = feature << 16 | row in chunk) and 9 split points
+// that cut the sorted list into 8 slices on feature boundaries, one per wave. A block puts the
+// chunk's u rows in LDS; each lane sums a contiguous run of its wave's slice feature by feature;
+// a segmented scan over the lanes joins runs that share a feature, so every feature is added to
+// the block's LDS copy of F_V by exactly one lane - no LDS atomics. The block's F_V tile goes to
+// the global F_V with one atomic add per entry at the end.
+template <int RT, bool SMOOTH>
+__global__ void __launch_bounds__(512)
+    k_pass2c(int nchunks, int64_t S, const int32_t *__restrict__ wsplit,
+             const uint32_t *__restrict__ pkey, const float *__restrict__ pval,
+             const int32_t *__restrict__ rowsubj, const float *__restrict__ C,
+             const float *__restrict__ M, int64_t J, int R, int l, float *__restrict__ FV) {
+  extern __shared__ float4 smem4[];
+  float *sF = reinterpret_cast<float *>(smem4);
+  float *sU = sF + J * RT;
+  const int c0 = blockIdx.y * RT;
+  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wave = t >> 6;
+  for (int64_t e = t; e < J * RT; e += nt) sF[e] = 0.0f;
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int64_t r0 = (int64_t)c * kChunkRows;
+    const int n = (int)((S - r0) < kChunkRows ? (S - r0) : kChunkRows);
+    __syncthreads();
+    for (int q = t; q < n; q += nt) {
+      const int64_t i = r0 + q;
+      float u[RT];
+      if constexpr (SMOOTH) {
+        const int64_t k = rowsubj[i];
+        const float4 *c4 = reinterpret_cast<const float4 *>(C + i * kLMax);
+        const float4 ca = c4[0], cb = c4[1];
+        const float cr[kLMax] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+#pragma unroll
+        for (int r = 0; r < RT; ++r) u[r] = 0.0f;
+        // basis columns at or past l are zero: clamp the M row and column instead of branching
+#pragma unroll
+        for (int a = 0; a < kLMax; ++a) {
+          const float *mr = M + (k * l + (a < l ? a : l - 1)) * R;
+#pragma unroll
+          for (int r = 0; r < RT; ++r) u[r] += cr[a] * mr[c0 + r < R ? c0 + r : R - 1];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) u[r] = M[i * R + (c0 + r < R ? c0 + r : R - 1)];
+      }
+#pragma unroll
+      for (int r = 0; r < RT; ++r) sU[q * RT + r] = u[r];
+    }
+    __syncthreads();
+    const int s0 = wsplit[c * 9 + wave], s1 = wsplit[c * 9 + wave + 1];
+    const int per = (s1 - s0 + 63) >> 6;
+    const int a = s0 + lane * per;
+    const int b = a + per < s1 ? a + per : s1;
+    float acc[RT], head[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      acc[r] = 0.0f;
+      head[r] = 0.0f;
+    }
+    int cur = -1, hkey = -1, nseg = 0;
+    for (int eb = a; eb < b; eb += 8) {
+      uint32_t kv[8];
+      float xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int ec = eb + u < b ? eb + u : a;
+        kv[u] = pkey[ec];
+        xv[u] = pval[ec];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+      if (eb + u >= b) break;
+      const uint32_t key = kv[u];
+      const int j = (int)(key >> 16);
+      const float x = xv[u];
+      const float *ur = sU + (key & 0xffffu) * RT;
+      if (j != cur) {
+        if (nseg == 1) {
+          hkey = cur;
+#pragma unroll
+          for (int r = 0; r < RT; ++r) head[r] = acc[r];
+        } else if (nseg > 1) {
+          // a segment that starts and ends inside this lane's run: no other lane has it
+#pragma unroll
+          for (int r = 0; r < RT; ++r) sF[cur * RT + r] += acc[r];
+        }
+        cur = j;
+        ++nseg;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
+      }
+#pragma unroll
+      for (int r = 0; r < RT; ++r) acc[r] += x * ur[r];
+      }
+    }
+    // tail segment (cur, acc); the first key of this lane's run is hkey (several segments) or cur
+    const int first = nseg > 1 ? hkey : cur;
+    // inclusive segmented scan of the tails over lanes (keys are non-decreasing along lanes)
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int kprev = __shfl_up(cur, d, 64);
+      float vprev[RT];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) vprev[r] = __shfl_up(acc[r], d, 64);
+      if (lane >= d && cur >= 0 && kprev == cur) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[r] += vprev[r];
+      }
+    }
+    const int knext = __shfl_down(first, 1, 64);
+    const int kprev1 = __shfl_up(cur, 1, 64);
+    float carry[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) carry[r] = __shfl_up(acc[r], 1, 64);
+    if (nseg > 1) {
+      // head segment: complete once the previous lane's tail (if same feature) is added
+      const bool join = lane > 0 && kprev1 == hkey;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) sF[hkey * RT + r] += head[r] + (join ? carry[r] : 0.0f);
+    }
+    if (cur >= 0) {
+      // tail: flushed unless the next lane's run starts with the same feature
+      const bool cont = lane < 63 && knext == cur;
+      if (!cont) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) sF[cur * RT + r] += acc[r];
+      }
+    }
+  }
+  __syncthreads();
+  for (int64_t e = t; e < J * RT; e += nt) {
+    const int64_t j = e / RT;
+    const int r = (int)(e - j * RT);
+    const float v = sF[e];
+    if (c0 + r < R && v != 0.0f) unsafeAtomicAdd(&FV[j * R + c0 + r], v);
+  }
+}
+
+// Unchunked fallback (features >= 2^16): global atomics per nonzero.
+template <int RT, bool SMOOTH>
+__global__ void __launch_bounds__(256)
+    k_pass2(const WaveEntry *__restrict__ waves, int n_waves, const int32_t *__restrict__ order,
+            const int32_t *__restrict__ subj, const int32_t *__restrict__ row,
+            const int32_t *__restrict__ col, const float *__restrict__ val,
+            const float *__restrict__ C, const float *__restrict__ M, int64_t J, int R, int l,
+            float *__restrict__ FV) {
+  const int lane = threadIdx.x & 63;
+  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wv >= n_waves) return;
+  const int c0 = blockIdx.y * RT;
+  const WaveEntry we = waves[wv];
+  const int lg = we.lg_count & 255, cnt = we.lg_count >> 8;
+  const int G = 1 << lg, sidx = lane >> lg, sub = lane & (G - 1);
+  if (sidx >= cnt) return;
+  const int k = order[we.first + sidx];
+  const int r0 = subj[k], r1 = subj[k + 1];
+  for (int i = r0 + sub; i < r1; i += G) {
+    float u[RT];
+    if constexpr (SMOOTH) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        float s = 0.0f;
+        for (int a = 0; a < l; ++a)
+          if (c0 + r < R) s += C[(int64_t)i * kLMax + a] * M[((int64_t)k * l + a) * R + c0 + r];
+        u[r] = s;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) u[r] = (c0 + r < R) ? M[(int64_t)i * R + c0 + r] : 0.0f;
+    }
+    for (int e = row[i]; e < row[i + 1]; ++e) {
+      const float x = val[e];
+      const int64_t j = col[e];
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        if (c0 + r < R) unsafeAtomicAdd(&FV[j * R + c0 + r], x * u[r]);
+    }
+  }
+}
+
+}  // namespace copa

@@ -512,7 +512,7 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
     COPA_TRY(dalloc(&p->Vp, (size_t)p->tiles.nt * p->J * rtp));
     COPA_HIP(hipMemsetAsync(p->Vp, 0, (size_t)p->tiles.nt * p->J * rtp * sizeof(float), s));
   }
-  COPA_TRY(dalloc(&p->gpart, (size_t)kGramBlocks * R * R));
+  COPA_TRY(dalloc(&p->gpart, (size_t)4 * std::max<int64_t>(kGramBlocks, (p->J + 255) / 256) * R * R));
   COPA_TRY(dalloc(&p->gcount, 8));
   COPA_HIP(hipMemsetAsync(p->gcount, 0, 8 * sizeof(int32_t), s));
   COPA_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
@@ -521,7 +521,7 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   p->p2c = p->J <= 65536 && nnz > 0 &&
            ((int64_t)p->J * p->tiles.rt + (int64_t)kChunkRows * p->tiles.rt) * 4 <= p->lds_limit;
   if (p->p2c) COPA_TRY(build_sorted_chunks(X, p, s));
-  p->n_vblocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (p->J + 255) / 256));
+  p->n_vblocks = (int)std::max<int64_t>(1, (p->J + 255) / 256);
   COPA_TRY(dalloc(&p->vpart, (size_t)p->n_vblocks * 4));
   COPA_TRY(dalloc(&p->wpart, (size_t)std::max<int64_t>(1, (K + 63) / 64)));
   COPA_TRY(dalloc(&p->small, 8 * R * R));
@@ -547,7 +547,8 @@ static void free_plan(copa_plan *p) {
   void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->C, p->rk, p->order, p->waves,
                   p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->cptr, p->wsplit, p->pkey, p->pval, p->Vp,
                   p->gpart, p->gcount,
-                  p->vpart, p->wpart, p->small, p->modes, p->scal, p->dloss, p->gradbuf};
+                  p->vpart, p->wpart, p->small, p->modes, p->scal, p->dloss, p->gradbuf,
+                  p->lpart};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -622,10 +623,6 @@ copa_status copa_plan_create(const copa_tensor *X, const copa_options *opt, void
   }
   copa_plan *p = new copa_plan();
   copa_status st = build_plan(X, opt, (hipStream_t)stream, p);
-  if (st == COPA_OK && p->n_big > 0) {
-    set_error("unsmoothed subjects with min(I_k, R) > 8 need the wave Procrustes kernel");
-    st = COPA_EUNSUPPORTED;
-  }
   if (st != COPA_OK) {
     (void)hipDeviceSynchronize();
     free_plan(p);

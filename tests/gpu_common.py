@@ -55,3 +55,19 @@ def run_oracle(coh, R, l, iters, seed=0, inner=5, prox=(co.PROX_NONE, co.PROX_NO
 
 def split_rows(coh, X):
     return [X[coh.subj_ptr[k]:coh.subj_ptr[k + 1]] for k in range(coh.K)]
+
+
+def procrustes_condition(coh, R, l, H, W, V, rtol=1e-6):
+    """Per subject: sigma_1 / sigma_r of A_k = X'_k V S_k H^T over the kept singular values (the
+    sensitivity of the polar factor to a relative perturbation of A_k)."""
+    prob = co.build_problem(coh, l)
+    out = []
+    for k, Xh in enumerate(prob.Xh):
+        A = Xh @ V @ np.diag(W[k]) @ H.T
+        s = np.linalg.svd(np.asarray(A), compute_uv=False) if A.size else np.zeros(0)
+        if s.size == 0 or s[0] == 0:
+            out.append(1.0)
+            continue
+        kept = s[s > rtol * s[0]]
+        out.append(kept[0] / kept[-1])
+    return np.array(out)

@@ -1,0 +1,138 @@
+"""Adjoint of the reconstruction loss (copa_loss_grad) against the FP64 oracle gradient and FP64
+central finite differences, plus the torch.autograd wrapper."""
+import numpy as np
+import pytest
+
+from oracle import copa_oracle as co
+from paper_1803_04572_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _point(coh, R, seed):
+    """FP32-representable evaluation point: Qt_k with orthonormal columns (rows when I_k < R),
+    H ~ N(0,1), V, W ~ U[0,1)."""
+    rng = np.random.default_rng(seed)
+    Qts = []
+    for k in range(coh.K):
+        n = int(coh.subj_ptr[k + 1] - coh.subj_ptr[k])
+        g = rng.standard_normal((n, R))
+        if n >= R:
+            q, _ = np.linalg.qr(g)
+        else:
+            q, _ = np.linalg.qr(g.T)
+            q = q.T
+        Qts.append(_f32(q))
+    H = _f32(rng.standard_normal((R, R)))
+    V = _f32(rng.random((coh.J, R)))
+    W = _f32(rng.random((coh.K, R)))
+    return Qts, H, V, W
+
+
+def _gpu(coh, R, Qts, H, V, W, want_dS=False, l=0):
+    import torch
+    from paper_1803_04572_amd import copa
+    plan = copa.Plan.from_cohort(coh, R=R, l=l)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).cuda()  # noqa
+    Qt = d(np.concatenate(Qts, axis=0))
+    out = plan.loss_grad(d(H), d(V), d(W), Qt, want_dS=want_dS)
+    torch.cuda.synchronize()
+    loss = out[0]
+    grads = [None if g is None else g.double().cpu().numpy() for g in out[1:]]
+    return plan, loss, grads
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("K,R,l", [(50, 10, 0), (2000, 10, 0), (300, 5, 7)])
+def test_loss_grad_matches_fp64_reference(K, R, l):
+    coh, _ = synth.make_config("c5", K=K)
+    Qts, H, V, W = _point(coh, R, seed=K)
+    plan, loss, (dH, dV, dW, dS) = _gpu(coh, R, Qts, H, V, W, want_dS=True, l=l)
+    Xs = co.subject_matrices(coh)
+    L, rH, rV, rW, rS = co.loss_grad(Xs, Qts, H, V, W)
+    errs = dict(loss=abs(loss - L) / L, dH=_rel(dH, rH), dV=_rel(dV, rV), dW=_rel(dW, rW),
+                dS=_rel(dS, np.stack(rS)))
+    print("adjoint", K, R, l, " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    assert errs["loss"] < 1e-6
+    for k in ("dH", "dV", "dW", "dS"):
+        assert errs[k] < 1e-4, (k, errs[k])
+    # W's gradient is the diagonal of the full S_k gradient
+    np.testing.assert_allclose(np.einsum("krr->kr", dS), dW, rtol=1e-5, atol=1e-5 * np.abs(dW).max())
+
+
+def test_gradient_matches_fp64_central_differences():
+    """K = 50 slice of the adjoint workload: GPU gradient entries against central differences
+    (h = 1e-6) of the FP64 loss at the same point."""
+    coh, _ = synth.make_config("c5", K=50)
+    R = 10
+    Qts, H, V, W = _point(coh, R, seed=7)
+    plan, loss, (dH, dV, dW, _) = _gpu(coh, R, Qts, H, V, W)
+    Xs = co.subject_matrices(coh)
+    rng = np.random.default_rng(8)
+    h = 1e-6
+    scale = {"H": np.abs(dH).max(), "V": np.abs(dV).max(), "W": np.abs(dW).max()}
+    for name, P, G in (("H", H, dH), ("V", V, dV), ("W", W, dW)):
+        for _ in range(8):
+            idx = tuple(int(rng.integers(0, s)) for s in P.shape)
+            args = {"H": H, "V": V, "W": W}
+            Pp, Pm = P.copy(), P.copy()
+            Pp[idx] += h
+            Pm[idx] -= h
+            fp = co.loss_grad(Xs, Qts, **{**args, name: Pp})[0]
+            fm = co.loss_grad(Xs, Qts, **{**args, name: Pm})[0]
+            fd = (fp - fm) / (2 * h)
+            assert abs(G[idx] - fd) <= 1e-4 * scale[name] + 1e-4 * abs(fd), (name, idx, G[idx], fd)
+
+
+def test_gradient_vanishes_at_exact_model():
+    """X_k = Q_k H S_k V^T exactly (FP32 values): the gradient at the truth is ~0 relative to
+    its size at a perturbed point."""
+    rng = np.random.default_rng(3)
+    K, J, R = 40, 30, 4
+    H = _f32(rng.standard_normal((R, R)))
+    V = _f32(np.abs(rng.standard_normal((J, R))) + 0.1)
+    W = _f32(0.5 + rng.random((K, R)))
+    Qs, Xs = [], []
+    for k in range(K):
+        q, _ = np.linalg.qr(rng.standard_normal((int(rng.integers(5, 12)), R)))
+        Qs.append(_f32(q))
+        Xs.append(Qs[-1] @ H @ np.diag(W[k]) @ V.T)
+    from tests_support import dense_cohort
+    coh = dense_cohort(Xs, J)
+    _, loss, (dH, dV, dW, _) = _gpu(coh, R, Qs, H, V, W)
+    _, loss2, (eH, eV, eW, _) = _gpu(coh, R, Qs, H, V * 1.01, W)
+    for g, e in ((dH, eH), (dV, eV), (dW, eW)):
+        assert np.abs(g).max() < 1e-3 * np.abs(e).max()
+    assert loss < 1e-5 * loss2 + 1e-6
+
+
+def test_autograd_function_returns_the_adjoint():
+    import torch
+    from paper_1803_04572_amd import copa
+    coh, _ = synth.make_config("c5", K=200)
+    R = 10
+    Qts, H, V, W = _point(coh, R, seed=11)
+    plan = copa.Plan.from_cohort(coh, R=R, l=0)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).cuda()  # noqa
+    Qt = d(np.concatenate(Qts, axis=0))
+    Ht, Vt, Wt = (d(a).requires_grad_(True) for a in (H, V, W))
+    loss = copa.copa_loss(Ht, Vt, Wt, plan, Qt)
+    (3.0 * loss).backward()
+    _, dH, dV, dW, _ = plan.loss_grad(d(H), d(V), d(W), Qt)
+    torch.testing.assert_close(Ht.grad, 3.0 * dH, rtol=1e-5, atol=1e-6)
+    torch.testing.assert_close(Vt.grad, 3.0 * dV, rtol=1e-5, atol=1e-6)
+    torch.testing.assert_close(Wt.grad, 3.0 * dW, rtol=1e-5, atol=1e-6)
