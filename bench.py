@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "outer AO-ADMM iters/sec + MTTKRP HBM GB/s at fixed fit vs FP64 oracle"
-SOURCES = ["copa_iter.hip", "copa_setup.hip", "copa_common.h"]
+SOURCES = ["copa_iter.hip", "copa_setup.hip", "copa_kernels.h", "copa_common.h"]
 
 
 def kernel_source_hash():
@@ -48,16 +48,15 @@ def algorithmic_bytes(coh, R, l, nfv):
         "pass1": x_stream + J * R * 4 + rows * R * 4,
         "procrustes": rows * R * 4 * 2 + K * R * 4 + R * R * 4,
         "gram_FH": rows * R * 4 * 2 + K * R * 4,
+        "mode_H": R * R * 8 * 3,
         "w_admm": rows * R * 4 * 3 + K * R * 4 * 5,
-        "gram_W": K * R * 4,
-        "gram_M": rows * R * 4,
+        "gram_WM": K * R * 4 + rows * R * 4,
         "pass2": x_stream + rows * R * 4 + K * R * 4 + J * R * 4,
         "v_admm": J * R * 4 * 5,
-        "gram_V": J * R * 4,
     }
 
 
-def cpu_baseline(cfg_name, R, l, K_full, n_subjects=2000, iters=3):
+def cpu_baseline(cfg_name, R, l, K_full, n_subjects=10000, iters=10):
     """The FP64 oracle, as it is, on a bounded sample of the same workload: `iters` outer
     iterations on a cohort of `n_subjects` drawn with the same recipe, scaled by subject count."""
     try:
