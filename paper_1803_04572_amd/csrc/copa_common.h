@@ -16,7 +16,10 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kLMax = 8;           // spline basis functions per subject (padded row width of C)
 constexpr int kNMax = 8;           // largest Procrustes eigenproblem handled one subject per lane
 constexpr int kHistCap = 1024;     // per-iteration scalars buffered on the device
-constexpr int kGramBlocks = 64;    // partial-sum blocks of the row-Gram reductions
+constexpr int kGramSlots = 6;      // F_H, W^TW, Psi, V^TV partials; adjoint G and its second Gram
+
+// Layout of one Gram slot (R x R FP64 blocks): [maxnb block partials | total].
+__host__ __device__ constexpr int64_t gram_total_offset(int maxnb) { return (int64_t)maxnb; }
 constexpr int kChunkRows = 512;    // visit rows per chunk of the feature-sorted pass-2 layout
 constexpr int kMaxR = 64;
 constexpr int kNumKernels = 8;     // kernels of one outer iteration (see kernel_names)
@@ -83,6 +86,7 @@ struct copa_plan {
   int32_t *rowsubj = nullptr;  // [S] subject of each visit row (unsmoothed only)
   float *C = nullptr;        // [S x 8] smoothing basis rows (l > 0)
   int32_t *rk = nullptr;     // [K] basis ranks (l > 0)
+  float *Ew = nullptr;       // [64 x K] Procrustes eigenvectors of the last outer iteration (l > 0)
   int32_t *order = nullptr;  // [K] subjects by decreasing visit count
   copa::WaveEntry *waves = nullptr;
   int32_t n_waves = 0;
@@ -105,7 +109,11 @@ struct copa_plan {
   uint32_t *pkey = nullptr;  // [nnz] feature << 16 | row within chunk
   float *pval = nullptr;     // [nnz]
   int n_cu = 0;
-  double *gpart = nullptr;  // [4 x kGramBlocks x R x R] Gram partials: F_H, W^TW, Psi, V^TV
+  // Gram slots (gstride doubles each): F_H, W^TW, Psi, V^TV partials of the V update, and two
+  // more for the adjoint; a slot holds gmaxnb block partials and their total.
+  double *gpart = nullptr;
+  int gmaxnb = 0;
+  int64_t gstride = 0;
   int32_t *gcount = nullptr;  // [8] last-block counters of the row Grams
   double *vpart = nullptr;  // [blocks x 4] V-ADMM scalar partials
   int n_vblocks = 0;
@@ -124,6 +132,15 @@ struct copa_plan {
   float *gradbuf = nullptr; // [2 x S x R] U and D rows of the adjoint (allocated on first use)
   double *lpart = nullptr;  // per-block loss partials of the adjoint
 };
+namespace copa {
+enum { kSlotFH = 0, kSlotWtW = 1, kSlotPsi = 2, kSlotVtV = 3, kSlotG = 4, kSlotG2 = 5 };
+inline double *gram_slot(const copa_plan *p, int slot) { return p->gpart + (int64_t)slot * p->gstride; }
+// The reduced R x R total of a slot after a k_rows_gram launch.
+inline double *gram_total(const copa_plan *p, int slot) {
+  return gram_slot(p, slot) + gram_total_offset(p->gmaxnb) * p->R * p->R;
+}
+}  // namespace copa
+
 
 namespace copa {
 

@@ -221,13 +221,6 @@ __global__ void __launch_bounds__(64)
       for (int c = 0; c < R; ++c) dS[(k * R + a0 + a) * R + c] = acc[a][c];
 }
 
-template <int R>
-__global__ void __launch_bounds__(256)
-    k_grad_reduce(const double *__restrict__ part, int nb, double *dst) {
-  __shared__ double scratch[256];
-  block_reduce_parts<R * R>(part, nb, dst, scratch);
-}
-
 __global__ void k_zero_f(float *x, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x)
@@ -266,28 +259,23 @@ template <int R>
 static copa_status loss_grad_r(copa_plan *p, const float *H, const float *V, const float *W,
                                const float *Qt, float *dH, float *dV, float *dW, float *dS,
                                hipStream_t s) {
-  constexpr int RR = R * R;
-  double *partA = p->gpart;
-  double *partB = p->gpart + (size_t)kGramBlocks * RR;
-  double *Gm = p->small + 5 * RR;
+  // G = V^T V
+  gram<R>(p, V, V, p->J, nullptr, 0, kSlotG, nullptr, 0, 0, s);
+  const double *Gm = gram_total(p, kSlotG);
   float *U = p->gradbuf;
   float *D = p->gradbuf + (size_t)p->S * R;
-  // G = V^T V
-  k_rows_gram<R><<<dim3(kGramBlocks, 1), 1024, 0, s>>>(V, V, p->J, nullptr, 0, 1, nullptr, partA,
-                                                       nullptr, 0, nullptr);
-  k_grad_reduce<R><<<1, 256, 0, s>>>(partA, kGramBlocks, Gm);
   const int nb = std::max(1, (p->n_waves + 3) / 4);
   k_grad_rows<R><<<nb, 256, 0, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row, p->col,
                                     p->val, V, H, W, Qt, Gm, U, D, dW, p->lpart);
   // dL/dH = Qt^T D and Psi' = U^T U in one launch
-  k_rows_gram<R><<<dim3(kGramBlocks, 2), 1024, 0, s>>>(Qt, D, p->S, nullptr, 0, 1, nullptr,
-                                                       partA, U, p->S, partB);
+  gram<R>(p, Qt, D, p->S, nullptr, 0, kSlotFH, U, p->S, kSlotG2, s);
   // F = X^T U through the feature-sorted scatter
   float *F = p->gradbuf + (size_t)2 * p->S * R;
   k_zero_f<<<(unsigned)std::min<int64_t>(1024, (p->J * R + 255) / 256), 256, 0, s>>>(F, p->J * R);
   launch_scatter_rows<R>(p, U, F, s);
   k_grad_finish<R><<<(unsigned)std::max<int64_t>(1, (p->J + 255) / 256), 256, 0, s>>>(
-      p->J, F, V, partA, partB, kGramBlocks, p->lpart, nb, p->normX2, dV, dH, p->dloss);
+      p->J, F, V, gram_total(p, kSlotFH), gram_total(p, kSlotG2), 1, p->lpart, nb, p->normX2,
+      dV, dH, p->dloss);
   if (dS && p->K > 0) {
     constexpr int AR = R <= 12 ? R : (128 / R > 0 ? 128 / R : 1);
     constexpr int NP = (R + AR - 1) / AR;

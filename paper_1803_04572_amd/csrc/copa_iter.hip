@@ -257,11 +257,16 @@ __host__ __device__ constexpr int tri8(int i, int j) {
   return i <= j ? 8 * i - (i * (i - 1)) / 2 + (j - i) : 8 * j - (j * (j - 1)) / 2 + (i - j);
 }
 
+// With INIT = false, V holds an orthogonal matrix on entry and the rotations are accumulated onto
+// it: then A must be V^T G V and on return V holds the eigenvectors of G.
+template <bool INIT = true>
 __device__ __forceinline__ void jacobi8_tri(double (&A)[36], double (&V)[kNMax][kNMax]) {
+  if constexpr (INIT) {
 #pragma unroll
-  for (int i = 0; i < kNMax; ++i)
+    for (int i = 0; i < kNMax; ++i)
 #pragma unroll
-    for (int j = 0; j < kNMax; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+      for (int j = 0; j < kNMax; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+  }
   double scale = 0.0;
 #pragma unroll
   for (int i = 0; i < kNMax; ++i) scale += fabs(A[tri8(i, i)]);
@@ -298,6 +303,43 @@ __device__ __forceinline__ void jacobi8_tri(double (&A)[36], double (&V)[kNMax][
       }
     }
     if (!rotated) break;
+  }
+}
+
+// E <- E (3 I - E^T E) / 2: one Newton-Schulz step towards the nearest orthogonal matrix, taking
+// an FP32-rounded orthogonal matrix (deviation ~1e-7) to FP64 orthogonality (~1e-14).
+__device__ __forceinline__ void orthonormalize8(double (&E)[kNMax][kNMax]) {
+  double N[36];
+#pragma unroll
+  for (int p = 0; p < kNMax; ++p)
+#pragma unroll
+    for (int q = p; q < kNMax; ++q) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < kNMax; ++i) s += E[i][p] * E[i][q];
+      N[tri8(p, q)] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < kNMax; ++i) {
+    double r[kNMax];
+#pragma unroll
+    for (int q = 0; q < kNMax; ++q) {
+      double s = 0.0;
+#pragma unroll
+      for (int p = 0; p < kNMax; ++p) s += E[i][p] * N[tri8(p, q)];
+      r[q] = 1.5 * E[i][q] - 0.5 * s;
+    }
+#pragma unroll
+    for (int q = 0; q < kNMax; ++q) E[i][q] = r[q];
+  }
+}
+
+__global__ void k_eye8(float *__restrict__ Ew, int64_t K) {
+  const int64_t n = K * kNMax * kNMax;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ent = e / K;
+    Ew[e] = (ent / kNMax == ent % kNMax) ? 1.0f : 0.0f;
   }
 }
 
@@ -614,7 +656,7 @@ template <int R>
 __global__ void __launch_bounds__(64)
     k_procrustes_s(int64_t K, int l, const int32_t *__restrict__ rk, const float *__restrict__ T,
                    float *__restrict__ Q, const float *__restrict__ H, const float *__restrict__ W,
-                   double rtol, int32_t *rank_def) {
+                   float *__restrict__ Ew, double rtol, int32_t *rank_def) {
   __shared__ float sH[R * R];
   __shared__ float sA[kLMax * R * 64];  // A of this lane's subject, element (i, c) at (i R + c) 64 + lane
   const int lane = threadIdx.x;
@@ -644,21 +686,41 @@ __global__ void __launch_bounds__(64)
   }
   auto Aat = [&](int i, int c) -> double { return (double)sA[(i * R + c) * 64 + lane]; };
   const bool rows_side = l <= R;
+  // Warm start: the Gram's eigenvectors change little between outer iterations, so the Jacobi
+  // sweeps run on E^T G E with E = last iteration's eigenvectors (identity on the first), made
+  // orthogonal to FP64 precision first. G = A A^T (rows side) or A^T A (columns side) is summed
+  // from the rotated vectors E^T v over the columns (rows) v of A.
+  double E[kNMax][kNMax];
+#pragma unroll
+  for (int i = 0; i < kNMax; ++i)
+#pragma unroll
+    for (int j = 0; j < kNMax; ++j) E[i][j] = (double)Ew[(int64_t)(i * kNMax + j) * K + k];
+  orthonormalize8(E);
   double G[36];
 #pragma unroll
-  for (int p = 0; p < kNMax; ++p)
+  for (int e = 0; e < 36; ++e) G[e] = 0.0;
+  const int nv = rows_side ? R : kLMax;
+  for (int c = 0; c < nv; ++c) {
+    double v[kNMax], a[kNMax];
 #pragma unroll
-    for (int q = p; q < kNMax; ++q) {
+    for (int p = 0; p < kNMax; ++p) v[p] = rows_side ? Aat(p, c) : (p < R ? Aat(c, p) : 0.0);
+#pragma unroll
+    for (int q = 0; q < kNMax; ++q) {
       double s = 0.0;
-      if (rows_side) {
-        for (int c = 0; c < R; ++c) s += Aat(p, c) * Aat(q, c);
-      } else if (p < R && q < R) {
-        for (int i = 0; i < kLMax; ++i) s += Aat(i, p) * Aat(i, q);
-      }
-      G[tri8(p, q)] = s;
+#pragma unroll
+      for (int p = 0; p < kNMax; ++p) s += E[p][q] * v[p];
+      a[q] = s;
     }
-  double E[kNMax][kNMax];
-  jacobi8_tri(G, E);
+#pragma unroll
+    for (int p = 0; p < kNMax; ++p)
+#pragma unroll
+      for (int q = p; q < kNMax; ++q) G[tri8(p, q)] += a[p] * a[q];
+  }
+  jacobi8_tri<false>(G, E);
+#pragma unroll
+  for (int i = 0; i < kNMax; ++i)
+#pragma unroll
+    for (int j = 0; j < kNMax; ++j) Ew[(int64_t)(i * kNMax + j) * K + k] = (float)E[i][j];
   double lmax = 0.0;
 #pragma unroll
   for (int j = 0; j < kNMax; ++j) lmax = fmax(lmax, G[tri8(j, j)]);
@@ -1230,16 +1292,6 @@ static void launch_pass2_rt(copa_plan *p, hipStream_t s) {
     default: break;                                                                          \
   }
 
-template <int R>
-static void gram(copa_plan *p, const float *A, const float *B, int64_t rows, const float *W,
-                 int wsel, double *part, const float *A2, int64_t rows2, double *part2,
-                 hipStream_t s) {
-  dim3 grid(kGramBlocks, A2 ? 2 : 1);
-  k_rows_gram<R><<<grid, 1024, 0, s>>>(A, B, rows, W, wsel,
-                                       p->slot_rows > 0 ? p->slot_rows : 1, p->rowsubj, part, A2,
-                                       rows2, part2);
-}
-
 const char *const kernel_names[kNumKernels] = {"pass1",  "procrustes", "gram_FH", "mode_H",
                                                "w_admm", "gram_WM",    "pass2",   "v_admm"};
 
@@ -1282,7 +1334,8 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
       if constexpr (R <= 16) {
         if (p->l > 0) {
           k_procrustes_s<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-              K, p->l, p->rk, p->T, p->Q, st->H, st->W, o.rank_rtol, &p->scal->rank_def_cur);
+              K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol,
+              &p->scal->rank_def_cur);
           return;
         }
       }
@@ -1295,11 +1348,10 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
             &p->scal->rank_def_cur);
     });
   timed(p, s, kidGramFH, [&] {
-    gram<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, p->gpart, nullptr, 0,
-            nullptr, s);
+    gram<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, kSlotFH, nullptr, 0, 0, s);
   });
   timed(p, s, kidModeH, [&] {
-    k_mode_H<R><<<1, 256, 0, s>>>(p->gpart, kGramBlocks, p->small, p->modes, p->scal, st->H,
+    k_mode_H<R><<<1, 256, 0, s>>>(gram_total(p, kSlotFH), 1, p->small, p->modes, p->scal, st->H,
                                   st->D_H, o.prox_H, o.lambda_H, o.inner_iters, p->FV,
                                   p->J * R);
   });
@@ -1310,16 +1362,15 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
                                    o.inner_iters, p->wpart);
   });
   timed(p, s, kidGramWM, [&] {
-    gram<R>(p, st->W, st->W, K, nullptr, 0, p->gpart + (size_t)kGramBlocks * RR, p->M,
-            p->rows_total, p->gpart + (size_t)2 * kGramBlocks * RR, s);
+    gram<R>(p, st->W, st->W, K, nullptr, 0, kSlotWtW, p->M, p->rows_total, kSlotPsi, s);
   });
   timed(p, s, kidPass2, [&] { RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s); });
   timed(p, s, kidVadmm, [&] {
     k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(
         p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, (p->tiles.rt + 3) & ~3,
-        p->gpart + (size_t)kGramBlocks * RR, p->gpart + (size_t)2 * kGramBlocks * RR,
-        kGramBlocks, p->small, p->scal, o.prox_V, o.lambda_V, o.inner_iters, p->vpart,
-        p->gpart + (size_t)3 * kGramBlocks * RR, p->wpart, (int)nwb, st->H, p->normX2,
+        gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), 1, p->small, p->scal, o.prox_V,
+        o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV), p->wpart, (int)nwb, st->H,
+        p->normX2,
         o.prox_H, o.lambda_H, o.prox_W, o.lambda_W, p->gcount + 6);
   });
 }
@@ -1328,12 +1379,14 @@ template <int R>
 static void init_grams_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   constexpr int RR = R * R;
   k_reset_scalars<<<1, 64, 0, s>>>(p->scal);
+  if (p->Ew && p->K > 0)
+    k_eye8<<<(unsigned)std::min<int64_t>(4096, (p->K * kNMax * kNMax + 255) / 256), 256, 0, s>>>(
+        p->Ew, p->K);
   if (p->J > 0)
     k_pad_V<R><<<(unsigned)((p->J * R + 255) / 256), 256, 0, s>>>(
         st->V, p->Vp, p->J, p->tiles.rt, (p->tiles.rt + 3) & ~3);
-  gram<R>(p, st->W, st->W, p->K, nullptr, 0, p->gpart, st->V, p->J,
-          p->gpart + (size_t)kGramBlocks * RR, s);
-  k_init_small<R><<<1, 256, 0, s>>>(p->gpart, p->gpart + (size_t)kGramBlocks * RR, kGramBlocks,
+  gram<R>(p, st->W, st->W, p->K, nullptr, 0, kSlotWtW, st->V, p->J, kSlotVtV, s);
+  k_init_small<R><<<1, 256, 0, s>>>(gram_total(p, kSlotWtW), gram_total(p, kSlotVtV), 1,
                                     p->small);
 }
 

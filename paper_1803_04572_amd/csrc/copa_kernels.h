@@ -7,30 +7,73 @@
 namespace copa {
 
 // ======================================================================= row Gram reductions
+// dst[e] = sum_b part[b * RR + e] over b = 0..nb-1 in a fixed order, using the whole block
+// (scratch: blockDim.x doubles of LDS). dst may be LDS or global memory.
+template <int RR>
+__device__ void block_reduce_parts(const double *__restrict__ part, int nb, double *dst,
+                                   double *scratch) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  auto ld = [&](int64_t i) { return part[i]; };
+  if (RR <= nt) {
+    const int G = nt / RR;
+    const int e = t % RR, g = t / RR;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (g < G) {
+      int b = g;
+      for (; b + 7 * G < nb; b += 8 * G) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += ld((int64_t)(b + u * G) * RR + e);
+      }
+      for (; b < nb; b += G) s[0] += ld((int64_t)b * RR + e);
+    }
+    scratch[t] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    __syncthreads();
+    if (t < RR) {
+      double v = 0.0;
+      for (int q = 0; q < G; ++q) v += scratch[q * RR + t];
+      dst[t] = v;
+    }
+    __syncthreads();
+  } else {
+    for (int e = t; e < RR; e += nt) {
+      double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int b = 0;
+      for (; b + 8 <= nb; b += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += ld((int64_t)(b + u) * RR + e);
+      }
+      for (; b < nb; ++b) s[0] += ld((int64_t)b * RR + e);
+      dst[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    }
+    __syncthreads();
+  }
+}
+
 // part[block] = sum over the block's rows of A_row^T (B_row * w_subj(row)) (R x R, FP64): a dense
 // contraction over the long row dimension on the matrix cores. v_mfma_f64_16x16x4f64 takes 4 rows
 // per instruction, lane l holding A[row0 + l/16][16 ti + l%16] and B[row0 + l/16][16 tj + l%16];
-// each wave loads 8 such steps (32 rows) before issuing their 8 instructions. blockIdx.y == 1
-// computes a second, unscaled Gram A2^T A2 into part2 in the same launch.
-// wsel: 0 = no scaling; 1 = scale B by W[row / slot_rows]; 2 = scale by W[rowsubj[row]].
+// each wave loads BATCH such steps (64 rows; 32 for R > 16) before issuing their instructions.
+// blockIdx.y == 1 computes a second, unscaled Gram A2^T A2 into part2 in the same launch (WSEL 0
+// only). WSEL: 0 = no scaling; 1 = scale B by W[row / slot_rows]; 2 = scale by W[rowsubj[row]].
+// The partials are added by k_gram_reduce, a separate launch: publishing a partial to other
+// blocks of the same launch would take a device-scope release (an L2 write-back) per block.
 typedef double dbl4_t __attribute__((ext_vector_type(4)));
 
-template <int R>
-__global__ void __launch_bounds__(1024)
+template <int R, int WSEL>
+__global__ void __launch_bounds__(256)
     k_rows_gram(const float *__restrict__ A, const float *__restrict__ B, int64_t rows,
-                const float *__restrict__ W, int wsel, int slot_rows,
-                const int32_t *__restrict__ rowsubj, double *__restrict__ part,
-                const float *__restrict__ A2, int64_t rows2, double *__restrict__ part2) {
+                const float *__restrict__ W, int slot_rows, const int32_t *__restrict__ rowsubj,
+                double *__restrict__ part, const float *__restrict__ A2, int64_t rows2,
+                double *__restrict__ part2) {
   constexpr int NT = (R + 15) / 16;
   constexpr int RP = NT * 16;
   constexpr int RR = R * R;
-  constexpr int BATCH = 16;
+  constexpr int BATCH = NT >= 2 ? 8 : 16;  // 4-row steps in flight per wave (registers)
   __shared__ double sacc[RP * RP];
-  if (blockIdx.y == 1) {
+  if (WSEL == 0 && blockIdx.y == 1) {
     A = A2;
     B = A2;
     rows = rows2;
-    wsel = 0;
     part = part2;
   }
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
@@ -49,25 +92,40 @@ __global__ void __launch_bounds__(1024)
       acc2[i][j] = dbl4_t{0.0, 0.0, 0.0, 0.0};
     }
   for (int64_t u = u0 + wave; u < u1; u += nw) {
-    // loads from clamped (always valid) addresses, masked afterwards, so that they issue together
-    double av[BATCH][NT], bv[BATCH][NT];
+    // every load goes to a clamped (always valid) address and is masked afterwards, so that the
+    // whole batch is in flight at once
+    int64_t rc[BATCH];
+    bool ok[BATCH];
 #pragma unroll
     for (int s = 0; s < BATCH; ++s) {
       const int64_t rr = u * (4 * BATCH) + 4 * s + kk;
-      const bool ok = rr < rows;
-      const int64_t rc = ok ? rr : rows - 1;
-      const int64_t wrow = wsel == 1 ? (int64_t)((uint32_t)rc / (uint32_t)slot_rows)
-                                     : (wsel == 2 ? (int64_t)rowsubj[rc] : 0);
+      ok[s] = rr < rows;
+      rc[s] = ok[s] ? rr : rows - 1;
+    }
+    int64_t wrow[BATCH];
+#pragma unroll
+    for (int s = 0; s < BATCH; ++s) {
+      if constexpr (WSEL == 1)
+        wrow[s] = (int64_t)((uint32_t)rc[s] / (uint32_t)slot_rows);
+      else if constexpr (WSEL == 2)
+        wrow[s] = rowsubj[rc[s]];
+      else
+        wrow[s] = 0;
+    }
+    double av[BATCH][NT], bv[BATCH][NT];
+#pragma unroll
+    for (int s = 0; s < BATCH; ++s) {
 #pragma unroll
       for (int q = 0; q < NT; ++q) {
         const int c = q * 16 + m;
-        const bool in = ok && c < R;
+        const bool in = ok[s] && c < R;
         const int cc = c < R ? c : R - 1;
-        const float a = A[rc * R + cc];
-        const float b = B[rc * R + cc];
-        const float w = wsel ? W[wrow * R + cc] : 1.0f;
+        const float a = A[rc[s] * R + cc];
+        const float b = B[rc[s] * R + cc];
+        double bw = (double)b;
+        if constexpr (WSEL != 0) bw *= (double)W[wrow[s] * R + cc];
         av[s][q] = in ? (double)a : 0.0;
-        bv[s][q] = in ? (double)b * (double)w : 0.0;
+        bv[s][q] = in ? bw : 0.0;
       }
     }
 #pragma unroll
@@ -105,45 +163,50 @@ __global__ void __launch_bounds__(1024)
     part[(int64_t)blockIdx.x * RR + e] = sacc[(e / R) * RP + e % R];
 }
 
-// dst[e] = sum_b part[b * RR + e] over b = 0..nb-1 in a fixed order, using the whole block
-// (scratch: blockDim.x doubles of LDS). dst may be LDS or global memory.
+// total[e] = sum_b part[b * RR + e] over the nb block partials in a fixed order: one block per
+// group of 4 entries, 64 threads per entry, fixed-shape tree. blockIdx.y selects the launch half.
 template <int RR>
-__device__ void block_reduce_parts(const double *__restrict__ part, int nb, double *dst,
-                                   double *scratch) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  if (RR <= nt) {
-    const int G = nt / RR;
-    const int e = t % RR, g = t / RR;
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (g < G) {
-      int b = g;
-      for (; b + 7 * G < nb; b += 8 * G) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) s[u] += part[(int64_t)(b + u * G) * RR + e];
-      }
-      for (; b < nb; b += G) s[0] += part[(int64_t)b * RR + e];
-    }
-    scratch[t] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-    __syncthreads();
-    if (t < RR) {
-      double v = 0.0;
-      for (int q = 0; q < G; ++q) v += scratch[q * RR + t];
-      dst[t] = v;
-    }
-    __syncthreads();
-  } else {
-    for (int e = t; e < RR; e += nt) {
-      double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      int b = 0;
-      for (; b + 8 <= nb; b += 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) s[u] += part[(int64_t)(b + u) * RR + e];
-      }
-      for (; b < nb; ++b) s[0] += part[(int64_t)b * RR + e];
-      dst[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-    }
+__global__ void __launch_bounds__(256)
+    k_gram_reduce(const double *__restrict__ part, double *__restrict__ total,
+                  const double *__restrict__ part2, double *__restrict__ total2, int nb) {
+  __shared__ double red[256];
+  if (blockIdx.y == 1) {
+    part = part2;
+    total = total2;
+  }
+  const int t = threadIdx.x, lane = t & 63;
+  const int e = blockIdx.x * 4 + (t >> 6);
+  double s = 0.0;
+  if (e < RR)
+    for (int b = lane; b < nb; b += 64) s += part[(int64_t)b * RR + e];
+  red[t] = s;
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if (lane < w) red[t] += red[t + w];
     __syncthreads();
   }
+  if (lane == 0 && e < RR) total[e] = red[t];
+}
+
+// Launches k_rows_gram and k_gram_reduce: A^T (B * w) into the total of `slot` and, when A2 is
+// given, A2^T A2 into the total of `slot2`. wsel as WSEL of k_rows_gram (0 when A2 is given).
+template <int R>
+inline void gram(copa_plan *p, const float *A, const float *B, int64_t rows, const float *W,
+                 int wsel, int slot, const float *A2, int64_t rows2, int slot2, hipStream_t s) {
+  // about two 64-row units per wave of the 4-wave blocks
+  const int64_t units = (std::max<int64_t>(rows, A2 ? rows2 : 0) + 63) / 64;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(p->gmaxnb, (units + 7) / 8));
+  const dim3 grid(nb, A2 ? 2 : 1);
+  double *p1 = gram_slot(p, slot), *p2 = A2 ? gram_slot(p, slot2) : nullptr;
+  const int sr = p->slot_rows > 0 ? p->slot_rows : 1;
+  if (wsel == 1)
+    k_rows_gram<R, 1><<<grid, 256, 0, s>>>(A, B, rows, W, sr, p->rowsubj, p1, nullptr, 0, nullptr);
+  else if (wsel == 2)
+    k_rows_gram<R, 2><<<grid, 256, 0, s>>>(A, B, rows, W, sr, p->rowsubj, p1, nullptr, 0, nullptr);
+  else
+    k_rows_gram<R, 0><<<grid, 256, 0, s>>>(A, B, rows, W, sr, p->rowsubj, p1, A2, rows2, p2);
+  k_gram_reduce<R * R><<<dim3((R * R + 3) / 4, A2 ? 2 : 1), 256, 0, s>>>(
+      p1, gram_total(p, slot), p2, A2 ? gram_total(p, slot2) : nullptr, nb);
 }
 
 // ======================================================================= streaming pass 2

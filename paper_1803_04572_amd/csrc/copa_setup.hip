@@ -480,6 +480,7 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
     p->rows_total = K * p->l;
     COPA_TRY(dalloc(&p->C, S * kLMax));
     COPA_TRY(dalloc(&p->rk, K));
+    COPA_TRY(dalloc(&p->Ew, (size_t)K * kNMax * kNMax));
     if (K > 0) COPA_TRY(launch_basis(p->l, p->subj, X->days, p->C, p->rk, K, p->opt.basis_rtol, s));
   } else {
     p->slot_rows = 0;
@@ -512,16 +513,18 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
     COPA_TRY(dalloc(&p->Vp, (size_t)p->tiles.nt * p->J * rtp));
     COPA_HIP(hipMemsetAsync(p->Vp, 0, (size_t)p->tiles.nt * p->J * rtp * sizeof(float), s));
   }
-  COPA_TRY(dalloc(&p->gpart, (size_t)4 * std::max<int64_t>(kGramBlocks, (p->J + 255) / 256) * R * R));
+  COPA_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
+  p->gmaxnb = 2 * std::max(1, p->n_cu);
+  p->n_vblocks = (int)std::max<int64_t>(1, (p->J + 255) / 256);
+  p->gstride = (std::max<int64_t>(p->gmaxnb, p->n_vblocks) + 1) * R * R;
+  COPA_TRY(dalloc(&p->gpart, (size_t)kGramSlots * p->gstride));
   COPA_TRY(dalloc(&p->gcount, 8));
   COPA_HIP(hipMemsetAsync(p->gcount, 0, 8 * sizeof(int32_t), s));
-  COPA_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
   // ---- feature-sorted chunks for pass 2 (features < 2^16 and the F_V tile plus one chunk of
   // u rows fit in LDS)
   p->p2c = p->J <= 65536 && nnz > 0 &&
            ((int64_t)p->J * p->tiles.rt + (int64_t)kChunkRows * p->tiles.rt) * 4 <= p->lds_limit;
   if (p->p2c) COPA_TRY(build_sorted_chunks(X, p, s));
-  p->n_vblocks = (int)std::max<int64_t>(1, (p->J + 255) / 256);
   COPA_TRY(dalloc(&p->vpart, (size_t)p->n_vblocks * 4));
   COPA_TRY(dalloc(&p->wpart, (size_t)std::max<int64_t>(1, (K + 63) / 64)));
   COPA_TRY(dalloc(&p->small, 8 * R * R));
@@ -544,7 +547,7 @@ using namespace copa;
 
 static void free_plan(copa_plan *p) {
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-  void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->C, p->rk, p->order, p->waves,
+  void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->C, p->rk, p->Ew, p->order, p->waves,
                   p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->cptr, p->wsplit, p->pkey, p->pval, p->Vp,
                   p->gpart, p->gcount,
                   p->vpart, p->wpart, p->small, p->modes, p->scal, p->dloss, p->gradbuf,
