@@ -46,7 +46,7 @@ struct WaveEntry {
 // Scalars of one ADMM mode for one outer iteration, written by the single-block prep kernels.
 struct ModeParams {
   double rho;
-  double L[kMaxR * kMaxR];  // Cholesky factor of G + rho I, row-major lower triangle
+  double Gi[kMaxR * kMaxR];  // (G + rho I)^{-1}, row-major
 };
 
 // Device-side scalars of the fit (one struct, zeroed per copa_fit call).
@@ -54,7 +54,7 @@ struct FitScalars {
   int32_t iter;            // iterations completed in this call
   int32_t fail_iter;       // first failing iteration or INT_MAX
   int32_t rank_deficient;  // subjects with truncated Procrustes rank (last iteration)
-  int32_t rank_def_cur;    // same, accumulating during the current iteration
+  int32_t rank_def_slot[2];  // same, accumulating for iterations of parity 0 / 1
   double hist_fit[kHistCap];
   double hist_obj[kHistCap];
   double last_fit, last_obj, last_sparsity;
@@ -145,7 +145,8 @@ inline double *gram_total(const copa_plan *p, int slot) {
 namespace copa {
 
 // ---------------------------------------------------------------- launchers (copa_iter.hip)
-copa_status launch_iteration(copa_plan *p, const copa_state *st, hipStream_t s);
+copa_status launch_iteration(copa_plan *p, const copa_state *st, int it, hipStream_t s);
+copa_status launch_fit(copa_plan *p, const copa_state *st, int it, hipStream_t s);
 copa_status launch_init_grams(copa_plan *p, const copa_state *st, hipStream_t s);
 copa_status launch_qtilde(copa_plan *p, float *Qt, hipStream_t s);
 copa_status harvest_timing(copa_plan *p);
@@ -159,20 +160,18 @@ copa_status launch_loss_grad(copa_plan *p, const float *H, const float *V, const
                              hipStream_t s);
 
 // ---------------------------------------------------------------- device helpers
-__device__ __forceinline__ double prox_apply(double x, int kind, double lam, double rho) {
-  switch (kind) {
-    case COPA_PROX_NONNEG: return x > 0.0 ? x : 0.0;
-    case COPA_PROX_L1: {
-      double a = fabs(x) - lam / rho;
-      return a > 0.0 ? copysign(a, x) : 0.0;
-    }
-    case COPA_PROX_L0: return x * x > lam ? x : 0.0;
-    case COPA_PROX_NONNEG_L1: {
-      double a = x - lam / rho;
-      return a > 0.0 ? a : 0.0;
-    }
-    default: return x;
-  }
+// Proximity operators of the constraints (Section "Examples of useful constraints"), without
+// branches (kind is uniform across the wave; thr = lam / rho precomputed): nonnegativity,
+// signed soft threshold at lam / rho, hard threshold keeping x when x^2 > lam, and their
+// nonnegative combination.
+__device__ __forceinline__ double prox_sel(double x, int kind, double lam, double thr) {
+  const double a1 = fabs(x) - thr, a2 = x - thr;
+  double r = x;
+  r = kind == COPA_PROX_NONNEG ? (x > 0.0 ? x : 0.0) : r;
+  r = kind == COPA_PROX_L1 ? (a1 > 0.0 ? copysign(a1, x) : 0.0) : r;
+  r = kind == COPA_PROX_L0 ? (x * x > lam ? x : 0.0) : r;
+  r = kind == COPA_PROX_NONNEG_L1 ? (a2 > 0.0 ? a2 : 0.0) : r;
+  return r;
 }
 
 __device__ __forceinline__ float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, kWave); }

@@ -59,9 +59,14 @@ __global__ void __launch_bounds__(256)
             const int32_t *__restrict__ subj, const int32_t *__restrict__ row,
             const int32_t *__restrict__ col, const float *__restrict__ val,
             const float *__restrict__ C, const float *__restrict__ Vp, int64_t J, int R, int l,
-            float *__restrict__ T) {
+            float *__restrict__ T, float *__restrict__ FV) {
   constexpr int RTP = (RT + 3) & ~3;
   extern __shared__ float4 smem4[];
+  // F_V is accumulated by pass 2 of this iteration: clear it here
+  if (blockIdx.y == 0)
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < J * R;
+         e += (int64_t)gridDim.x * blockDim.x)
+      FV[e] = 0.0f;
   {
     // stage the tile with 8 loads in flight per thread
     const float4 *src = reinterpret_cast<const float4 *>(Vp + (int64_t)blockIdx.y * J * RTP);
@@ -201,6 +206,34 @@ __global__ void k_pad_V(const float *__restrict__ V, float *__restrict__ Vp, int
 }
 
 // ======================================================================= Procrustes
+// Reciprocal and reciprocal square root in FP64 from the hardware estimates plus two Newton
+// steps each (a few ulp; far shorter dependency chains than IEEE division and sqrt).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double h = 0.5 * x;
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+// Jacobi rotation of the pair (p, q): t = tan(theta) of the smaller angle that annihilates
+// a_pq, c = cos(theta), s = sin(theta). |tau| < 1e17 because a_pq is above the threshold, so
+// 1 + tau^2 does not overflow.
+__device__ __forceinline__ void jacobi_cs(double app, double aqq, double apq, double &t, double &c,
+                                          double &s) {
+  const double tau = (aqq - app) * rcp_nr(2.0 * apq);
+  const double x = fma(tau, tau, 1.0);
+  const double h = x * rsq_nr(x);  // sqrt(1 + tau^2)
+  t = copysign(rcp_nr(fabs(tau) + h), tau);
+  c = rsq_nr(fma(t, t, 1.0));
+  s = t * c;
+}
+
 // Symmetric eigenproblem of size <= kNMax in registers (cyclic Jacobi, FP64). A is stored as a
 // full array but only compile-time indices are used; on return A's diagonal holds the
 // eigenvalues and V the eigenvectors (columns).
@@ -222,9 +255,8 @@ __device__ __forceinline__ void jacobi8(double (&A)[kNMax][kNMax], double (&V)[k
         const double apq = A[p][q];
         if (fabs(apq) > tiny) {
           rotated = true;
-          const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
-          const double t = copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+          double t, c, s;
+          jacobi_cs(A[p][p], A[q][q], apq, t, c, s);
 #pragma unroll
           for (int k = 0; k < kNMax; ++k) {
             if (k == p || k == q) continue;
@@ -280,9 +312,8 @@ __device__ __forceinline__ void jacobi8_tri(double (&A)[36], double (&V)[kNMax][
         const double apq = A[tri8(p, q)];
         if (fabs(apq) > tiny) {
           rotated = true;
-          const double tau = (A[tri8(q, q)] - A[tri8(p, p)]) / (2.0 * apq);
-          const double t = copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+          double t, c, s;
+          jacobi_cs(A[tri8(p, p)], A[tri8(q, q)], apq, t, c, s);
 #pragma unroll
           for (int k = 0; k < kNMax; ++k) {
             if (k == p || k == q) continue;
@@ -575,9 +606,8 @@ __global__ void __launch_bounds__(64)
         if (fabs(apq) > tiny) {
           rotated = true;
           const double app = sG[p * n + p], aqq = sG[q * n + q];
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double t = copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+          double t, c, s;
+          jacobi_cs(app, aqq, apq, t, c, s);
           __syncthreads();
           if (lane < n && lane != p && lane != q) {
             const double gkp = sG[lane * n + p], gkq = sG[lane * n + q];
@@ -766,151 +796,296 @@ __global__ void __launch_bounds__(64)
 }
 
 // ======================================================================= ADMM helpers
-// sL <- Cholesky factor of X * Y + rho I (Hadamard product, FP64, lower triangle, row-major),
-// rho = trace(X * Y) / R (Algorithm 1). Whole block; one thread for R <= 16. Returns false (and
-// leaves L = I, rho = 1) when a pivot is not positive and finite.
+// sGi <- (X * Y + rho I)^{-1} (Hadamard product, FP64, full R x R), rho = trace(X * Y) / R
+// (Algorithm 1). The first wavefront runs Gauss-Jordan elimination on [G + rho I | I], lane i
+// holding row i; at step j lane j puts the live part of its row in LDS and every lane reads it
+// back (wavefront-local, in order). No pivoting is needed because the matrix is symmetric
+// positive definite, and the rho shift bounds its condition number by R + 1, so the explicit
+// inverse is as accurate as triangular solves and turns every later ADMM step into one
+// matrix-vector product. Whole block (sL: R x R LDS scratch). Returns false (and leaves
+// Gi = I, rho = 1) when a pivot is not positive and finite.
 template <int R>
-__device__ bool build_system(const double *__restrict__ X, const double *__restrict__ Y,
-                             double *sL, double *srho, int *sflag) {
+__device__ __forceinline__ bool build_system(const double *__restrict__ X,
+                                             const double *__restrict__ Y, double *sL,
+                                             double *sGi, double *srho, int *sflag) {
+  static_assert(R <= kWave, "one row per lane");
+  __shared__ double spiv[R + 1];
   const int t = threadIdx.x;
   for (int e = t; e < R * R; e += blockDim.x) sL[e] = X[e] * Y[e];
   __syncthreads();
-  if (t == 0) {
+  if (t < kWave) {
+    const int row = t < R ? t : 0;
     double tr = 0.0;
+#pragma unroll
     for (int i = 0; i < R; ++i) tr += sL[i * R + i];
     const double rho = tr / R;
-    *srho = rho;
-    *sflag = (isfinite(rho) && rho > 0.0) ? 0 : 1;
-    for (int i = 0; i < R; ++i) sL[i * R + i] += rho;
-  }
-  __syncthreads();
-  if constexpr (R <= 16) {
-    if (t == 0) {
-      for (int j = 0; j < R; ++j) {
-        double d = sL[j * R + j];
-        for (int k = 0; k < j; ++k) d -= sL[j * R + k] * sL[j * R + k];
-        if (!(d > 0.0) || !isfinite(d)) {
-          *sflag = 1;
-          d = 1.0;
-        }
-        const double ljj = sqrt(d);
-        sL[j * R + j] = ljj;
-        for (int i = j + 1; i < R; ++i) {
-          double v = sL[i * R + j];
-          for (int k = 0; k < j; ++k) v -= sL[i * R + k] * sL[j * R + k];
-          sL[i * R + j] = v / ljj;
-        }
-      }
+    bool ok = isfinite(rho) && rho > 0.0;
+    double a[R], b[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      a[c] = sL[row * R + c] + (c == row ? rho : 0.0);
+      b[c] = c == row ? 1.0 : 0.0;
     }
-    __syncthreads();
-  } else {
+#pragma unroll
     for (int j = 0; j < R; ++j) {
-      if (t == 0) {
-        double d = sL[j * R + j];
-        if (!(d > 0.0) || !isfinite(d)) {
-          *sflag = 1;
-          d = 1.0;
-        }
-        sL[j * R + j] = sqrt(d);
+      // live part of pivot row j: a[j..R-1] and b[0..j] (R + 1 values)
+      if (t == j) {
+#pragma unroll
+        for (int c = j; c < R; ++c) spiv[c - j] = a[c];
+#pragma unroll
+        for (int c = 0; c <= j; ++c) spiv[R - j + c] = b[c];
       }
-      __syncthreads();
-      const double djj = sL[j * R + j];
-      for (int i = j + 1 + t; i < R; i += blockDim.x) sL[i * R + j] /= djj;
-      __syncthreads();
-      for (int e = t; e < R * R; e += blockDim.x) {
-        const int i = e / R, c = e % R;
-        if (i > j && c > j && c <= i) sL[i * R + c] -= sL[i * R + j] * sL[c * R + j];
-      }
-      __syncthreads();
+      __builtin_amdgcn_wave_barrier();
+      const double piv = spiv[0];
+      ok = ok && piv > 0.0 && isfinite(piv);
+      const double inv = rcp_nr(piv > 0.0 ? piv : 1.0);
+      const bool me = t == j;
+      const double f = me ? 0.0 : a[j] * inv;
+#pragma unroll
+      for (int c = j + 1; c < R; ++c) a[c] = me ? a[c] * inv : a[c] - f * spiv[c - j];
+#pragma unroll
+      for (int c = 0; c <= j; ++c) b[c] = me ? b[c] * inv : b[c] - f * spiv[R - j + c];
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (t < R) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) sGi[t * R + c] = ok ? b[c] : (c == t ? 1.0 : 0.0);
+    }
+    if (t == 0) {
+      *srho = ok ? rho : 1.0;
+      *sflag = ok ? 0 : 1;
     }
   }
-  const bool ok = *sflag == 0;
-  if (!ok) {
-    for (int e = t; e < R * R; e += blockDim.x) sL[e] = (e / R == e % R) ? 1.0 : 0.0;
-    if (t == 0) *srho = 1.0;
-  }
   __syncthreads();
-  return ok;
+  return *sflag == 0;
 }
 
 // Inner ADMM steps on one row (Algorithm 1 inner loop):
-//   Z = (F + rho (Zb + D)) (G + rho I)^{-1}  via L L^T,  Zb = prox(Z - D),  D += Zb - Z.
+//   Z = (F + rho (Zb + D)) (G + rho I)^{-1},  Zb = prox(Z - D),  D += Zb - Z.
 template <int R>
 __device__ __forceinline__ void admm_row(const double (&F)[R], float (&Zb)[R], float (&D)[R],
-                                         const double *__restrict__ sL, double rho, int kind,
+                                         const double *__restrict__ sGi, double rho, int kind,
                                          double lam, int iters) {
+  const double thr = lam / rho;
   for (int it = 0; it < iters; ++it) {
-    double z[R];
+    // small R: the compiler keeps (G + rho I)^{-1} in registers across the steps; larger R
+    // re-reads it from LDS in every step (a compiler-only barrier stops the hoisting)
+    if constexpr (R > 12) __asm__ volatile("" ::: "memory");
+    double r[R], z[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      double s = F[i] + rho * ((double)Zb[i] + (double)D[i]);
-#pragma unroll
-      for (int j = 0; j < i; ++j) s -= sL[i * R + j] * z[j];
-      z[i] = s / sL[i * R + i];
-    }
-#pragma unroll
-    for (int i = R - 1; i >= 0; --i) {
-      double s = z[i];
-#pragma unroll
-      for (int j = i + 1; j < R; ++j) s -= sL[j * R + i] * z[j];
-      z[i] = s / sL[i * R + i];
+      r[i] = F[i] + rho * ((double)Zb[i] + (double)D[i]);
+      z[i] = 0.0;
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      const double zb = prox_apply(z[i] - (double)D[i], kind, lam, rho);
+      if constexpr (R > 12)
+        if (i % 2 == 0) __asm__ volatile("" ::: "memory");
+#pragma unroll
+      for (int c = 0; c < R; ++c) z[c] += r[i] * sGi[i * R + c];
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const double zb = prox_sel(z[i] - (double)D[i], kind, lam, thr);
       D[i] = (float)((double)D[i] + zb - z[i]);
       Zb[i] = (float)zb;
     }
   }
 }
 
-// ======================================================================= mode H (one block)
-// F_H from the Gram partials; G_H = W^TW * V^TV, rho, Cholesky; inner ADMM on the R rows of H;
-// H^T H; then the W-mode system G_W = H^TH * V^TV for the W update. Also clears F_V for pass 2.
+// ======================================================================= ADMM on rows by lanes
+// One factor row spread over R lanes of a wavefront (lane c holds column c): the inner ADMM
+// steps of Algorithm 1, Z = (F + rho (Zb + D)) (G + rho I)^{-1}, Zb = prox(Z - D), D += Zb - Z,
+// with the row vector exchanged through this group's LDS slot xrow (wavefront-local: LDS
+// operations of one wavefront complete in order, so a compiler barrier is enough).
+template <int R>
+__device__ __forceinline__ void admm_lanes(double F, float &Zb, float &D,
+                                           const double *__restrict__ sGi, double rho, int kind,
+                                           double lam, int iters, double *xrow, int c) {
+  const double thr = lam / rho;
+  for (int it = 0; it < iters; ++it) {
+    xrow[c] = F + rho * ((double)Zb + (double)D);
+    __builtin_amdgcn_wave_barrier();
+    double z = 0.0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) z += xrow[k] * sGi[k * R + c];
+    __builtin_amdgcn_wave_barrier();
+    const double zb = prox_sel(z - (double)D, kind, lam, thr);
+    D = (float)((double)D + zb - z);
+    Zb = (float)zb;
+  }
+}
+
+// ======================================================================= FIT of an iteration
+// Inputs of the FIT and objective of outer iteration `it`, left as per-block partials by the V
+// update and the W update of that iteration.
+struct FitArgs {
+  const double *vpart;    // [nvb x 4] <F_V, V>, |V|_1, zeros
+  const double *vtvpart;  // [nvb x R x R] V^T V
+  int nvb;
+  const double *wl1part;  // [nwb] |W|_1
+  int nwb;
+  double normX2;
+  int64_t J;
+  int proxV, proxW, proxH;
+  double lamV, lamW, lamH;
+};
+
+// Whole block (256 threads; red: 6 x 256 doubles of LDS, sVtV: R x R of LDS). Adds the partials
+// in block order, stores V^T V, and evaluates
+//   FIT = 1 - (|X|^2 - 2 <F_V, V> + <Psi, V^T V>) / |X|^2   (Section "Evaluation Metrics")
+// and the objective with the l1 penalties, with H = the factor of that iteration.
+template <int R>
+__device__ __forceinline__ void fit_finalize(const FitArgs &fa, int it, const float *H,
+                                             double *small, FitScalars *sc, double (*red)[256],
+                                             double *sVtV) {
+  constexpr int RR = R * R;
+  const int t = threadIdx.x;
+  block_reduce_parts<RR>(fa.vtvpart, fa.nvb, sVtV, red[0]);
+  double dot = 0.0, l1 = 0.0, zeros = 0.0, wl1 = 0.0, hl1 = 0.0, quad = 0.0;
+  for (int b = t; b < fa.nvb; b += blockDim.x) {
+    dot += fa.vpart[b * 4 + 0];
+    l1 += fa.vpart[b * 4 + 1];
+    zeros += fa.vpart[b * 4 + 2];
+  }
+  for (int b = t; b < fa.nwb; b += blockDim.x) wl1 += fa.wl1part[b];
+  for (int e = t; e < RR; e += blockDim.x) {
+    hl1 += fabs((double)H[e]);
+    quad += small[kPsi * RR + e] * sVtV[e];
+    small[kVtV * RR + e] = sVtV[e];
+  }
+  red[0][t] = dot;
+  red[1][t] = l1;
+  red[2][t] = zeros;
+  red[3][t] = quad;
+  red[4][t] = wl1;
+  red[5][t] = hl1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) red[q][t] += red[q][t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double resid = fa.normX2 - 2.0 * red[0][0] + red[3][0];
+    const double fit = fa.normX2 > 0.0 ? 1.0 - resid / fa.normX2 : 0.0;
+    auto pen = [](int k, double la, double v) {
+      return (k == COPA_PROX_L1 || k == COPA_PROX_NONNEG_L1) ? la * v : 0.0;
+    };
+    const double obj = 0.5 * resid + pen(fa.proxV, fa.lamV, red[1][0]) +
+                       pen(fa.proxW, fa.lamW, red[4][0]) + pen(fa.proxH, fa.lamH, red[5][0]);
+    if (!isfinite(fit) || !isfinite(obj)) atomicMin(&sc->fail_iter, it);
+    if (it < kHistCap) {
+      sc->hist_fit[it] = fit;
+      sc->hist_obj[it] = obj;
+    }
+    sc->last_fit = fit;
+    sc->last_obj = obj;
+    sc->last_sparsity = fa.J > 0 ? red[2][0] / ((double)fa.J * R) : 0.0;
+    sc->rank_deficient = sc->rank_def_slot[it & 1];
+    sc->rank_def_slot[it & 1] = 0;
+    sc->iter = it + 1;
+  }
+  __syncthreads();
+}
+
 template <int R>
 __global__ void __launch_bounds__(256)
-    k_mode_H(const double *__restrict__ partFH, int nb, double *small, ModeParams *modes,
-             FitScalars *sc, float *H, float *DH, int kind, double lam, int iters,
-             float *__restrict__ FV, int64_t nFV) {
-  __shared__ double sFH[R * R];
-  __shared__ double sL[R * R];
-  __shared__ double scratch[256];
+    k_fit(FitArgs fa, int it, const float *H, double *small, FitScalars *sc) {
+  __shared__ double red[6][256];
+  __shared__ double sVtV[R * R];
+  fit_finalize<R>(fa, it, H, small, sc, red, sVtV);
+}
+
+// The row Gram F_H = sum Q_row^T (T_row * w) (as k_rows_gram) with one extra block that takes
+// the FIT of the previous outer iteration meanwhile (fit_block: that block's index, or -1).
+template <int R, int WSEL>
+__global__ void __launch_bounds__(256)
+    k_rows_gram_fit(const float *__restrict__ A, const float *__restrict__ B, int64_t rows,
+                    const float *__restrict__ W, int slot_rows,
+                    const int32_t *__restrict__ rowsubj, double *__restrict__ part, int nb,
+                    FitArgs fa, int fit_it, const float *__restrict__ H, double *small,
+                    FitScalars *sc) {
+  if ((int)blockIdx.x == nb) {
+    __shared__ double red[6][256];
+    __shared__ double sVtV[R * R];
+    fit_finalize<R>(fa, fit_it, H, small, sc, red, sVtV);
+    return;
+  }
+  rows_gram_block<R, WSEL>(A, B, rows, W, slot_rows, rowsubj, part, blockIdx.x, nb);
+}
+
+template <int R>
+static void gram_fit(copa_plan *p, const float *A, const float *B, int64_t rows,
+                     const float *W, int wsel, int slot, bool fit, const FitArgs &fa,
+                     int fit_it, const float *H, hipStream_t s) {
+  const int64_t units = (rows + 63) / 64;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(p->gmaxnb, (units + 7) / 8));
+  const unsigned grid = (unsigned)nb + (fit ? 1u : 0u);
+  double *p1 = gram_slot(p, slot);
+  const int sr = p->slot_rows > 0 ? p->slot_rows : 1;
+  if (wsel == 1)
+    k_rows_gram_fit<R, 1><<<grid, 256, 0, s>>>(A, B, rows, W, sr, p->rowsubj, p1, nb, fa,
+                                               fit_it, H, p->small, p->scal);
+  else
+    k_rows_gram_fit<R, 2><<<grid, 256, 0, s>>>(A, B, rows, W, sr, p->rowsubj, p1, nb, fa,
+                                               fit_it, H, p->small, p->scal);
+  k_gram_reduce<R * R><<<dim3((R * R + 3) / 4, 1), 256, 0, s>>>(p1, gram_total(p, slot), nullptr,
+                                                                 nullptr, nb);
+}
+
+// ======================================================================= mode H (one block)
+// G_H = W^TW * V^TV, rho, (G_H + rho I)^{-1}; inner ADMM on the R rows of H (R lanes per row);
+// H^T H; then the W-mode system G_W = H^TH * V^TV for the W update.
+template <int R>
+__global__ void __launch_bounds__(256)
+    k_mode_H(int it, const double *FHtot, double *small, ModeParams *modes, FitScalars *sc,
+             float *H, float *DH, int kind, double lam, int iters) {
+  constexpr int RR = R * R;
+  constexpr int G = kWave / R;
+  __shared__ double sFH[RR], sX[RR], sY[RR], sL[RR], sGi[RR];
+  __shared__ double xch[4][G + 1][R];
+  __shared__ float sH[RR];
   __shared__ double srho;
   __shared__ int sflag;
-  const int t = threadIdx.x;
-  for (int64_t e = t; e < nFV; e += blockDim.x) FV[e] = 0.0f;
-  block_reduce_parts<R * R>(partFH, nb, sFH, scratch);
-  for (int e = t; e < R * R; e += blockDim.x) small[kFH * R * R + e] = sFH[e];
-  bool ok = build_system<R>(small + kWtW * R * R, small + kVtV * R * R, sL, &srho, &sflag);
-  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->iter);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = lane / R, c = lane % R;
+  for (int e = t; e < RR; e += blockDim.x) {
+    sFH[e] = FHtot[e];
+    sX[e] = small[kWtW * RR + e];
+    sY[e] = small[kVtV * RR + e];
+  }
+  __syncthreads();
+  for (int e = t; e < RR; e += blockDim.x) small[kFH * RR + e] = sFH[e];
+  bool ok = build_system<R>(sX, sY, sL, sGi, &srho, &sflag);
+  if (t == 0 && !ok) atomicMin(&sc->fail_iter, it);
   const double rho = srho;
-  if (t < R) {
-    double F[R];
-    float Zb[R], D[R];
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      F[c] = sFH[t * R + c];
-      Zb[c] = H[t * R + c];
-      D[c] = DH[t * R + c];
-    }
-    admm_row<R>(F, Zb, D, sL, rho, kind, lam, iters);
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      H[t * R + c] = Zb[c];
-      DH[t * R + c] = D[c];
+  for (int r0 = 0; r0 < R; r0 += 4 * G) {
+    const int row = r0 + wave * G + g;
+    const bool act = g < G && row < R;
+    const int rc = act ? row : 0;
+    float Zb = H[rc * R + c], D = DH[rc * R + c];
+    admm_lanes<R>(sFH[rc * R + c], Zb, D, sGi, rho, kind, lam, iters, xch[wave][g], c);
+    if (act) {
+      H[row * R + c] = Zb;
+      DH[row * R + c] = D;
+      sH[row * R + c] = Zb;
     }
   }
   __syncthreads();
-  for (int e = t; e < R * R; e += blockDim.x) {
+  for (int e = t; e < RR; e += blockDim.x) {
     const int a = e / R, b = e % R;
     double v = 0.0;
-    for (int i = 0; i < R; ++i) v += (double)H[i * R + a] * (double)H[i * R + b];
-    small[kHtH * R * R + e] = v;
+#pragma unroll
+    for (int i = 0; i < R; ++i) v += (double)sH[i * R + a] * (double)sH[i * R + b];
+    sX[e] = v;
+    small[kHtH * RR + e] = v;
   }
   __syncthreads();
-  ok = build_system<R>(small + kHtH * R * R, small + kVtV * R * R, sL, &srho, &sflag);
-  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->iter);
-  for (int e = t; e < R * R; e += blockDim.x) modes[1].L[e] = sL[e];
+  ok = build_system<R>(sX, sY, sL, sGi, &srho, &sflag);
+  if (t == 0 && !ok) atomicMin(&sc->fail_iter, it);
+  for (int e = t; e < RR; e += blockDim.x) modes[1].Gi[e] = sGi[e];
   if (t == 0) modes[1].rho = srho;
 }
 
@@ -922,11 +1097,11 @@ __global__ void __launch_bounds__(64)
              const float *__restrict__ H, float *__restrict__ W, float *__restrict__ DW,
              float *__restrict__ FW, const ModeParams *__restrict__ modes, int kind, double lam,
              int iters, double *__restrict__ l1part) {
-  __shared__ double sL[R * R];
+  __shared__ double sGi[R * R];
   __shared__ float sH[R * R];
   __shared__ double sred[64];
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
-    sL[e] = modes[1].L[e];
+    sGi[e] = modes[1].Gi[e];
     sH[e] = H[e];
   }
   __syncthreads();
@@ -947,7 +1122,31 @@ __global__ void __launch_bounds__(64)
     double F[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) F[c] = 0.0;
-    for (int i = 0; i < m; ++i) {
+    float qh[kLMax][R];  // smoothed: the l rows q_i H, kept for the M rows
+    if (l > 0) {
+      // at most kLMax projected rows: all loads issued at once from clamped rows, masked after
+      float qv[kLMax][R], tv[kLMax][R];
+#pragma unroll
+      for (int i = 0; i < kLMax; ++i) {
+        const int64_t ri = base + (i < l ? i : 0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          qv[i][r] = Q[ri * R + r];
+          tv[i][r] = T[ri * R + r];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kLMax; ++i)
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+          double p = 0.0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) p += (double)qv[i][r] * sH[r * R + c];
+          F[c] += i < m ? p * (double)tv[i][c] : 0.0;
+          qh[i][c] = (float)p;
+        }
+    }
+    for (int i = 0; l == 0 && i < m; ++i) {
       const float *q = Q + (base + i) * R;
       const float *t = T + (base + i) * R;
       float qv[R];
@@ -968,7 +1167,7 @@ __global__ void __launch_bounds__(64)
       D[c] = DW[k * R + c];
       FW[k * R + c] = (float)F[c];
     }
-    admm_row<R>(F, Zb, D, sL, rho, kind, lam, iters);
+    admm_row<R>(F, Zb, D, sGi, rho, kind, lam, iters);
 #pragma unroll
     for (int c = 0; c < R; ++c) {
       W[k * R + c] = Zb[c];
@@ -976,8 +1175,16 @@ __global__ void __launch_bounds__(64)
       l1 += fabs((double)Zb[c]);
     }
     // M rows = (q_i H) * w_new
-    const int mall = l > 0 ? l : m;
-    for (int i = 0; i < mall; ++i) {
+    if (l > 0) {
+#pragma unroll
+      for (int i = 0; i < kLMax; ++i)
+        if (i < l) {
+#pragma unroll
+          for (int c = 0; c < R; ++c)
+            M[(base + i) * R + c] = (float)((double)qh[i][c] * (double)Zb[c]);
+        }
+    }
+    for (int i = 0; l == 0 && i < m; ++i) {
       const float *q = Q + (base + i) * R;
       float qv[R];
 #pragma unroll
@@ -1001,73 +1208,86 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// ======================================================================= mode V (+ FIT)
-// Every block: W^T W and Psi from the Gram partials, G_V = H^TH * W^TW, rho, Cholesky; then one
-// V row per thread (inner ADMM, l1 prox), the padded V tile copy for the next pass 1, per-block
-// sums of <F_V, V>, |V|_1 and zeros, and the block's share of V^T V on the matrix cores. The last
-// block to finish adds the block results in block order and evaluates
-//   FIT = 1 - (|X|^2 - 2 <F_V, V> + <Psi, V^T V>) / |X|^2   (Section "Evaluation Metrics").
+// ======================================================================= mode V
+// Every block: G_V = H^TH * W^TW, rho, (G_V + rho I)^{-1}; then its V rows, R lanes per row
+// (inner ADMM, l1 prox), the padded V tile copy for the next pass 1, and per-block partials of
+// <F_V, V>, |V|_1, zeros and V^T V for the FIT (added by the next launch that needs them).
 template <int R>
 __global__ void __launch_bounds__(256)
-    k_v_admm(int64_t J, const float *__restrict__ FV, float *__restrict__ V,
+    k_v_admm(int it, int64_t J, const float *__restrict__ FV, float *__restrict__ V,
              float *__restrict__ DV, float *__restrict__ Vp, int rt, int rtp,
-             const double *__restrict__ partW, const double *__restrict__ partM, int nbp,
-             double *small, FitScalars *sc, int kind, double lam, int iters,
-             double *__restrict__ vpart, double *__restrict__ vtvpart,
-             const double *__restrict__ wl1part, int nwb, const float *__restrict__ H,
-             double normX2, int proxH, double lamH, int proxW, double lamW, int32_t *counter) {
+             const double *__restrict__ WtWtot, const double *__restrict__ Psitot, double *small,
+             FitScalars *sc, int kind, double lam, int iters, double *__restrict__ vpart,
+             double *__restrict__ vtvpart) {
   constexpr int RR = R * R;
-  constexpr int NT = (R + 15) / 16;
-  constexpr int RP = NT * 16;
-  __shared__ double sW[RR];
-  __shared__ double sPsi[RR];
-  __shared__ double sL[RR];
-  __shared__ double sacc[RP * RP];
-  __shared__ double scratch[256];
+  constexpr int G = kWave / R;
+  constexpr int RB = 4 * G;  // rows per block pass
+  __shared__ double sW[RR], sPsi[RR], sHH[RR], sL[RR], sGi[RR];
+  __shared__ double xch[4][G + 1][R];
+  __shared__ float sV[RB][R];
   __shared__ double red[3][256];
   __shared__ double srho;
   __shared__ int sflag;
-  __shared__ int last;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  block_reduce_parts<RR>(partW, nbp, sW, scratch);
-  block_reduce_parts<RR>(partM, nbp, sPsi, scratch);
+  const int g = lane / R, c = lane % R;
+  const int slot = wave * G + g;
+  for (int e = t; e < RR; e += blockDim.x) {
+    sW[e] = WtWtot[e];
+    sPsi[e] = Psitot[e];
+    sHH[e] = small[kHtH * RR + e];
+  }
+  __syncthreads();
   if (blockIdx.x == 0) {
     for (int e = t; e < RR; e += blockDim.x) {
       small[kWtW * RR + e] = sW[e];
       small[kPsi * RR + e] = sPsi[e];
     }
   }
-  const bool ok = build_system<R>(small + kHtH * RR, sW, sL, &srho, &sflag);
-  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->iter);
+  const bool ok = build_system<R>(sHH, sW, sL, sGi, &srho, &sflag);
+  if (t == 0 && !ok) atomicMin(&sc->fail_iter, it);
   const double rho = srho;
-  const int64_t j0 = (int64_t)blockIdx.x * blockDim.x;
-  const int64_t j = j0 + t;
   double dot = 0.0, l1 = 0.0, zeros = 0.0;
-  if (j < J) {
-    double F[R];
+  double vtv[(RR + 255) / 256];
 #pragma unroll
-    for (int c = 0; c < R; ++c) F[c] = FV[j * R + c];
-    float Zb[R], D[R];
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      Zb[c] = V[j * R + c];
-      D[c] = DV[j * R + c];
+  for (int u = 0; u < (RR + 255) / 256; ++u) vtv[u] = 0.0;
+  for (int64_t j0 = (int64_t)blockIdx.x * RB; j0 < J; j0 += (int64_t)gridDim.x * RB) {
+    const int64_t j = j0 + slot;
+    const bool act = g < G && j < J;
+    const int64_t jc = act ? j : 0;
+    const double F = FV[jc * R + c];
+    float Zb = V[jc * R + c], D = DV[jc * R + c];
+    admm_lanes<R>(F, Zb, D, sGi, rho, kind, lam, iters, xch[wave][g], c);
+    if (act) {
+      V[j * R + c] = Zb;
+      DV[j * R + c] = D;
+      Vp[((int64_t)(c / rt) * J + j) * rtp + c % rt] = Zb;
+      dot += F * (double)Zb;
+      l1 += fabs((double)Zb);
+      zeros += Zb == 0.0f ? 1.0 : 0.0;
     }
-    admm_row<R>(F, Zb, D, sL, rho, kind, lam, iters);
+    if (g < G) sV[slot][c] = act ? Zb : 0.0f;
+    __syncthreads();
 #pragma unroll
-    for (int c = 0; c < R; ++c) {
-      V[j * R + c] = Zb[c];
-      DV[j * R + c] = D[c];
-      Vp[((int64_t)(c / rt) * J + j) * rtp + c % rt] = Zb[c];
-      dot += F[c] * (double)Zb[c];
-      l1 += fabs((double)Zb[c]);
-      zeros += Zb[c] == 0.0f ? 1.0 : 0.0;
+    for (int u = 0; u < (RR + 255) / 256; ++u) {
+      const int e = t + 256 * u;
+      if (e < RR) {
+        const int a = e / R, b = e % R;
+        double v = 0.0;
+#pragma unroll
+        for (int s = 0; s < RB; ++s) v += (double)sV[s][a] * (double)sV[s][b];
+        vtv[u] += v;
+      }
     }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < (RR + 255) / 256; ++u) {
+    const int e = t + 256 * u;
+    if (e < RR) vtvpart[(int64_t)blockIdx.x * RR + e] = vtv[u];
   }
   red[0][t] = dot;
   red[1][t] = l1;
   red[2][t] = zeros;
-  for (int e = t; e < RP * RP; e += blockDim.x) sacc[e] = 0.0;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (t < w)
@@ -1075,115 +1295,8 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
   }
   if (t < 3) vpart[blockIdx.x * 4 + t] = red[t][0];
-  // this block's rows of V^T V: 4 waves x 64 rows, 16 MFMA steps each, loads first
-  {
-    const int m = lane & 15, kk = lane >> 4;
-    dbl4_t acc[NT][NT];
-#pragma unroll
-    for (int i = 0; i < NT; ++i)
-#pragma unroll
-      for (int q = 0; q < NT; ++q) acc[i][q] = dbl4_t{0.0, 0.0, 0.0, 0.0};
-    double av[16][NT];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int64_t rr = j0 + wave * 64 + 4 * s + kk;
-#pragma unroll
-      for (int q = 0; q < NT; ++q) {
-        const int c = q * 16 + m;
-        av[s][q] = (rr < J && c < R) ? (double)V[rr * R + c] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < 16; ++s)
-#pragma unroll
-      for (int i = 0; i < NT; ++i)
-#pragma unroll
-        for (int q = 0; q < NT; ++q)
-          acc[i][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][i], av[s][q], acc[i][q], 0, 0, 0);
-    for (int w = 0; w < 4; ++w) {
-      if (wave == w) {
-#pragma unroll
-        for (int i = 0; i < NT; ++i)
-#pragma unroll
-          for (int q = 0; q < NT; ++q)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int ii = i * 16 + 4 * v + (lane >> 4), jj = q * 16 + (lane & 15);
-              sacc[ii * RP + jj] += acc[i][q][v];
-            }
-      }
-      __syncthreads();
-    }
-    for (int e = t; e < RR; e += blockDim.x)
-      vtvpart[(int64_t)blockIdx.x * RR + e] = sacc[(e / R) * RP + e % R];
-  }
-  __threadfence();
-  __syncthreads();
-  if (t == 0) last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const int nb = gridDim.x;
-  // V^T V in block order
-  for (int e = t; e < RR; e += blockDim.x) {
-    double v = 0.0;
-    for (int b = 0; b < nb; ++b)
-      v += __hip_atomic_load(&vtvpart[(int64_t)b * RR + e], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    small[kVtV * RR + e] = v;
-  }
-  __syncthreads();
-  double quad = 0.0, wl1 = 0.0;
-  for (int e = t; e < RR; e += blockDim.x) quad += sPsi[e] * small[kVtV * RR + e];
-  for (int b = t; b < nwb; b += blockDim.x) wl1 += wl1part[b];
-  dot = l1 = zeros = 0.0;
-  for (int b = t; b < nb; b += blockDim.x) {
-    dot += __hip_atomic_load(&vpart[b * 4 + 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    l1 += __hip_atomic_load(&vpart[b * 4 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    zeros += __hip_atomic_load(&vpart[b * 4 + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  red[0][t] = dot;
-  red[1][t] = l1;
-  red[2][t] = zeros;
-  scratch[t] = quad;
-  sacc[t] = wl1;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
-      for (int q = 0; q < 3; ++q) red[q][t] += red[q][t + w];
-      scratch[t] += scratch[t + w];
-      sacc[t] += sacc[t + w];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    double hl1 = 0.0;
-    for (int e = 0; e < RR; ++e) hl1 += fabs((double)H[e]);
-    const double resid = normX2 - 2.0 * red[0][0] + scratch[0];
-    const double fit = normX2 > 0.0 ? 1.0 - resid / normX2 : 0.0;
-    auto pen = [](int k, double la, double v) {
-      return (k == COPA_PROX_L1 || k == COPA_PROX_NONNEG_L1) ? la * v : 0.0;
-    };
-    const double obj = 0.5 * resid + pen(kind, lam, red[1][0]) + pen(proxW, lamW, sacc[0]) +
-                       pen(proxH, lamH, hl1);
-    const int it = sc->iter;
-    if (!isfinite(fit) || !isfinite(obj)) atomicMin(&sc->fail_iter, it);
-    if (it < kHistCap) {
-      sc->hist_fit[it] = fit;
-      sc->hist_obj[it] = obj;
-    }
-    sc->last_fit = fit;
-    sc->last_obj = obj;
-    sc->last_sparsity = J > 0 ? red[2][0] / ((double)J * R) : 0.0;
-    sc->rank_deficient = sc->rank_def_cur;
-    sc->rank_def_cur = 0;
-    sc->iter = it + 1;
-    *counter = 0;
-  }
 }
 
-// W^T W and V^T V of the starting point (copa_fit entry)
 template <int R>
 __global__ void __launch_bounds__(256)
     k_init_small(const double *__restrict__ partW, const double *__restrict__ partV, int nb,
@@ -1204,7 +1317,8 @@ __global__ void k_reset_scalars(FitScalars *sc) {
     sc->iter = 0;
     sc->fail_iter = INT_MAX;
     sc->rank_deficient = 0;
-    sc->rank_def_cur = 0;
+    sc->rank_def_slot[0] = 0;
+    sc->rank_def_slot[1] = 0;
   }
 }
 
@@ -1245,11 +1359,11 @@ static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
   if (p->l > 0)
     k_pass1<RT, true><<<grid, block, lds, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
                                               p->col, p->val, p->C, p->Vp, p->J, p->R, p->l,
-                                              p->T);
+                                              p->T, p->FV);
   else
     k_pass1<RT, false><<<grid, block, lds, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
                                                p->col, p->val, p->C, p->Vp, p->J, p->R, p->l,
-                                               p->T);
+                                               p->T, p->FV);
 }
 
 template <int RT>
@@ -1323,37 +1437,56 @@ copa_status harvest_timing(copa_plan *p) {
   return COPA_OK;
 }
 
+static FitArgs fit_args(const copa_plan *p) {
+  const copa_options &o = p->opt;
+  FitArgs fa;
+  fa.vpart = p->vpart;
+  fa.vtvpart = gram_slot(p, kSlotVtV);
+  fa.nvb = p->n_vblocks;
+  fa.wl1part = p->wpart;
+  fa.nwb = (int)std::max<int64_t>(1, (p->K + 63) / 64);
+  fa.normX2 = p->normX2;
+  fa.J = p->J;
+  fa.proxV = o.prox_V;
+  fa.proxW = o.prox_W;
+  fa.proxH = o.prox_H;
+  fa.lamV = o.lambda_V;
+  fa.lamW = o.lambda_W;
+  fa.lamH = o.lambda_H;
+  return fa;
+}
+
+// Outer iteration number it of the current chunk (the device history index).
 template <int R>
-static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
+static void iteration_r(copa_plan *p, const copa_state *st, int it, hipStream_t s) {
   const copa_options &o = p->opt;
   const int64_t K = p->K;
-  constexpr int RR = R * R;
+  int32_t *rank_def = &p->scal->rank_def_slot[it & 1];
   timed(p, s, kidPass1, [&] { RT_SWITCH(p->tiles.rt, launch_pass1_rt, p, st->V, s); });
   if (K > 0)
     timed(p, s, kidProcrustes, [&] {
       if constexpr (R <= 16) {
         if (p->l > 0) {
           k_procrustes_s<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-              K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol,
-              &p->scal->rank_def_cur);
+              K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, rank_def);
           return;
         }
       }
       k_procrustes<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-          K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W, o.rank_rtol,
-          &p->scal->rank_def_cur);
+          K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W, o.rank_rtol, rank_def);
       if (p->n_big > 0)
         k_procrustes_wave<R><<<(unsigned)p->n_big, 64, 0, s>>>(
-            p->big_list, p->n_big, p->subj, p->T, p->Q, st->H, st->W, o.rank_rtol,
-            &p->scal->rank_def_cur);
+            p->big_list, p->n_big, p->subj, p->T, p->Q, st->H, st->W, o.rank_rtol, rank_def);
     });
   timed(p, s, kidGramFH, [&] {
-    gram<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, kSlotFH, nullptr, 0, 0, s);
+    // one more block of the same launch takes the FIT of the previous outer iteration
+    const FitArgs fa = fit_args(p);
+    gram_fit<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, kSlotFH, it > 0, fa,
+                it - 1, st->H, s);
   });
   timed(p, s, kidModeH, [&] {
-    k_mode_H<R><<<1, 256, 0, s>>>(gram_total(p, kSlotFH), 1, p->small, p->modes, p->scal, st->H,
-                                  st->D_H, o.prox_H, o.lambda_H, o.inner_iters, p->FV,
-                                  p->J * R);
+    k_mode_H<R><<<1, 256, 0, s>>>(it, gram_total(p, kSlotFH), p->small, p->modes, p->scal,
+                                  st->H, st->D_H, o.prox_H, o.lambda_H, o.inner_iters);
   });
   const unsigned nwb = (unsigned)std::max<int64_t>(1, (K + 63) / 64);
   timed(p, s, kidWadmm, [&] {
@@ -1367,11 +1500,9 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   timed(p, s, kidPass2, [&] { RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s); });
   timed(p, s, kidVadmm, [&] {
     k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(
-        p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, (p->tiles.rt + 3) & ~3,
-        gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), 1, p->small, p->scal, o.prox_V,
-        o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV), p->wpart, (int)nwb, st->H,
-        p->normX2,
-        o.prox_H, o.lambda_H, o.prox_W, o.lambda_W, p->gcount + 6);
+        it, p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, (p->tiles.rt + 3) & ~3,
+        gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->scal, o.prox_V,
+        o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV));
   });
 }
 
@@ -1390,10 +1521,22 @@ static void init_grams_r(copa_plan *p, const copa_state *st, hipStream_t s) {
                                     p->small);
 }
 
-copa_status launch_iteration(copa_plan *p, const copa_state *st, hipStream_t s) {
+copa_status launch_iteration(copa_plan *p, const copa_state *st, int it, hipStream_t s) {
   switch (p->R) {
 #define CASE(r) \
-  case r: iteration_r<r>(p, st, s); break;
+  case r: iteration_r<r>(p, st, it, s); break;
+    COPA_R_LIST(CASE)
+#undef CASE
+    default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
+  }
+  COPA_HIP(hipGetLastError());
+  return COPA_OK;
+}
+
+copa_status launch_fit(copa_plan *p, const copa_state *st, int it, hipStream_t s) {
+  switch (p->R) {
+#define CASE(r) \
+  case r: k_fit<r><<<1, 256, 0, s>>>(fit_args(p), it, st->H, p->small, p->scal); break;
     COPA_R_LIST(CASE)
 #undef CASE
     default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
@@ -1455,9 +1598,12 @@ copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Q
     const int chunk = std::min(iters - done, p->timing ? kTimingChunk : kHistCap);
     if (done > 0) k_reset_scalars<<<1, 64, 0, s>>>(p->scal);
     for (int t = 0; t < chunk; ++t) {
-      cs = launch_iteration(p, st, s);
+      cs = launch_iteration(p, st, t, s);
       if (cs != COPA_OK) return cs;
     }
+    // the FIT of the chunk's last iteration (the others are taken by the next mode-H launch)
+    cs = launch_fit(p, st, chunk - 1, s);
+    if (cs != COPA_OK) return cs;
     COPA_HIP(hipMemcpyAsync(&hs, p->scal, sizeof(FitScalars), hipMemcpyDeviceToHost, s));
     COPA_HIP(hipStreamSynchronize(s));
     if (p->timing) {

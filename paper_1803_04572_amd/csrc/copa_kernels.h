@@ -59,29 +59,24 @@ __device__ void block_reduce_parts(const double *__restrict__ part, int nb, doub
 // blocks of the same launch would take a device-scope release (an L2 write-back) per block.
 typedef double dbl4_t __attribute__((ext_vector_type(4)));
 
+// Block `bid` of `nblk` blocks: the partial of its share of the rows into part[bid].
 template <int R, int WSEL>
-__global__ void __launch_bounds__(256)
-    k_rows_gram(const float *__restrict__ A, const float *__restrict__ B, int64_t rows,
-                const float *__restrict__ W, int slot_rows, const int32_t *__restrict__ rowsubj,
-                double *__restrict__ part, const float *__restrict__ A2, int64_t rows2,
-                double *__restrict__ part2) {
+__device__ __forceinline__ void rows_gram_block(const float *__restrict__ A,
+                                                const float *__restrict__ B, int64_t rows,
+                                                const float *__restrict__ W, int slot_rows,
+                                                const int32_t *__restrict__ rowsubj,
+                                                double *__restrict__ part, int bid, int nblk) {
   constexpr int NT = (R + 15) / 16;
   constexpr int RP = NT * 16;
   constexpr int RR = R * R;
   constexpr int BATCH = NT >= 2 ? 8 : 16;  // 4-row steps in flight per wave (registers)
   __shared__ double sacc[RP * RP];
-  if (WSEL == 0 && blockIdx.y == 1) {
-    A = A2;
-    B = A2;
-    rows = rows2;
-    part = part2;
-  }
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
   const int m = lane & 15, kk = lane >> 4;
   for (int e = t; e < RP * RP; e += blockDim.x) sacc[e] = 0.0;
   const int64_t units = (rows + 4 * BATCH - 1) / (4 * BATCH);
-  const int64_t upb = (units + gridDim.x - 1) / gridDim.x;
-  const int64_t u0 = blockIdx.x * upb;
+  const int64_t upb = (units + nblk - 1) / nblk;
+  const int64_t u0 = bid * upb;
   const int64_t u1 = u0 + upb < units ? u0 + upb : units;
   dbl4_t acc[NT][NT], acc2[NT][NT];
 #pragma unroll
@@ -160,7 +155,19 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
   }
   for (int e = t; e < RR; e += blockDim.x)
-    part[(int64_t)blockIdx.x * RR + e] = sacc[(e / R) * RP + e % R];
+    part[(int64_t)bid * RR + e] = sacc[(e / R) * RP + e % R];
+}
+
+template <int R, int WSEL>
+__global__ void __launch_bounds__(256)
+    k_rows_gram(const float *__restrict__ A, const float *__restrict__ B, int64_t rows,
+                const float *__restrict__ W, int slot_rows, const int32_t *__restrict__ rowsubj,
+                double *__restrict__ part, const float *__restrict__ A2, int64_t rows2,
+                double *__restrict__ part2) {
+  if (WSEL == 0 && blockIdx.y == 1)
+    rows_gram_block<R, 0>(A2, A2, rows2, W, slot_rows, rowsubj, part2, blockIdx.x, gridDim.x);
+  else
+    rows_gram_block<R, WSEL>(A, B, rows, W, slot_rows, rowsubj, part, blockIdx.x, gridDim.x);
 }
 
 // total[e] = sum_b part[b * RR + e] over the nb block partials in a fixed order: one block per

@@ -515,7 +515,11 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   }
   COPA_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
   p->gmaxnb = 2 * std::max(1, p->n_cu);
-  p->n_vblocks = (int)std::max<int64_t>(1, (p->J + 255) / 256);
+  {
+    // V update: 4 wavefronts per block, 64 / R rows per wavefront (R lanes per row)
+    const int64_t rb = 4 * (kWave / R);
+    p->n_vblocks = (int)std::max<int64_t>(1, std::min<int64_t>((p->J + rb - 1) / rb, 4 * std::max(1, p->n_cu)));
+  }
   p->gstride = (std::max<int64_t>(p->gmaxnb, p->n_vblocks) + 1) * R * R;
   COPA_TRY(dalloc(&p->gpart, (size_t)kGramSlots * p->gstride));
   COPA_TRY(dalloc(&p->gcount, 8));
