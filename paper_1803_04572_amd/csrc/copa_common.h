@@ -105,6 +105,8 @@ struct copa_plan {
   bool p2c = false;
   int nchunks = 0;
   int32_t *cptr = nullptr;   // [nchunks+1] nonzero offsets of the chunks
+  int32_t *crow = nullptr;   // [nchunks+1] first visit row of each chunk
+  int32_t *cinfo = nullptr;  // [nchunks x 2] first subject and subject count of each chunk
   int32_t *wsplit = nullptr; // [nchunks x 9] per-wave slices of each chunk (feature boundaries)
   uint32_t *pkey = nullptr;  // [nnz] feature << 16 | row within chunk
   float *pval = nullptr;     // [nnz]

@@ -231,11 +231,7 @@ __global__ void k_zero_f(float *x, int64_t n) {
 template <int RT>
 static void scatter_rt(copa_plan *p, const float *U, float *F, hipStream_t s) {
   if (p->p2c) {
-    dim3 grid((unsigned)std::min(p->nchunks, 2 * std::max(1, p->n_cu)), (unsigned)p->tiles.nt),
-        block(512);
-    size_t lds = ((size_t)p->J * RT + (size_t)kChunkRows * RT) * sizeof(float);
-    k_pass2c<RT, false><<<grid, block, lds, s>>>(p->nchunks, p->S, p->wsplit, p->pkey, p->pval,
-                                                 p->rowsubj, p->C, U, p->J, p->R, 0, F);
+    launch_pass2c<RT, false>(p, U, F, s);
   } else {
     dim3 grid((unsigned)((p->n_waves + 3) / 4), (unsigned)p->tiles.nt), block(256);
     k_pass2<RT, false><<<grid, block, 0, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,

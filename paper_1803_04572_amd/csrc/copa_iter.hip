@@ -1369,17 +1369,10 @@ static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
 template <int RT>
 static void launch_pass2_rt(copa_plan *p, hipStream_t s) {
   if (p->p2c) {
-    dim3 grid((unsigned)std::min(p->nchunks, 2 * std::max(1, p->n_cu)), (unsigned)p->tiles.nt),
-        block(512);
-    size_t lds = ((size_t)p->J * RT + (size_t)kChunkRows * RT) * sizeof(float);
     if (p->l > 0)
-      k_pass2c<RT, true><<<grid, block, lds, s>>>(p->nchunks, p->S, p->wsplit, p->pkey, p->pval,
-                                                  p->rowsubj, p->C, p->M, p->J, p->R, p->l,
-                                                  p->FV);
+      launch_pass2c<RT, true>(p, p->M, p->FV, s);
     else
-      k_pass2c<RT, false><<<grid, block, lds, s>>>(p->nchunks, p->S, p->wsplit, p->pkey, p->pval,
-                                                   p->rowsubj, p->C, p->M, p->J, p->R, p->l,
-                                                   p->FV);
+      launch_pass2c<RT, false>(p, p->M, p->FV, s);
   } else {
     dim3 grid((unsigned)((p->n_waves + 3) / 4), (unsigned)p->tiles.nt), block(256);
     if (p->l > 0)

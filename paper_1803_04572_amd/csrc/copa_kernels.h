@@ -218,58 +218,98 @@ inline void gram(copa_plan *p, const float *A, const float *B, int64_t rows, con
 
 // ======================================================================= streaming pass 2
 // F_V(j,:) += x_ij * u_i with u_i = c_i M_k (smoothed: basis row times Q_k H S_k) or the M row of
-// visit i (plain). Chunked form: for every block of kChunkRows visit rows the plan stores the
-// chunk's nonzeros sorted by feature (key = feature << 16 | row in chunk) and 9 split points
-// that cut the sorted list into 8 slices on feature boundaries, one per wave. A block puts the
-// chunk's u rows in LDS; each lane sums a contiguous run of its wave's slice feature by feature;
-// a segmented scan over the lanes joins runs that share a feature, so every feature is added to
-// the block's LDS copy of F_V by exactly one lane - no LDS atomics. The block's F_V tile goes to
-// the global F_V with one atomic add per entry at the end.
+// visit i (plain). Chunked form: the plan cuts the visit rows into chunks of at most kChunkRows
+// rows (and, smoothed, at most kChunkRows / l subjects), and stores each chunk's nonzeros sorted
+// by feature (key = feature << 16 | row in chunk) with 9 split points that cut the sorted list
+// into 8 slices on feature boundaries, one per wave. Per chunk a block issues every global load
+// at once: the chunk's M rows (one contiguous block, staged in LDS), each row's basis row and
+// subject, and each lane's first 8 keys and values; the next chunk's bounds are prefetched.
+// Then the u rows are formed in LDS; each lane sums a contiguous run of its wave's slice feature
+// by feature; a segmented scan over the lanes joins runs that share a feature, so every feature
+// is added to the block's LDS copy of F_V by exactly one lane - no LDS atomics. The block's F_V
+// tile goes to the global F_V with one atomic add per entry at the end.
 template <int RT, bool SMOOTH>
 __global__ void __launch_bounds__(512)
-    k_pass2c(int nchunks, int64_t S, const int32_t *__restrict__ wsplit,
-             const uint32_t *__restrict__ pkey, const float *__restrict__ pval,
-             const int32_t *__restrict__ rowsubj, const float *__restrict__ C,
-             const float *__restrict__ M, int64_t J, int R, int l, float *__restrict__ FV) {
+    k_pass2c(int nchunks, const int32_t *__restrict__ crow, const int32_t *__restrict__ cinfo,
+             const int32_t *__restrict__ wsplit, const uint32_t *__restrict__ pkey,
+             const float *__restrict__ pval, const int32_t *__restrict__ rowsubj,
+             const float *__restrict__ C, const float *__restrict__ M, int64_t J, int R, int l,
+             float *__restrict__ FV) {
   extern __shared__ float4 smem4[];
   float *sF = reinterpret_cast<float *>(smem4);
-  float *sU = sF + J * RT;
+  float *sU = sF + J * RT;  // u rows of the chunk; first holds the chunk's M block
   const int c0 = blockIdx.y * RT;
   const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wave = t >> 6;
   for (int64_t e = t; e < J * RT; e += nt) sF[e] = 0.0f;
-  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const int64_t r0 = (int64_t)c * kChunkRows;
-    const int n = (int)((S - r0) < kChunkRows ? (S - r0) : kChunkRows);
-    __syncthreads();
-    for (int q = t; q < n; q += nt) {
-      const int64_t i = r0 + q;
-      float u[RT];
+  int nr0 = 0, nr1 = 0, nk0 = 0, nns = 0, ns0 = 0, ns1 = 0;
+  auto fetch = [&](int cc) {
+    if (cc < nchunks) {
+      nr0 = crow[cc];
+      nr1 = crow[cc + 1];
       if constexpr (SMOOTH) {
-        const int64_t k = rowsubj[i];
-        const float4 *c4 = reinterpret_cast<const float4 *>(C + i * kLMax);
-        const float4 ca = c4[0], cb = c4[1];
-        const float cr[kLMax] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
-#pragma unroll
-        for (int r = 0; r < RT; ++r) u[r] = 0.0f;
-        // basis columns at or past l are zero: clamp the M row and column instead of branching
-#pragma unroll
-        for (int a = 0; a < kLMax; ++a) {
-          const float *mr = M + (k * l + (a < l ? a : l - 1)) * R;
-#pragma unroll
-          for (int r = 0; r < RT; ++r) u[r] += cr[a] * mr[c0 + r < R ? c0 + r : R - 1];
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < RT; ++r) u[r] = M[i * R + (c0 + r < R ? c0 + r : R - 1)];
+        nk0 = cinfo[2 * cc];
+        nns = cinfo[2 * cc + 1];
       }
-#pragma unroll
-      for (int r = 0; r < RT; ++r) sU[q * RT + r] = u[r];
+      ns0 = wsplit[cc * 9 + wave];
+      ns1 = wsplit[cc * 9 + wave + 1];
     }
-    __syncthreads();
-    const int s0 = wsplit[c * 9 + wave], s1 = wsplit[c * 9 + wave + 1];
+  };
+  fetch(blockIdx.x);
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int r0 = nr0, n = nr1 - nr0, k0 = nk0, nsub = nns, s0 = ns0, s1 = ns1;
+    __syncthreads();  // the previous chunk is done with sU
+    // ---- every global load of this chunk
     const int per = (s1 - s0 + 63) >> 6;
     const int a = s0 + lane * per;
     const int b = a + per < s1 ? a + per : s1;
+    uint32_t kv[8];
+    float xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int ec = a + u < b ? a + u : 0;
+      kv[u] = pkey[ec];
+      xv[u] = pval[ec];
+    }
+    const int tc = t < n ? t : 0;
+    float cr[kLMax];
+    int kl = 0;
+    float u[RT];
+    if constexpr (SMOOTH) {
+      const int64_t i = r0 + tc;
+      kl = rowsubj[i] - k0;
+      const float4 *c4 = reinterpret_cast<const float4 *>(C + i * kLMax);
+      const float4 ca = c4[0], cb = c4[1];
+      cr[0] = ca.x; cr[1] = ca.y; cr[2] = ca.z; cr[3] = ca.w;
+      cr[4] = cb.x; cr[5] = cb.y; cr[6] = cb.z; cr[7] = cb.w;
+      const int nm = nsub * l * RT;
+      const float *Mb = M + (int64_t)k0 * l * R + c0;
+      for (int e = t; e < nm; e += nt) {
+        const int q = e / RT, r = e - q * RT;
+        sU[e] = Mb[(int64_t)q * R + (c0 + r < R ? r : R - 1 - c0)];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) u[r] = M[(int64_t)(r0 + tc) * R + (c0 + r < R ? c0 + r : R - 1)];
+    }
+    fetch(c + gridDim.x);
+    if constexpr (SMOOTH) {
+      __syncthreads();
+      // basis columns at or past l are zero: clamp the M row instead of branching
+#pragma unroll
+      for (int r = 0; r < RT; ++r) u[r] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < kLMax; ++q) {
+        const float *mr = sU + (kl * l + (q < l ? q : l - 1)) * RT;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) u[r] += cr[q] * mr[r];
+      }
+      __syncthreads();
+    }
+    if (t < n) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) sU[t * RT + r] = u[r];
+    }
+    __syncthreads();
     float acc[RT], head[RT];
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
@@ -278,38 +318,38 @@ __global__ void __launch_bounds__(512)
     }
     int cur = -1, hkey = -1, nseg = 0;
     for (int eb = a; eb < b; eb += 8) {
-      uint32_t kv[8];
-      float xv[8];
+      if (eb > a) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int ec = eb + u < b ? eb + u : a;
-        kv[u] = pkey[ec];
-        xv[u] = pval[ec];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-      if (eb + u >= b) break;
-      const uint32_t key = kv[u];
-      const int j = (int)(key >> 16);
-      const float x = xv[u];
-      const float *ur = sU + (key & 0xffffu) * RT;
-      if (j != cur) {
-        if (nseg == 1) {
-          hkey = cur;
-#pragma unroll
-          for (int r = 0; r < RT; ++r) head[r] = acc[r];
-        } else if (nseg > 1) {
-          // a segment that starts and ends inside this lane's run: no other lane has it
-#pragma unroll
-          for (int r = 0; r < RT; ++r) sF[cur * RT + r] += acc[r];
+        for (int q = 0; q < 8; ++q) {
+          const int ec = eb + q < b ? eb + q : a;
+          kv[q] = pkey[ec];
+          xv[q] = pval[ec];
         }
-        cur = j;
-        ++nseg;
-#pragma unroll
-        for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
       }
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[r] += x * ur[r];
+      for (int q = 0; q < 8; ++q) {
+        if (eb + q >= b) break;
+        const uint32_t key = kv[q];
+        const int j = (int)(key >> 16);
+        const float x = xv[q];
+        const float *ur = sU + (key & 0xffffu) * RT;
+        if (j != cur) {
+          if (nseg == 1) {
+            hkey = cur;
+#pragma unroll
+            for (int r = 0; r < RT; ++r) head[r] = acc[r];
+          } else if (nseg > 1) {
+            // a segment that starts and ends inside this lane's run: no other lane has it
+#pragma unroll
+            for (int r = 0; r < RT; ++r) sF[cur * RT + r] += acc[r];
+          }
+          cur = j;
+          ++nseg;
+#pragma unroll
+          for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[r] += x * ur[r];
       }
     }
     // tail segment (cur, acc); the first key of this lane's run is hkey (several segments) or cur
@@ -356,6 +396,17 @@ __global__ void __launch_bounds__(512)
 }
 
 // Unchunked fallback (features >= 2^16): global atomics per nonzero.
+// Launches k_pass2c on the plan's chunks: SMOOTH forms u rows from the basis and the M rows of
+// each chunk's subjects; otherwise u_i is row i of Mrows (R wide).
+template <int RT, bool SMOOTH>
+inline void launch_pass2c(const copa_plan *p, const float *Mrows, float *F, hipStream_t s) {
+  const dim3 grid((unsigned)std::min(p->nchunks, 2 * std::max(1, p->n_cu)), (unsigned)p->tiles.nt);
+  const size_t lds = ((size_t)p->J * RT + (size_t)kChunkRows * RT) * sizeof(float);
+  k_pass2c<RT, SMOOTH><<<grid, 512, lds, s>>>(p->nchunks, p->crow, p->cinfo, p->wsplit, p->pkey,
+                                             p->pval, p->rowsubj, p->C, Mrows, p->J, p->R,
+                                             SMOOTH ? p->l : 0, F);
+}
+
 template <int RT, bool SMOOTH>
 __global__ void __launch_bounds__(256)
     k_pass2(const WaveEntry *__restrict__ waves, int n_waves, const int32_t *__restrict__ order,

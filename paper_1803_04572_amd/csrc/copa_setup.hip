@@ -307,9 +307,33 @@ static copa_status build_sorted_chunks(const copa_tensor *X, copa_plan *p, hipSt
   COPA_HIP(hipMemcpyAsync(cl.data(), X->col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   COPA_HIP(hipMemcpyAsync(vl.data(), X->val, nnz * sizeof(float), hipMemcpyDeviceToHost, s));
   COPA_HIP(hipStreamSynchronize(s));
-  const int nch = (int)((S + kChunkRows - 1) / kChunkRows);
+  // chunks of at most kChunkRows rows and, smoothed, at most kChunkRows / l subjects (so that the
+  // chunk's M rows fit the LDS space of its u rows)
+  const int64_t K = p->K;
+  std::vector<int64_t> sp(K + 1);
+  COPA_HIP(hipMemcpyAsync(sp.data(), X->subj_ptr, (K + 1) * sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipStreamSynchronize(s));
+  const int64_t msub = p->l > 0 ? kChunkRows / p->l : K + 1;
+  std::vector<int32_t> crow, cinf;
+  {
+    int64_t r = 0, k = 0;
+    while (r < S) {
+      while (sp[k + 1] <= r) ++k;  // subject of row r
+      int64_t end = std::min<int64_t>(r + kChunkRows, S);
+      if (k + msub < K) end = std::min<int64_t>(end, sp[k + msub]);
+      int64_t klast = k;
+      while (sp[klast + 1] < end) ++klast;  // subject of row end - 1
+      crow.push_back((int32_t)r);
+      cinf.push_back((int32_t)k);
+      cinf.push_back((int32_t)(klast - k + 1));
+      r = end;
+    }
+    crow.push_back((int32_t)S);
+  }
+  const int nch = (int)crow.size() - 1;
   std::vector<int32_t> cp(nch + 1);
-  for (int c = 0; c <= nch; ++c) cp[c] = (int32_t)rp[std::min<int64_t>((int64_t)c * kChunkRows, S)];
+  for (int c = 0; c <= nch; ++c) cp[c] = (int32_t)rp[crow[c]];
   std::vector<uint32_t> key(nnz);
   std::vector<float> sv(nnz);
   const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -318,7 +342,7 @@ static copa_status build_sorted_chunks(const copa_tensor *X, copa_plan *p, hipSt
     pool.emplace_back([&, w]() {
       std::vector<uint64_t> tmp;
       for (int c = (int)w; c < nch; c += (int)nthreads) {
-        const int64_t r0 = (int64_t)c * kChunkRows, r1 = std::min<int64_t>(r0 + kChunkRows, S);
+        const int64_t r0 = crow[c], r1 = crow[c + 1];
         const int64_t e0 = rp[r0];
         tmp.clear();
         for (int64_t i = r0; i < r1; ++i)
@@ -354,6 +378,10 @@ static copa_status build_sorted_chunks(const copa_tensor *X, copa_plan *p, hipSt
   COPA_TRY(dalloc(&p->wsplit, (size_t)nch * 9));
   COPA_HIP(hipMemcpyAsync(p->wsplit, ws.data(), ws.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   COPA_TRY(dalloc(&p->cptr, nch + 1));
+  COPA_TRY(dalloc(&p->crow, nch + 1));
+  COPA_TRY(dalloc(&p->cinfo, (size_t)2 * nch));
+  COPA_HIP(hipMemcpyAsync(p->crow, crow.data(), (nch + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  COPA_HIP(hipMemcpyAsync(p->cinfo, cinf.data(), 2 * nch * sizeof(int32_t), hipMemcpyHostToDevice, s));
   COPA_TRY(dalloc(&p->pkey, nnz));
   COPA_TRY(dalloc(&p->pval, nnz));
   COPA_HIP(hipMemcpyAsync(p->cptr, cp.data(), (nch + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -425,6 +453,10 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   if (nnz > 0) {
     COPA_HIP(hipMemcpyAsync(p->col, X->col, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     COPA_HIP(hipMemcpyAsync(p->val, X->val, nnz * sizeof(float), hipMemcpyDeviceToDevice, s));
+  } else {
+    // kernels read entry 0 as the clamped target of masked loads: keep it a valid feature
+    COPA_HIP(hipMemsetAsync(p->col, 0, sizeof(int32_t), s));
+    COPA_HIP(hipMemsetAsync(p->val, 0, sizeof(float), s));
   }
   {
     constexpr int nb = 512;
@@ -552,7 +584,7 @@ using namespace copa;
 static void free_plan(copa_plan *p) {
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->C, p->rk, p->Ew, p->order, p->waves,
-                  p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->cptr, p->wsplit, p->pkey, p->pval, p->Vp,
+                  p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->cptr, p->crow, p->cinfo, p->wsplit, p->pkey, p->pval, p->Vp,
                   p->gpart, p->gcount,
                   p->vpart, p->wpart, p->small, p->modes, p->scal, p->dloss, p->gradbuf,
                   p->lpart};
