@@ -178,4 +178,26 @@ __device__ __forceinline__ double prox_sel(double x, int kind, double lam, doubl
 
 __device__ __forceinline__ float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, kWave); }
 
+// v + (v of lane ^ M) for aligned lane groups, when the groups of M lanes below have already been
+// summed this way (then every lane of a 2M group ends with the same total): quad permutes for
+// M = 1, 2, half-row and row mirrors for M = 4, 8 (DPP, no LDS), swizzle for 16, permute for 32.
+template <int M>
+__device__ __forceinline__ float xor_step_sum(float v) {
+  const int x = __float_as_int(v);
+  int y;
+  if constexpr (M == 1)
+    y = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  else if constexpr (M == 2)
+    y = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  else if constexpr (M == 4)
+    y = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  else if constexpr (M == 8)
+    y = __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false);  // row_mirror
+  else if constexpr (M == 16)
+    y = __builtin_amdgcn_ds_swizzle(x, 0x401F);  // xor 16 within 32 lanes
+  else
+    y = __float_as_int(__shfl_xor(v, 32, kWave));
+  return v + __int_as_float(y);
+}
+
 }  // namespace copa

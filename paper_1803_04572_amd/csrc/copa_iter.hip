@@ -18,6 +18,7 @@
 //   v_admm      inner ADMM on V rows, FIT/penalty/sparsity partials
 //   gram(V), finalize  V^T V, FIT = 1 - (|X|^2 - 2<F_V,V> + <Psi, V^T V>) / |X|^2
 #include <climits>
+#include <type_traits>
 
 #include "copa_common.h"
 #include "copa_kernels.h"
@@ -42,7 +43,7 @@ Tiles choose_tiles(int R, int64_t J, int lds_limit) {
   for (;; ++nt) {
     int rt = (R + nt - 1) / nt;
     int rtp = (rt + 3) & ~3;
-    if ((int64_t)J * rtp * 4 <= lds_limit || rt == 1) return Tiles{nt, rt};
+    if ((int64_t)J * rtp * 4 + 16 <= lds_limit || rt == 1) return Tiles{nt, rt};
   }
 }
 
@@ -80,8 +81,10 @@ __global__ void __launch_bounds__(256)
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
+        // out-of-range lanes write the spare slot after the tile (no branch, so that the 8 loads
+        // above stay in flight together)
         const int64_t e = e0 + u * blockDim.x + threadIdx.x;
-        if (e < n4) smem4[e] = tmp[u];
+        smem4[e < n4 ? e : n4] = tmp[u];
       }
     }
   }
@@ -140,12 +143,20 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
           for (int r = 0; r < RT; ++r) acc[a][r] += c[a] * t[r];
       }
-      for (int m = 1; m < G; m <<= 1) {
+      // sum over the subject's G lanes (wave-uniform G; every lane ends with the totals)
+      auto step = [&](auto mc) {
+        constexpr int Mv = decltype(mc)::value;
 #pragma unroll
         for (int a = 0; a < kLMax; ++a)
 #pragma unroll
-          for (int r = 0; r < RT; ++r) acc[a][r] += shfl_xor_f(acc[a][r], m);
-      }
+          for (int r = 0; r < RT; ++r) acc[a][r] = xor_step_sum<Mv>(acc[a][r]);
+      };
+      if (G > 1) step(std::integral_constant<int, 1>{});
+      if (G > 2) step(std::integral_constant<int, 2>{});
+      if (G > 4) step(std::integral_constant<int, 4>{});
+      if (G > 8) step(std::integral_constant<int, 8>{});
+      if (G > 16) step(std::integral_constant<int, 16>{});
+      if (G > 32) step(std::integral_constant<int, 32>{});
       if (active) {
         float *dst = T + (int64_t)k * l * R + c0;
 #pragma unroll
@@ -1352,7 +1363,7 @@ __global__ void __launch_bounds__(256)
 template <int RT>
 static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
   constexpr int RTP = (RT + 3) & ~3;
-  size_t lds = (size_t)p->J * RTP * sizeof(float);
+  size_t lds = (size_t)p->J * RTP * sizeof(float) + sizeof(float4);  // + the spare slot
   const int per_cu = std::max(1, std::min(4, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
   const int nb = std::max(1, std::min((p->n_waves + 3) / 4, p->n_cu * per_cu));
   dim3 grid((unsigned)nb, (unsigned)p->tiles.nt), block(256);

@@ -531,7 +531,7 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   // ---- iteration buffers
   const int R = p->R;
   p->tiles = choose_tiles(R, p->J, p->lds_limit);
-  if ((int64_t)p->J * ((p->tiles.rt + 3) & ~3) * 4 > p->lds_limit) {
+  if ((int64_t)p->J * ((p->tiles.rt + 3) & ~3) * 4 + 16 > p->lds_limit) {
     set_error("J too large for the LDS-staged factor tile of this build");
     return COPA_EUNSUPPORTED;
   }
