@@ -105,20 +105,39 @@ __global__ void __launch_bounds__(256)
       for (int a = 0; a < kLMax; ++a)
 #pragma unroll
         for (int r = 0; r < RT; ++r) acc[a][r] = 0.0f;
-      for (int i = r0 + sub; i < r1; i += G) {
+      // two-stage pipeline over this lane's rows: the next row's bounds and basis row are
+      // requested while the current row's nonzeros are loaded and used
+      int i = r0 + sub;
+      int e0n = 0, e1n = 0;
+      float4 can = make_float4(0.f, 0.f, 0.f, 0.f), cbn = can;
+      if (i < r1) {
+        e0n = row[i];
+        e1n = row[i + 1];
         const float4 *c4 = reinterpret_cast<const float4 *>(C + (int64_t)i * kLMax);
-        const float4 ca = c4[0], cb = c4[1];
-        float t[RTP];
+        can = c4[0];
+        cbn = c4[1];
+      }
+      for (; i < r1; i += G) {
+        const int e0 = e0n, e1 = e1n;
+        const float4 ca = can, cb = cbn;
+        {
+          const int in = i + G < r1 ? i + G : r1 - 1;  // always a valid row of this subject
+          e0n = row[in];
+          e1n = row[in + 1];
+          const float4 *c4 = reinterpret_cast<const float4 *>(C + (int64_t)in * kLMax);
+          can = c4[0];
+          cbn = c4[1];
+        }
+        float t[RT];
 #pragma unroll
-        for (int r = 0; r < RTP; ++r) t[r] = 0.0f;
-        const int e0 = row[i], e1 = row[i + 1];
+        for (int r = 0; r < RT; ++r) t[r] = 0.0f;
         for (int eb = e0; eb < e1; eb += 8) {
           int cj[8];
           float xv[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const bool ok = eb + u < e1;
-            const int ec = ok ? eb + u : e0;
+            const unsigned ec = (unsigned)(ok ? eb + u : e0);
             cj[u] = col[ec];
             const float x = val[ec];
             xv[u] = ok ? x : 0.0f;
@@ -126,14 +145,14 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const float x = xv[u];
-            const float4 *v4 = reinterpret_cast<const float4 *>(sV + (int64_t)cj[u] * RTP);
+            const float4 *v4 = reinterpret_cast<const float4 *>(sV + cj[u] * RTP);
 #pragma unroll
             for (int q = 0; q < RTP / 4; ++q) {
               const float4 v = v4[q];
-              t[4 * q + 0] += x * v.x;
-              t[4 * q + 1] += x * v.y;
-              t[4 * q + 2] += x * v.z;
-              t[4 * q + 3] += x * v.w;
+              if (4 * q + 0 < RT) t[4 * q + 0] += x * v.x;
+              if (4 * q + 1 < RT) t[4 * q + 1] += x * v.y;
+              if (4 * q + 2 < RT) t[4 * q + 2] += x * v.z;
+              if (4 * q + 3 < RT) t[4 * q + 3] += x * v.w;
             }
           }
         }
