@@ -37,21 +37,25 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(coh, R, l, nfv):
+def algorithmic_bytes(coh, R, l, compact):
     """Bytes each kernel of one outer iteration must move at least (inputs read once, outputs
-    written once), for FP32 values, int32 indices and the l-wide basis rows of the smoothed path.
-    rows = projected rows (K*l smoothed, S plain)."""
+    written once), for FP32 factors. Pass 1 streams the CSR nonzeros (4 B each in the lossless
+    compact form: 16-bit feature id + bfloat16 value; else 8 B) with 4-B row offsets; pass 2 streams
+    the feature-sorted (key, value) pairs (8 B) and one subject id per row; smoothed passes read the
+    l basis coefficients of each row. rows = projected rows (K*l smoothed, S plain)."""
     K, J, S, nnz = coh.K, coh.J, coh.S, coh.nnz
     rows = K * l if l > 0 else S
-    x_stream = nnz * 8 + (S + 1) * 4 + (K + 1) * 4 + (S * l * 4 if l > 0 else 0)
+    basis = S * l * 4 if l > 0 else 0
+    x1 = nnz * (4 if compact else 8) + (S + 1) * 4 + (K + 1) * 4 + basis
+    x2 = nnz * 8 + S * 4 + basis
     return {
-        "pass1": x_stream + J * R * 4 + rows * R * 4,
+        "pass1": x1 + J * R * 4 + rows * R * 4,
         "procrustes": rows * R * 4 * 2 + K * R * 4 + R * R * 4,
         "gram_FH": rows * R * 4 * 2 + K * R * 4,
         "mode_H": R * R * 8 * 3,
         "w_admm": rows * R * 4 * 3 + K * R * 4 * 5,
         "gram_WM": K * R * 4 + rows * R * 4,
-        "pass2": x_stream + rows * R * 4 + K * R * 4 + J * R * 4,
+        "pass2": x2 + rows * R * 4 + J * R * 4,
         "v_admm": J * R * 4 * 5,
     }
 
@@ -128,7 +132,8 @@ def main():
     timing = plan.read_timing()
     plan.set_timing(False)
 
-    abytes = algorithmic_bytes(coh, R, l, plan)
+    compact = plan.query("compact")
+    abytes = algorithmic_bytes(coh, R, l, compact)
     per_kernel = {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in timing.items()
                   if n > 0}
     for k, v in per_kernel.items():
@@ -173,7 +178,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['name']}", "K": coh.K, "J": coh.J,
                    "R": R, "l": l, "S": coh.S, "nnz": coh.nnz, "inner_iters": cfg["inner"],
-                   "constraints": "H free, W nonneg, V l1 (lambda 0.1), cubic spline smoothing"},
+                   "constraints": "H free, W nonneg, V l1 (lambda 0.1), cubic spline smoothing",
+                   "nonzeros": "compact 4-byte (lossless)" if compact else "fp32 8-byte"},
         "fit": rep["fit"],
         "fit_after_timed_steps": rep_t["fit"],
         "mttkrp_hbm": mttkrp,

@@ -166,6 +166,17 @@ copa_status copa_set_timing(copa_plan *plan, int32_t enable);
 copa_status copa_read_timing(copa_plan *plan, double *ms, int64_t *launches);
 const char *copa_kernel_name(int32_t id);
 
+/* Facts about a plan's device layout, for reports and tests: `what` is one of
+ *   COPA_QUERY_COMPACT  1 if pass 1 streams the compact nonzeros (feature id below 2^16 and every
+ *                       value exactly representable as bfloat16, so the 4-byte form is lossless),
+ *   COPA_QUERY_CHUNKS   number of pass-2 chunks (0 if pass 2 uses its unchunked form),
+ *   COPA_QUERY_WAVES    number of pass-1 wave entries.
+ * *out (host) receives the value. COPA_EINVAL for a NULL argument or an unknown `what`.       */
+#define COPA_QUERY_COMPACT 0
+#define COPA_QUERY_CHUNKS 1
+#define COPA_QUERY_WAVES 2
+copa_status copa_plan_query(const copa_plan *plan, int32_t what, int64_t *out);
+
 /* 1 if this build has kernels for rank R, else 0.                                           */
 int32_t copa_rank_supported(int32_t R);
 

@@ -22,7 +22,8 @@ PROX_NONE, PROX_NONNEG, PROX_L1, PROX_L0, PROX_NONNEG_L1 = 0, 1, 2, 3, 4
 # every function declared in include/copa.h
 SYMBOLS = ("copa_plan_create", "copa_fit", "copa_mttkrp_last", "copa_plan_basis",
            "copa_loss_grad", "copa_plan_destroy", "copa_rank_supported", "copa_status_string",
-           "copa_last_error", "copa_set_timing", "copa_read_timing", "copa_kernel_name")
+           "copa_last_error", "copa_set_timing", "copa_read_timing", "copa_kernel_name",
+           "copa_plan_query")
 NUM_KERNELS = 8
 
 
@@ -84,6 +85,7 @@ def lib():
         L.copa_set_timing.argtypes = [c_void_p, c_int32]
         L.copa_read_timing.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
         L.copa_kernel_name.argtypes = [c_int32]
+        L.copa_plan_query.argtypes = [c_void_p, c_int32, POINTER(c_int64)]
         L.copa_kernel_name.restype = ctypes.c_char_p
         for name in ("copa_plan_create", "copa_fit", "copa_mttkrp_last", "copa_plan_basis",
                      "copa_loss_grad", "copa_rank_supported", "copa_set_timing",
@@ -220,6 +222,14 @@ class Plan:
                                     _ptr(dV), _ptr(dW), _ptr(dS), ctypes.byref(loss), _stream()),
                "copa_loss_grad")
         return loss.value, dH, dV, dW, dS
+
+    def query(self, what):
+        """Plan layout facts: 'compact' (pass 1 reads the lossless 4-byte nonzeros), 'chunks'
+        (pass-2 chunks), 'waves' (pass-1 wave entries)."""
+        code = {"compact": 0, "chunks": 1, "waves": 2}[what]
+        out = c_int64(0)
+        _check(lib().copa_plan_query(self._h, code, ctypes.byref(out)), "copa_plan_query")
+        return int(out.value)
 
     def set_timing(self, enable=True):
         _check(lib().copa_set_timing(self._h, int(bool(enable))), "copa_set_timing")

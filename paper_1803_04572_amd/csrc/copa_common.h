@@ -84,6 +84,8 @@ struct copa_plan {
   int32_t *col = nullptr;    // [nnz]
   float *val = nullptr;      // [nnz]
   int32_t *rowsubj = nullptr;  // [S] subject of each visit row (unsmoothed only)
+  bool compact = false;      // nonzeros also stored as xc (pass 1 reads those)
+  uint32_t *xc = nullptr;    // [nnz] feature (low 16 bits) | value as bfloat16 (high 16 bits)
   float *C = nullptr;        // [S x 8] smoothing basis rows (l > 0)
   int32_t *rk = nullptr;     // [K] basis ranks (l > 0)
   float *Ew = nullptr;       // [64 x K] Procrustes eigenvectors of the last outer iteration (l > 0)
@@ -108,8 +110,7 @@ struct copa_plan {
   int32_t *crow = nullptr;   // [nchunks+1] first visit row of each chunk
   int32_t *cinfo = nullptr;  // [nchunks x 2] first subject and subject count of each chunk
   int32_t *wsplit = nullptr; // [nchunks x 9] per-wave slices of each chunk (feature boundaries)
-  uint32_t *pkey = nullptr;  // [nnz] feature << 16 | row within chunk
-  float *pval = nullptr;     // [nnz]
+  uint2 *pkv = nullptr;      // [nnz] (feature << 16 | row within chunk, value bits)
   int n_cu = 0;
   // Gram slots (gstride doubles each): F_H, W^TW, Psi, V^TV partials of the V update, and two
   // more for the adjoint; a slot holds gmaxnb block partials and their total.

@@ -54,11 +54,12 @@ enum { kFH = 0, kHtH = 1, kWtW = 2, kVtV = 3, kPsi = 4 };
 // Persistent blocks of 4 waves; each block stages one column tile of V (kept padded to RTP
 // columns per row by the V update) in LDS once, then its waves walk the wave list: each wave takes
 // `cnt` subjects and G lanes per subject stride over the subject's visit rows.
-template <int RT, bool SMOOTH>
+template <int RT, bool SMOOTH, bool COMPACT>
 __global__ void __launch_bounds__(256)
     k_pass1(const WaveEntry *__restrict__ waves, int n_waves, const int32_t *__restrict__ order,
             const int32_t *__restrict__ subj, const int32_t *__restrict__ row,
             const int32_t *__restrict__ col, const float *__restrict__ val,
+            const uint32_t *__restrict__ xc,
             const float *__restrict__ C, const float *__restrict__ Vp, int64_t J, int R, int l,
             float *__restrict__ T, float *__restrict__ FV) {
   constexpr int RTP = (RT + 3) & ~3;
@@ -138,9 +139,15 @@ __global__ void __launch_bounds__(256)
           for (int u = 0; u < 8; ++u) {
             const bool ok = eb + u < e1;
             const unsigned ec = (unsigned)(ok ? eb + u : e0);
-            cj[u] = col[ec];
-            const float x = val[ec];
-            xv[u] = ok ? x : 0.0f;
+            if constexpr (COMPACT) {
+              const uint32_t w = xc[ec];
+              cj[u] = (int)(w & 0xffffu);
+              xv[u] = ok ? __uint_as_float(w & 0xffff0000u) : 0.0f;
+            } else {
+              cj[u] = col[ec];
+              const float x = val[ec];
+              xv[u] = ok ? x : 0.0f;
+            }
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
@@ -196,10 +203,16 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const bool ok = eb + u < e1;
-            const int ec = ok ? eb + u : e0;
-            cj[u] = col[ec];
-            const float x = val[ec];
-            xv[u] = ok ? x : 0.0f;
+            const unsigned ec = (unsigned)(ok ? eb + u : e0);
+            if constexpr (COMPACT) {
+              const uint32_t w = xc[ec];
+              cj[u] = (int)(w & 0xffffu);
+              xv[u] = ok ? __uint_as_float(w & 0xffff0000u) : 0.0f;
+            } else {
+              cj[u] = col[ec];
+              const float x = val[ec];
+              xv[u] = ok ? x : 0.0f;
+            }
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
@@ -1386,14 +1399,16 @@ static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
   const int per_cu = std::max(1, std::min(4, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
   const int nb = std::max(1, std::min((p->n_waves + 3) / 4, p->n_cu * per_cu));
   dim3 grid((unsigned)nb, (unsigned)p->tiles.nt), block(256);
-  if (p->l > 0)
-    k_pass1<RT, true><<<grid, block, lds, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
-                                              p->col, p->val, p->C, p->Vp, p->J, p->R, p->l,
-                                              p->T, p->FV);
-  else
-    k_pass1<RT, false><<<grid, block, lds, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
-                                               p->col, p->val, p->C, p->Vp, p->J, p->R, p->l,
-                                               p->T, p->FV);
+#define P1(SM, CP)                                                                              \
+  k_pass1<RT, SM, CP><<<grid, block, lds, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,  \
+                                              p->col, p->val, p->xc, p->C, p->Vp, p->J, p->R,  \
+                                              p->l, p->T, p->FV)
+  if (p->l > 0) {
+    if (p->compact) P1(true, true); else P1(true, false);
+  } else {
+    if (p->compact) P1(false, true); else P1(false, false);
+  }
+#undef P1
 }
 
 template <int RT>
@@ -1695,6 +1710,19 @@ copa_status copa_read_timing(copa_plan *p, double *ms, int64_t *launches) {
     p->t_cnt[k] = 0;
   }
   return COPA_OK;
+}
+
+copa_status copa_plan_query(const copa_plan *p, int32_t what, int64_t *out) {
+  if (!p || !out) {
+    set_error("plan or out is NULL");
+    return COPA_EINVAL;
+  }
+  switch (what) {
+    case COPA_QUERY_COMPACT: *out = p->compact ? 1 : 0; return COPA_OK;
+    case COPA_QUERY_CHUNKS: *out = p->p2c ? p->nchunks : 0; return COPA_OK;
+    case COPA_QUERY_WAVES: *out = p->n_waves; return COPA_OK;
+    default: set_error("unknown query"); return COPA_EINVAL;
+  }
 }
 
 const char *copa_kernel_name(int32_t id) {

@@ -231,8 +231,8 @@ inline void gram(copa_plan *p, const float *A, const float *B, int64_t rows, con
 template <int RT, bool SMOOTH>
 __global__ void __launch_bounds__(512)
     k_pass2c(int nchunks, const int32_t *__restrict__ crow, const int32_t *__restrict__ cinfo,
-             const int32_t *__restrict__ wsplit, const uint32_t *__restrict__ pkey,
-             const float *__restrict__ pval, const int32_t *__restrict__ rowsubj,
+             const int32_t *__restrict__ wsplit, const uint2 *__restrict__ pkv,
+             const int32_t *__restrict__ rowsubj,
              const float *__restrict__ C, const float *__restrict__ M, int64_t J, int R, int l,
              float *__restrict__ FV) {
   extern __shared__ float4 smem4[];
@@ -266,9 +266,9 @@ __global__ void __launch_bounds__(512)
     float xv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int ec = a + u < b ? a + u : 0;
-      kv[u] = pkey[ec];
-      xv[u] = pval[ec];
+      const uint2 w = pkv[a + u < b ? a + u : 0];
+      kv[u] = w.x;
+      xv[u] = __uint_as_float(w.y);
     }
     const int tc = t < n ? t : 0;
     float cr[kLMax];
@@ -321,9 +321,9 @@ __global__ void __launch_bounds__(512)
       if (eb > a) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          const int ec = eb + q < b ? eb + q : a;
-          kv[q] = pkey[ec];
-          xv[q] = pval[ec];
+          const uint2 w = pkv[eb + q < b ? eb + q : a];
+          kv[q] = w.x;
+          xv[q] = __uint_as_float(w.y);
         }
       }
 #pragma unroll
@@ -402,8 +402,8 @@ template <int RT, bool SMOOTH>
 inline void launch_pass2c(const copa_plan *p, const float *Mrows, float *F, hipStream_t s) {
   const dim3 grid((unsigned)std::min(p->nchunks, 2 * std::max(1, p->n_cu)), (unsigned)p->tiles.nt);
   const size_t lds = ((size_t)p->J * RT + (size_t)kChunkRows * RT) * sizeof(float);
-  k_pass2c<RT, SMOOTH><<<grid, 512, lds, s>>>(p->nchunks, p->crow, p->cinfo, p->wsplit, p->pkey,
-                                             p->pval, p->rowsubj, p->C, Mrows, p->J, p->R,
+  k_pass2c<RT, SMOOTH><<<grid, 512, lds, s>>>(p->nchunks, p->crow, p->cinfo, p->wsplit, p->pkv,
+                                             p->rowsubj, p->C, Mrows, p->J, p->R,
                                              SMOOTH ? p->l : 0, F);
 }
 

@@ -65,6 +65,22 @@ __global__ void k_row_subject(const int32_t *subj, int32_t *rowsubj, int64_t K) 
 }
 
 // sum of squares of the values, FP64, one partial per block then a single-block finish
+// flag[0] = 1 if some value is not exactly a bfloat16 (its low 16 bits are not zero)
+__global__ void k_check_bf16(const float *val, int64_t n, int *flag) {
+  int bad = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    bad |= (__float_as_uint(val[e]) & 0xffffu) != 0u;
+  if (bad) atomicOr(flag, 1);
+}
+
+// Compact nonzero: feature id in the low 16 bits, the value's bfloat16 bits (exact) in the high.
+__global__ void k_pack_compact(const int32_t *col, const float *val, int64_t n, uint32_t *xc) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    xc[e] = ((uint32_t)col[e] & 0xffffu) | (__float_as_uint(val[e]) & 0xffff0000u);
+}
+
 __global__ void k_sumsq(const float *val, int64_t n, double *part) {
   __shared__ double red[256];
   double acc = 0.0;
@@ -382,11 +398,18 @@ static copa_status build_sorted_chunks(const copa_tensor *X, copa_plan *p, hipSt
   COPA_TRY(dalloc(&p->cinfo, (size_t)2 * nch));
   COPA_HIP(hipMemcpyAsync(p->crow, crow.data(), (nch + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
   COPA_HIP(hipMemcpyAsync(p->cinfo, cinf.data(), 2 * nch * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  COPA_TRY(dalloc(&p->pkey, nnz));
-  COPA_TRY(dalloc(&p->pval, nnz));
+  COPA_TRY(dalloc(&p->pkv, nnz));
   COPA_HIP(hipMemcpyAsync(p->cptr, cp.data(), (nch + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  COPA_HIP(hipMemcpyAsync(p->pkey, key.data(), nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-  COPA_HIP(hipMemcpyAsync(p->pval, sv.data(), nnz * sizeof(float), hipMemcpyHostToDevice, s));
+  {
+    std::vector<uint2> kv(nnz);
+    for (int64_t e = 0; e < nnz; ++e) {
+      uint32_t vb;
+      std::memcpy(&vb, &sv[e], sizeof(vb));
+      kv[e] = make_uint2(key[e], vb);
+    }
+    COPA_HIP(hipMemcpyAsync(p->pkv, kv.data(), nnz * sizeof(uint2), hipMemcpyHostToDevice, s));
+    COPA_HIP(hipStreamSynchronize(s));
+  }
   COPA_HIP(hipStreamSynchronize(s));
   return COPA_OK;
 }
@@ -470,6 +493,26 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
     (void)hipFree(part);
     p->normX2 = 0.0;
     for (double v : h) p->normX2 += v;
+  }
+  // ---- compact nonzeros for pass 1 when lossless: features below 2^16 and every value exactly
+  // a bfloat16 (count data); half the bytes and one load per nonzero
+  p->compact = false;
+  if (nnz > 0 && p->J <= 65536) {
+    int *flag = nullptr;
+    COPA_TRY(dalloc(&flag, 1));
+    COPA_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    k_check_bf16<<<1024, 256, 0, s>>>(p->val, nnz, flag);
+    COPA_HIP(hipGetLastError());
+    int hf = 1;
+    COPA_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    COPA_HIP(hipStreamSynchronize(s));
+    (void)hipFree(flag);
+    if (hf == 0) {
+      COPA_TRY(dalloc(&p->xc, nnz));
+      k_pack_compact<<<2048, 256, 0, s>>>(p->col, p->val, nnz, p->xc);
+      COPA_HIP(hipGetLastError());
+      p->compact = true;
+    }
   }
 
   // ---- subject order and wave work list (host): subjects by decreasing visit count; a wave
@@ -583,8 +626,8 @@ using namespace copa;
 
 static void free_plan(copa_plan *p) {
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-  void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->C, p->rk, p->Ew, p->order, p->waves,
-                  p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->cptr, p->crow, p->cinfo, p->wsplit, p->pkey, p->pval, p->Vp,
+  void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->xc, p->C, p->rk, p->Ew, p->order, p->waves,
+                  p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->cptr, p->crow, p->cinfo, p->wsplit, p->pkv, p->Vp,
                   p->gpart, p->gcount,
                   p->vpart, p->wpart, p->small, p->modes, p->scal, p->dloss, p->gradbuf,
                   p->lpart};

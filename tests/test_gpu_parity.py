@@ -89,6 +89,24 @@ def test_fit_parity(cfg_name, K, R, l, iters):
     assert min(cong.values()) >= CONGRUENCE_MIN
 
 
+@pytest.mark.parametrize("scale,compact", [(1.0, 1), (1.1, 0)])
+def test_value_storage_forms(scale, compact):
+    """Integer counts are stored in the lossless 4-byte form (feature id + bfloat16 value); other
+    values keep FP32 nonzeros. Both forms fit the oracle."""
+    from paper_1803_04572_amd import copa
+    coh, _ = synth.make_config("c2", K=300)
+    coh.val = (coh.val * np.float32(scale)).astype(np.float32)
+    plan = copa.Plan.from_cohort(coh, R=10, l=7)
+    assert plan.query("compact") == compact
+    assert plan.query("chunks") > 0
+    g = run_gpu(coh, 10, 7, 10)
+    o, prob = run_oracle(coh, 10, 7, 10)
+    fit_rel = abs(g["rep"]["fit"] - o.fit[-1]) / abs(o.fit[-1])
+    cong = min(congruence(g["H"], o.H), congruence(g["V"], o.V), congruence(g["W"], o.W))
+    _report(f"storage scale={scale}", fit_rel=fit_rel, cong=cong)
+    assert fit_rel <= FIT_RTOL and cong >= CONGRUENCE_MIN
+
+
 def test_invalid_csr_is_rejected_on_device():
     import torch
     from paper_1803_04572_amd import copa
