@@ -120,7 +120,8 @@ struct copa_plan {
   int32_t *gcount = nullptr;  // [8] last-block counters of the row Grams
   double *vpart = nullptr;  // [blocks x 4] V-ADMM scalar partials
   int n_vblocks = 0;
-  double *wpart = nullptr;  // [ceil(K/64)] |W|_1 partials of the W update
+  double *wpart = nullptr;  // [n_wblocks] |W|_1 partials of the W update
+  int n_wblocks = 0;        // W-update blocks: 4 wavefronts of 64 / R subjects
   double *small = nullptr;  // FH, HtH, WtW, VtV, Psi : 5 x R x R
   copa::ModeParams *modes = nullptr;  // [3]
   copa::FitScalars *scal = nullptr;

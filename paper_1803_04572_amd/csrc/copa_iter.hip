@@ -903,39 +903,6 @@ __device__ __forceinline__ bool build_system(const double *__restrict__ X,
   return *sflag == 0;
 }
 
-// Inner ADMM steps on one row (Algorithm 1 inner loop):
-//   Z = (F + rho (Zb + D)) (G + rho I)^{-1},  Zb = prox(Z - D),  D += Zb - Z.
-template <int R>
-__device__ __forceinline__ void admm_row(const double (&F)[R], float (&Zb)[R], float (&D)[R],
-                                         const double *__restrict__ sGi, double rho, int kind,
-                                         double lam, int iters) {
-  const double thr = lam / rho;
-  for (int it = 0; it < iters; ++it) {
-    // small R: the compiler keeps (G + rho I)^{-1} in registers across the steps; larger R
-    // re-reads it from LDS in every step (a compiler-only barrier stops the hoisting)
-    if constexpr (R > 12) __asm__ volatile("" ::: "memory");
-    double r[R], z[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      r[i] = F[i] + rho * ((double)Zb[i] + (double)D[i]);
-      z[i] = 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      if constexpr (R > 12)
-        if (i % 2 == 0) __asm__ volatile("" ::: "memory");
-#pragma unroll
-      for (int c = 0; c < R; ++c) z[c] += r[i] * sGi[i * R + c];
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const double zb = prox_sel(z[i] - (double)D[i], kind, lam, thr);
-      D[i] = (float)((double)D[i] + zb - z[i]);
-      Zb[i] = (float)zb;
-    }
-  }
-}
-
 // ======================================================================= ADMM on rows by lanes
 // One factor row spread over R lanes of a wavefront (lane c holds column c): the inner ADMM
 // steps of Algorithm 1, Z = (F + rho (Zb + D)) (G + rho I)^{-1}, Zb = prox(Z - D), D += Zb - Z,
@@ -1132,123 +1099,113 @@ __global__ void __launch_bounds__(256)
   if (t == 0) modes[1].rho = srho;
 }
 
-// ======================================================================= mode W (lane/subject)
+// ======================================================================= mode W (R lanes/subject)
+// One subject per group of R lanes (lane c holds column c): F_W(k, c) = sum_i (q_i H)(c) t_i(c)
+// (the q rows exchanged through wavefront-local LDS), the inner ADMM steps on W's row k, then the
+// M rows (q_i H) * w_k for pass 2 and the Psi Gram; per-block |W|_1 for the objective.
 template <int R>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
     k_w_admm(int64_t K, int l, const int32_t *__restrict__ subj, const int32_t *__restrict__ rk,
              const float *__restrict__ T, const float *__restrict__ Q, float *__restrict__ M,
              const float *__restrict__ H, float *__restrict__ W, float *__restrict__ DW,
              float *__restrict__ FW, const ModeParams *__restrict__ modes, int kind, double lam,
              int iters, double *__restrict__ l1part) {
+  constexpr int G = kWave / R;
   __shared__ double sGi[R * R];
   __shared__ float sH[R * R];
-  __shared__ double sred[64];
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+  __shared__ float xq[4][G + 1][kLMax][R];
+  __shared__ double xch[4][G + 1][R];
+  __shared__ double sred[256];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = lane / R, c = lane % R;
+  for (int e = t; e < R * R; e += blockDim.x) {
     sGi[e] = modes[1].Gi[e];
     sH[e] = H[e];
   }
+  const int64_t k = ((int64_t)blockIdx.x * 4 + wave) * G + g;
+  const bool act = g < G && k < K;
+  const int64_t kc = act ? k : 0;
+  float Zb = W[kc * R + c], D = DW[kc * R + c];
+  int64_t base;
+  int m;
+  if (l > 0) {
+    base = kc * l;
+    m = rk[kc];
+  } else {
+    base = subj[kc];
+    m = subj[kc + 1] - subj[kc];
+  }
+  if (!act) m = 0;
   __syncthreads();
   const double rho = modes[1].rho;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double F = 0.0;
+  float qh[kLMax];  // smoothed: (q_i H)(c) of the l rows, kept for the M rows
+  float(&xg)[kLMax][R] = xq[wave][g];
+  if (l > 0) {
+    float qv[kLMax], tv[kLMax];
+#pragma unroll
+    for (int i = 0; i < kLMax; ++i) {
+      const int64_t ri = base + (i < l ? i : 0);
+      qv[i] = Q[ri * R + c];
+      tv[i] = T[ri * R + c];
+    }
+#pragma unroll
+    for (int i = 0; i < kLMax; ++i) xg[i][c] = qv[i];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int i = 0; i < kLMax; ++i) {
+      double p = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) p += (double)xg[i][r] * (double)sH[r * R + c];
+      F += i < m ? p * (double)tv[i] : 0.0;
+      qh[i] = (float)p;
+    }
+  } else {
+    for (int i = 0; i < m; ++i) {
+      const float qv = Q[(base + i) * R + c], tv = T[(base + i) * R + c];
+      __builtin_amdgcn_wave_barrier();
+      xg[0][c] = qv;
+      __builtin_amdgcn_wave_barrier();
+      double p = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) p += (double)xg[0][r] * (double)sH[r * R + c];
+      F += p * (double)tv;
+    }
+  }
+  if (act) FW[k * R + c] = (float)F;
+  admm_lanes<R>(F, Zb, D, sGi, rho, kind, lam, iters, xch[wave][g], c);
   double l1 = 0.0;
-  if (k < K) {
-    int64_t base;
-    int m;
-    if (l > 0) {
-      base = k * l;
-      m = rk[k];
-    } else {
-      base = subj[k];
-      m = subj[k + 1] - subj[k];
-    }
-    // F_W(k, c) = sum_i (q_i H)(c) t_i(c)
-    double F[R];
-#pragma unroll
-    for (int c = 0; c < R; ++c) F[c] = 0.0;
-    float qh[kLMax][R];  // smoothed: the l rows q_i H, kept for the M rows
-    if (l > 0) {
-      // at most kLMax projected rows: all loads issued at once from clamped rows, masked after
-      float qv[kLMax][R], tv[kLMax][R];
-#pragma unroll
-      for (int i = 0; i < kLMax; ++i) {
-        const int64_t ri = base + (i < l ? i : 0);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          qv[i][r] = Q[ri * R + r];
-          tv[i][r] = T[ri * R + r];
-        }
-      }
+  if (act) {
+    W[k * R + c] = Zb;
+    DW[k * R + c] = D;
+    l1 = fabs((double)Zb);
+  }
+  // M rows = (q_i H) * w_new
+  if (l > 0) {
+    if (act) {
 #pragma unroll
       for (int i = 0; i < kLMax; ++i)
-#pragma unroll
-        for (int c = 0; c < R; ++c) {
-          double p = 0.0;
-#pragma unroll
-          for (int r = 0; r < R; ++r) p += (double)qv[i][r] * sH[r * R + c];
-          F[c] += i < m ? p * (double)tv[i][c] : 0.0;
-          qh[i][c] = (float)p;
-        }
+        if (i < l) M[(base + i) * R + c] = (float)((double)qh[i] * (double)Zb);
     }
-    for (int i = 0; l == 0 && i < m; ++i) {
-      const float *q = Q + (base + i) * R;
-      const float *t = T + (base + i) * R;
-      float qv[R];
+  } else {
+    for (int i = 0; i < m; ++i) {
+      const float qv = Q[(base + i) * R + c];
+      __builtin_amdgcn_wave_barrier();
+      xg[0][c] = qv;
+      __builtin_amdgcn_wave_barrier();
+      double p = 0.0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) qv[r] = q[r];
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        double p = 0.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) p += (double)qv[r] * sH[r * R + c];
-        F[c] += p * (double)t[c];
-      }
-    }
-    float Zb[R], D[R];
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      Zb[c] = W[k * R + c];
-      D[c] = DW[k * R + c];
-      FW[k * R + c] = (float)F[c];
-    }
-    admm_row<R>(F, Zb, D, sGi, rho, kind, lam, iters);
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      W[k * R + c] = Zb[c];
-      DW[k * R + c] = D[c];
-      l1 += fabs((double)Zb[c]);
-    }
-    // M rows = (q_i H) * w_new
-    if (l > 0) {
-#pragma unroll
-      for (int i = 0; i < kLMax; ++i)
-        if (i < l) {
-#pragma unroll
-          for (int c = 0; c < R; ++c)
-            M[(base + i) * R + c] = (float)((double)qh[i][c] * (double)Zb[c]);
-        }
-    }
-    for (int i = 0; l == 0 && i < m; ++i) {
-      const float *q = Q + (base + i) * R;
-      float qv[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) qv[r] = q[r];
-      float *dst = M + (base + i) * R;
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        double p = 0.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) p += (double)qv[r] * sH[r * R + c];
-        dst[c] = (float)(p * (double)Zb[c]);
-      }
+      for (int r = 0; r < R; ++r) p += (double)xg[0][r] * (double)sH[r * R + c];
+      M[(base + i) * R + c] = (float)(p * (double)Zb);
     }
   }
-  sred[threadIdx.x] = l1;
+  sred[t] = l1;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < 64; ++i) s += sred[i];
-    l1part[blockIdx.x] = s;
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sred[t] += sred[t + w];
+    __syncthreads();
   }
+  if (t == 0) l1part[blockIdx.x] = sred[0];
 }
 
 // ======================================================================= mode V
@@ -1482,7 +1439,7 @@ static FitArgs fit_args(const copa_plan *p) {
   fa.vtvpart = gram_slot(p, kSlotVtV);
   fa.nvb = p->n_vblocks;
   fa.wl1part = p->wpart;
-  fa.nwb = (int)std::max<int64_t>(1, (p->K + 63) / 64);
+  fa.nwb = p->n_wblocks;
   fa.normX2 = p->normX2;
   fa.J = p->J;
   fa.proxV = o.prox_V;
@@ -1526,9 +1483,8 @@ static void iteration_r(copa_plan *p, const copa_state *st, int it, hipStream_t 
     k_mode_H<R><<<1, 256, 0, s>>>(it, gram_total(p, kSlotFH), p->small, p->modes, p->scal,
                                   st->H, st->D_H, o.prox_H, o.lambda_H, o.inner_iters);
   });
-  const unsigned nwb = (unsigned)std::max<int64_t>(1, (K + 63) / 64);
   timed(p, s, kidWadmm, [&] {
-    k_w_admm<R><<<nwb, 64, 0, s>>>(K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W,
+    k_w_admm<R><<<(unsigned)p->n_wblocks, 256, 0, s>>>(K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W,
                                    st->D_W, p->FW, p->modes, o.prox_W, o.lambda_W,
                                    o.inner_iters, p->wpart);
   });

@@ -605,7 +605,11 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
            ((int64_t)p->J * p->tiles.rt + (int64_t)kChunkRows * p->tiles.rt) * 4 <= p->lds_limit;
   if (p->p2c) COPA_TRY(build_sorted_chunks(X, p, s));
   COPA_TRY(dalloc(&p->vpart, (size_t)p->n_vblocks * 4));
-  COPA_TRY(dalloc(&p->wpart, (size_t)std::max<int64_t>(1, (K + 63) / 64)));
+  {
+    const int64_t per_block = 4 * (kWave / R);
+    p->n_wblocks = (int)std::max<int64_t>(1, (K + per_block - 1) / per_block);
+  }
+  COPA_TRY(dalloc(&p->wpart, (size_t)p->n_wblocks));
   COPA_TRY(dalloc(&p->small, 8 * R * R));
   COPA_TRY(dalloc(&p->modes, 3));
   COPA_TRY(dalloc(&p->scal, 1));
