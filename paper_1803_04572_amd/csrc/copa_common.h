@@ -180,6 +180,19 @@ __device__ __forceinline__ double prox_sel(double x, int kind, double lam, doubl
 
 __device__ __forceinline__ float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, kWave); }
 
+// Value of the DPP source lane (CTRL: row_shr:n = 0x110 + n, row_bcast:15 = 0x142, row_bcast:31 =
+// 0x143, wave_shl:1 = 0x130, wave_shr:1 = 0x138), or `old` where the source lane is outside the
+// row or wave, or the lane's row is not in ROWMASK.
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ int dpp_i(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWMASK, 0xF, false);
+}
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ float dpp_f(float old, float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+}
+
 // v + (v of lane ^ M) for aligned lane groups, when the groups of M lanes below have already been
 // summed this way (then every lane of a 2M group ends with the same total): quad permutes for
 // M = 1, 2, half-row and row mirrors for M = 4, 8 (DPP, no LDS), swizzle for 16, permute for 32.

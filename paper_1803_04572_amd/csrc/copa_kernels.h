@@ -2,6 +2,8 @@
 // contraction on the matrix cores and the feature-sorted streaming scatter F += X^T U.
 #pragma once
 
+#include <type_traits>
+
 #include "copa_common.h"
 
 namespace copa {
@@ -354,23 +356,31 @@ __global__ void __launch_bounds__(512)
     }
     // tail segment (cur, acc); the first key of this lane's run is hkey (several segments) or cur
     const int first = nseg > 1 ? hkey : cur;
-    // inclusive segmented scan of the tails over lanes (keys are non-decreasing along lanes)
+    // inclusive segmented scan of the tails over lanes (keys are non-decreasing along lanes, so
+    // equal keys at two lanes mean one segment between them): DPP shifts within rows of 16 lanes,
+    // then the row broadcasts of lanes 15 and 31 (no LDS traffic)
+    auto seg_step = [&](auto ctrl, auto mask) {
+      constexpr int CT = decltype(ctrl)::value, MK = decltype(mask)::value;
+      const int kp = dpp_i<CT, MK>(-1, cur);
+      float vp[RT];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int kprev = __shfl_up(cur, d, 64);
-      float vprev[RT];
+      for (int r = 0; r < RT; ++r) vp[r] = dpp_f<CT, MK>(0.0f, acc[r]);
+      if (cur >= 0 && kp == cur) {
 #pragma unroll
-      for (int r = 0; r < RT; ++r) vprev[r] = __shfl_up(acc[r], d, 64);
-      if (lane >= d && cur >= 0 && kprev == cur) {
-#pragma unroll
-        for (int r = 0; r < RT; ++r) acc[r] += vprev[r];
+        for (int r = 0; r < RT; ++r) acc[r] += vp[r];
       }
-    }
-    const int knext = __shfl_down(first, 1, 64);
-    const int kprev1 = __shfl_up(cur, 1, 64);
+    };
+    seg_step(std::integral_constant<int, 0x111>{}, std::integral_constant<int, 0xF>{});
+    seg_step(std::integral_constant<int, 0x112>{}, std::integral_constant<int, 0xF>{});
+    seg_step(std::integral_constant<int, 0x114>{}, std::integral_constant<int, 0xF>{});
+    seg_step(std::integral_constant<int, 0x118>{}, std::integral_constant<int, 0xF>{});
+    seg_step(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
+    seg_step(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
+    const int knext = dpp_i<0x130>(-1, first);   // lane + 1
+    const int kprev1 = dpp_i<0x138>(-1, cur);    // lane - 1
     float carry[RT];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) carry[r] = __shfl_up(acc[r], 1, 64);
+    for (int r = 0; r < RT; ++r) carry[r] = dpp_f<0x138>(0.0f, acc[r]);
     if (nseg > 1) {
       // head segment: complete once the previous lane's tail (if same feature) is added
       const bool join = lane > 0 && kprev1 == hkey;
