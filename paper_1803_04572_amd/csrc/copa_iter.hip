@@ -327,48 +327,50 @@ __device__ __forceinline__ void jacobi8(double (&A)[kNMax][kNMax], double (&V)[k
   }
 }
 
-// Same eigensolver on a packed upper triangle (36 values), for the register-resident path.
-__host__ __device__ constexpr int tri8(int i, int j) {
-  return i <= j ? 8 * i - (i * (i - 1)) / 2 + (j - i) : 8 * j - (j * (j - 1)) / 2 + (i - j);
+// Same eigensolver on a packed upper triangle (N (N + 1) / 2 values), for the register-resident
+// path; N is the padded problem size.
+template <int N>
+__host__ __device__ constexpr int triN(int i, int j) {
+  return i <= j ? N * i - (i * (i - 1)) / 2 + (j - i) : N * j - (j * (j - 1)) / 2 + (i - j);
 }
 
 // With INIT = false, V holds an orthogonal matrix on entry and the rotations are accumulated onto
 // it: then A must be V^T G V and on return V holds the eigenvectors of G.
-template <bool INIT = true>
-__device__ __forceinline__ void jacobi8_tri(double (&A)[36], double (&V)[kNMax][kNMax]) {
+template <int N, bool INIT = true>
+__device__ __forceinline__ void jacobi_tri(double (&A)[N * (N + 1) / 2], double (&V)[N][N]) {
   if constexpr (INIT) {
 #pragma unroll
-    for (int i = 0; i < kNMax; ++i)
+    for (int i = 0; i < N; ++i)
 #pragma unroll
-      for (int j = 0; j < kNMax; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+      for (int j = 0; j < N; ++j) V[i][j] = i == j ? 1.0 : 0.0;
   }
   double scale = 0.0;
 #pragma unroll
-  for (int i = 0; i < kNMax; ++i) scale += fabs(A[tri8(i, i)]);
+  for (int i = 0; i < N; ++i) scale += fabs(A[triN<N>(i, i)]);
   const double tiny = 1e-300 + 1e-17 * scale;
   for (int sweep = 0; sweep < 16; ++sweep) {
     bool rotated = false;
 #pragma unroll
-    for (int p = 0; p < kNMax - 1; ++p) {
+    for (int p = 0; p < N - 1; ++p) {
 #pragma unroll
-      for (int q = p + 1; q < kNMax; ++q) {
-        const double apq = A[tri8(p, q)];
+      for (int q = p + 1; q < N; ++q) {
+        const double apq = A[triN<N>(p, q)];
         if (fabs(apq) > tiny) {
           rotated = true;
           double t, c, s;
-          jacobi_cs(A[tri8(p, p)], A[tri8(q, q)], apq, t, c, s);
+          jacobi_cs(A[triN<N>(p, p)], A[triN<N>(q, q)], apq, t, c, s);
 #pragma unroll
-          for (int k = 0; k < kNMax; ++k) {
+          for (int k = 0; k < N; ++k) {
             if (k == p || k == q) continue;
-            const double akp = A[tri8(k, p)], akq = A[tri8(k, q)];
-            A[tri8(k, p)] = c * akp - s * akq;
-            A[tri8(k, q)] = s * akp + c * akq;
+            const double akp = A[triN<N>(k, p)], akq = A[triN<N>(k, q)];
+            A[triN<N>(k, p)] = c * akp - s * akq;
+            A[triN<N>(k, q)] = s * akp + c * akq;
           }
-          A[tri8(p, p)] -= t * apq;
-          A[tri8(q, q)] += t * apq;
-          A[tri8(p, q)] = 0.0;
+          A[triN<N>(p, p)] -= t * apq;
+          A[triN<N>(q, q)] += t * apq;
+          A[triN<N>(p, q)] = 0.0;
 #pragma unroll
-          for (int k = 0; k < kNMax; ++k) {
+          for (int k = 0; k < N; ++k) {
             const double vkp = V[k][p], vkq = V[k][q];
             V[k][p] = c * vkp - s * vkq;
             V[k][q] = s * vkp + c * vkq;
@@ -382,29 +384,30 @@ __device__ __forceinline__ void jacobi8_tri(double (&A)[36], double (&V)[kNMax][
 
 // E <- E (3 I - E^T E) / 2: one Newton-Schulz step towards the nearest orthogonal matrix, taking
 // an FP32-rounded orthogonal matrix (deviation ~1e-7) to FP64 orthogonality (~1e-14).
-__device__ __forceinline__ void orthonormalize8(double (&E)[kNMax][kNMax]) {
-  double N[36];
+template <int N>
+__device__ __forceinline__ void orthonormalize(double (&E)[N][N]) {
+  double Nm[N * (N + 1) / 2];
 #pragma unroll
-  for (int p = 0; p < kNMax; ++p)
+  for (int p = 0; p < N; ++p)
 #pragma unroll
-    for (int q = p; q < kNMax; ++q) {
+    for (int q = p; q < N; ++q) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < kNMax; ++i) s += E[i][p] * E[i][q];
-      N[tri8(p, q)] = s;
+      for (int i = 0; i < N; ++i) s += E[i][p] * E[i][q];
+      Nm[triN<N>(p, q)] = s;
     }
 #pragma unroll
-  for (int i = 0; i < kNMax; ++i) {
-    double r[kNMax];
+  for (int i = 0; i < N; ++i) {
+    double r[N];
 #pragma unroll
-    for (int q = 0; q < kNMax; ++q) {
+    for (int q = 0; q < N; ++q) {
       double s = 0.0;
 #pragma unroll
-      for (int p = 0; p < kNMax; ++p) s += E[i][p] * N[tri8(p, q)];
+      for (int p = 0; p < N; ++p) s += E[i][p] * Nm[triN<N>(p, q)];
       r[q] = 1.5 * E[i][q] - 0.5 * s;
     }
 #pragma unroll
-    for (int q = 0; q < kNMax; ++q) E[i][q] = r[q];
+    for (int q = 0; q < N; ++q) E[i][q] = r[q];
   }
 }
 
@@ -723,15 +726,17 @@ __global__ void __launch_bounds__(64)
   if (lane == 0 && rank < (m < R ? m : R)) atomicAdd(rank_def, 1);
 }
 
-// Smoothed subjects (l <= 8 projected rows) with R <= 16: the same computation with T and A held
-// in registers, rows unrolled to kLMax (rows at or past l are zero).
-template <int R>
+// Smoothed subjects (l <= N <= 8 projected rows) with R <= 16: the same computation with T and A
+// held in registers and LDS, rows unrolled to N (rows at or past l are zero; N = l = 7 is the
+// usual instance, N = 8 the general one).
+template <int R, int N>
 __global__ void __launch_bounds__(64)
     k_procrustes_s(int64_t K, int l, const int32_t *__restrict__ rk, const float *__restrict__ T,
                    float *__restrict__ Q, const float *__restrict__ H, const float *__restrict__ W,
                    float *__restrict__ Ew, double rtol, int32_t *rank_def) {
+  constexpr int NT = N * (N + 1) / 2;
   __shared__ float sH[R * R];
-  __shared__ float sA[kLMax * R * 64];  // A of this lane's subject, element (i, c) at (i R + c) 64 + lane
+  __shared__ float sA[N * R * 64];  // A of this lane's subject, element (i, c) at (i R + c) 64 + lane
   const int lane = threadIdx.x;
   for (int e = lane; e < R * R; e += blockDim.x) sH[e] = H[e];
   __syncthreads();
@@ -743,12 +748,11 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
     for (int r = 0; r < R; ++r) w[r] = W[k * R + r];
 #pragma unroll
-    for (int i = 0; i < kLMax; ++i) {
+    for (int i = 0; i < N; ++i) {
       const float *t = T + (base + (i < l ? i : 0)) * R;
       float z[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) z[r] = t[r] * w[r];
-#pragma unroll
       for (int c = 0; c < R; ++c) {
         double s = 0.0;
 #pragma unroll
@@ -763,72 +767,72 @@ __global__ void __launch_bounds__(64)
   // sweeps run on E^T G E with E = last iteration's eigenvectors (identity on the first), made
   // orthogonal to FP64 precision first. G = A A^T (rows side) or A^T A (columns side) is summed
   // from the rotated vectors E^T v over the columns (rows) v of A.
-  double E[kNMax][kNMax];
+  double E[N][N];
 #pragma unroll
-  for (int i = 0; i < kNMax; ++i)
+  for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < kNMax; ++j) E[i][j] = (double)Ew[(int64_t)(i * kNMax + j) * K + k];
-  orthonormalize8(E);
-  double G[36];
+    for (int j = 0; j < N; ++j) E[i][j] = (double)Ew[(int64_t)(i * kNMax + j) * K + k];
+  orthonormalize<N>(E);
+  double G[NT];
 #pragma unroll
-  for (int e = 0; e < 36; ++e) G[e] = 0.0;
-  const int nv = rows_side ? R : kLMax;
+  for (int e = 0; e < NT; ++e) G[e] = 0.0;
+  const int nv = rows_side ? R : N;
   for (int c = 0; c < nv; ++c) {
-    double v[kNMax], a[kNMax];
+    double v[N], a[N];
 #pragma unroll
-    for (int p = 0; p < kNMax; ++p) v[p] = rows_side ? Aat(p, c) : (p < R ? Aat(c, p) : 0.0);
+    for (int p = 0; p < N; ++p) v[p] = rows_side ? Aat(p, c) : (p < R ? Aat(c, p) : 0.0);
 #pragma unroll
-    for (int q = 0; q < kNMax; ++q) {
+    for (int q = 0; q < N; ++q) {
       double s = 0.0;
 #pragma unroll
-      for (int p = 0; p < kNMax; ++p) s += E[p][q] * v[p];
+      for (int p = 0; p < N; ++p) s += E[p][q] * v[p];
       a[q] = s;
     }
 #pragma unroll
-    for (int p = 0; p < kNMax; ++p)
+    for (int p = 0; p < N; ++p)
 #pragma unroll
-      for (int q = p; q < kNMax; ++q) G[tri8(p, q)] += a[p] * a[q];
+      for (int q = p; q < N; ++q) G[triN<N>(p, q)] += a[p] * a[q];
   }
-  jacobi8_tri<false>(G, E);
+  jacobi_tri<N, false>(G, E);
 #pragma unroll
-  for (int i = 0; i < kNMax; ++i)
+  for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < kNMax; ++j) Ew[(int64_t)(i * kNMax + j) * K + k] = (float)E[i][j];
+    for (int j = 0; j < N; ++j) Ew[(int64_t)(i * kNMax + j) * K + k] = (float)E[i][j];
   double lmax = 0.0;
 #pragma unroll
-  for (int j = 0; j < kNMax; ++j) lmax = fmax(lmax, G[tri8(j, j)]);
-  double f[kNMax];
+  for (int j = 0; j < N; ++j) lmax = fmax(lmax, G[triN<N>(j, j)]);
+  double f[N];
   int rank = 0;
 #pragma unroll
-  for (int j = 0; j < kNMax; ++j) {
-    const double lj = G[tri8(j, j)];
+  for (int j = 0; j < N; ++j) {
+    const double lj = G[triN<N>(j, j)];
     const bool keep = lmax > 0.0 && lj > rtol * rtol * lmax;
-    f[j] = keep ? 1.0 / sqrt(lj) : 0.0;
+    f[j] = keep ? rsq_nr(lj) : 0.0;
     rank += keep ? 1 : 0;
   }
   // B = E diag(f) E^T (symmetric) into the triangle
 #pragma unroll
-  for (int i = 0; i < kNMax; ++i)
+  for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = i; j < kNMax; ++j) {
+    for (int j = i; j < N; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int q = 0; q < kNMax; ++q) s += E[i][q] * f[q] * E[j][q];
-      G[tri8(i, j)] = s;
+      for (int q = 0; q < N; ++q) s += E[i][q] * f[q] * E[j][q];
+      G[triN<N>(i, j)] = s;
     }
 #pragma unroll
-  for (int i = 0; i < kLMax; ++i) {
+  for (int i = 0; i < N; ++i) {
     if (i < l) {
       float *dst = Q + (base + i) * R;
       for (int c = 0; c < R; ++c) {
         double s = 0.0;
         if (rows_side) {
 #pragma unroll
-          for (int j = 0; j < kLMax; ++j) s += G[tri8(i, j)] * Aat(j, c);
+          for (int j = 0; j < N; ++j) s += G[triN<N>(i, j)] * Aat(j, c);
         } else {
 #pragma unroll
-          for (int j = 0; j < kNMax; ++j)
-            if (j < R && c < kNMax) s += Aat(i, j) * G[tri8(j, c < kNMax ? c : 0)];
+          for (int j = 0; j < N; ++j)
+            if (j < R && c < N) s += Aat(i, j) * G[triN<N>(j, c < N ? c : 0)];
         }
         dst[c] = (float)s;
       }
@@ -1462,8 +1466,12 @@ static void iteration_r(copa_plan *p, const copa_state *st, int it, hipStream_t 
     timed(p, s, kidProcrustes, [&] {
       if constexpr (R <= 16) {
         if (p->l > 0) {
-          k_procrustes_s<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-              K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, rank_def);
+          if (p->l == 7)
+            k_procrustes_s<R, 7><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
+                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, rank_def);
+          else
+            k_procrustes_s<R, kLMax><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
+                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, rank_def);
           return;
         }
       }
