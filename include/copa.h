@@ -155,6 +155,12 @@ copa_status copa_loss_grad(copa_plan *plan, const float *H, const float *V, cons
 /* Frees every device buffer of the plan (synchronises its device first). NULL is a no-op.   */
 void copa_plan_destroy(copa_plan *plan);
 
+/* copa_fit replays each run of outer iterations from one hipGraph (captured on a stream of the
+ * plan on first use and again when the iteration count per call or the state buffers change),
+ * which removes the per-kernel launch cost. copa_set_graph(plan, 0) launches the kernels one by
+ * one instead (as does per-kernel timing). Default: enabled.                                 */
+copa_status copa_set_graph(copa_plan *plan, int32_t enable);
+
 /* Per-kernel GPU timing of copa_fit for benchmarking. copa_set_timing(plan, 1) makes later
  * copa_fit calls record a HIP event pair on `stream` around every kernel launch (events are
  * created here, once per plan; copa_fit then synchronises every 64 iterations to read them).

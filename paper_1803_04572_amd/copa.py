@@ -23,7 +23,7 @@ PROX_NONE, PROX_NONNEG, PROX_L1, PROX_L0, PROX_NONNEG_L1 = 0, 1, 2, 3, 4
 SYMBOLS = ("copa_plan_create", "copa_fit", "copa_mttkrp_last", "copa_plan_basis",
            "copa_loss_grad", "copa_plan_destroy", "copa_rank_supported", "copa_status_string",
            "copa_last_error", "copa_set_timing", "copa_read_timing", "copa_kernel_name",
-           "copa_plan_query")
+           "copa_plan_query", "copa_set_graph")
 NUM_KERNELS = 8
 
 
@@ -83,6 +83,7 @@ def lib():
         L.copa_status_string.restype = ctypes.c_char_p
         L.copa_last_error.restype = ctypes.c_char_p
         L.copa_set_timing.argtypes = [c_void_p, c_int32]
+        L.copa_set_graph.argtypes = [c_void_p, c_int32]
         L.copa_read_timing.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
         L.copa_kernel_name.argtypes = [c_int32]
         L.copa_plan_query.argtypes = [c_void_p, c_int32, POINTER(c_int64)]
@@ -230,6 +231,10 @@ class Plan:
         out = c_int64(0)
         _check(lib().copa_plan_query(self._h, code, ctypes.byref(out)), "copa_plan_query")
         return int(out.value)
+
+    def set_graph(self, enable=True):
+        """Replay outer iterations from a captured hipGraph (default) or launch kernel by kernel."""
+        _check(lib().copa_set_graph(self._h, int(bool(enable))), "copa_set_graph")
 
     def set_timing(self, enable=True):
         _check(lib().copa_set_timing(self._h, int(bool(enable))), "copa_set_timing")

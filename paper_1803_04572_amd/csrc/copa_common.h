@@ -51,6 +51,7 @@ struct ModeParams {
 
 // Device-side scalars of the fit (one struct, zeroed per copa_fit call).
 struct FitScalars {
+  int32_t cur;             // index of the outer iteration being run (within the current chunk)
   int32_t iter;            // iterations completed in this call
   int32_t fail_iter;       // first failing iteration or INT_MAX
   int32_t rank_deficient;  // subjects with truncated Procrustes rank (last iteration)
@@ -127,6 +128,12 @@ struct copa_plan {
   copa::FitScalars *scal = nullptr;
   double *dloss = nullptr;  // loss/grad scalars
   // optional per-kernel event timing of copa_fit
+  // hipGraph of one outer iteration (captured on cap_stream, replayed on the caller's stream);
+  // captured again when the state buffers change
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  copa_state gstate{};
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_kid;
@@ -149,8 +156,8 @@ inline double *gram_total(const copa_plan *p, int slot) {
 namespace copa {
 
 // ---------------------------------------------------------------- launchers (copa_iter.hip)
-copa_status launch_iteration(copa_plan *p, const copa_state *st, int it, hipStream_t s);
-copa_status launch_fit(copa_plan *p, const copa_state *st, int it, hipStream_t s);
+copa_status launch_iteration(copa_plan *p, const copa_state *st, hipStream_t s);
+copa_status launch_fit(copa_plan *p, const copa_state *st, hipStream_t s);
 copa_status launch_init_grams(copa_plan *p, const copa_state *st, hipStream_t s);
 copa_status launch_qtilde(copa_plan *p, float *Qt, hipStream_t s);
 copa_status harvest_timing(copa_plan *p);

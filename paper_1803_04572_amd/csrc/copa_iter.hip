@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(64)
     k_procrustes(int64_t K, int l, const int32_t *__restrict__ subj,
                  const int32_t *__restrict__ rk, const float *__restrict__ T,
                  float *__restrict__ Q, float *__restrict__ Abuf, const float *__restrict__ H,
-                 const float *__restrict__ W, double rtol, int32_t *rank_def) {
+                 const float *__restrict__ W, double rtol, FitScalars *sc) {
   __shared__ float sH[R * R];
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) sH[e] = H[e];
   __syncthreads();
@@ -565,7 +565,7 @@ __global__ void __launch_bounds__(64)
       }
     }
   }
-  if (rank < (meff < R ? meff : R)) atomicAdd(rank_def, 1);
+  if (rank < (meff < R ? meff : R)) atomicAdd(&sc->rank_def_slot[sc->cur & 1], 1);
 }
 
 // Unsmoothed subjects whose eigenproblem n = min(I_k, R) exceeds what a lane holds: one
@@ -578,7 +578,7 @@ __global__ void __launch_bounds__(64)
     k_procrustes_wave(const int32_t *__restrict__ list, int nlist,
                       const int32_t *__restrict__ subj, const float *__restrict__ T,
                       float *__restrict__ Q, const float *__restrict__ H,
-                      const float *__restrict__ W, double rtol, int32_t *rank_def) {
+                      const float *__restrict__ W, double rtol, FitScalars *sc) {
   __shared__ double sG[R * R];
   __shared__ double sE[R * R];
   __shared__ double sA[R * R];  // A (rows side) or Gamma, then N (columns side)
@@ -723,7 +723,7 @@ __global__ void __launch_bounds__(64)
       }
     }
   }
-  if (lane == 0 && rank < (m < R ? m : R)) atomicAdd(rank_def, 1);
+  if (lane == 0 && rank < (m < R ? m : R)) atomicAdd(&sc->rank_def_slot[sc->cur & 1], 1);
 }
 
 // Smoothed subjects (l <= N <= 8 projected rows) with R <= 16: the same computation with T and A
@@ -733,7 +733,7 @@ template <int R, int N>
 __global__ void __launch_bounds__(64)
     k_procrustes_s(int64_t K, int l, const int32_t *__restrict__ rk, const float *__restrict__ T,
                    float *__restrict__ Q, const float *__restrict__ H, const float *__restrict__ W,
-                   float *__restrict__ Ew, double rtol, int32_t *rank_def) {
+                   float *__restrict__ Ew, double rtol, FitScalars *sc) {
   constexpr int NT = N * (N + 1) / 2;
   __shared__ float sH[R * R];
   __shared__ float sA[N * R * 64];  // A of this lane's subject, element (i, c) at (i R + c) 64 + lane
@@ -839,7 +839,7 @@ __global__ void __launch_bounds__(64)
     }
   }
   const int meff = rk[k];
-  if (rank < (meff < R ? meff : R)) atomicAdd(rank_def, 1);
+  if (rank < (meff < R ? meff : R)) atomicAdd(&sc->rank_def_slot[sc->cur & 1], 1);
 }
 
 // ======================================================================= ADMM helpers
@@ -1006,25 +1006,26 @@ __device__ __forceinline__ void fit_finalize(const FitArgs &fa, int it, const fl
 
 template <int R>
 __global__ void __launch_bounds__(256)
-    k_fit(FitArgs fa, int it, const float *H, double *small, FitScalars *sc) {
+    k_fit(FitArgs fa, const float *H, double *small, FitScalars *sc) {
   __shared__ double red[6][256];
   __shared__ double sVtV[R * R];
-  fit_finalize<R>(fa, it, H, small, sc, red, sVtV);
+  fit_finalize<R>(fa, sc->cur - 1, H, small, sc, red, sVtV);
 }
 
 // The row Gram F_H = sum Q_row^T (T_row * w) (as k_rows_gram) with one extra block that takes
-// the FIT of the previous outer iteration meanwhile (fit_block: that block's index, or -1).
+// the FIT of the previous outer iteration meanwhile (when the current iteration is not the first
+// of its chunk).
 template <int R, int WSEL>
 __global__ void __launch_bounds__(256)
     k_rows_gram_fit(const float *__restrict__ A, const float *__restrict__ B, int64_t rows,
                     const float *__restrict__ W, int slot_rows,
                     const int32_t *__restrict__ rowsubj, double *__restrict__ part, int nb,
-                    FitArgs fa, int fit_it, const float *__restrict__ H, double *small,
-                    FitScalars *sc) {
+                    FitArgs fa, const float *__restrict__ H, double *small, FitScalars *sc) {
   if ((int)blockIdx.x == nb) {
     __shared__ double red[6][256];
     __shared__ double sVtV[R * R];
-    fit_finalize<R>(fa, fit_it, H, small, sc, red, sVtV);
+    const int it = sc->cur;
+    if (it > 0) fit_finalize<R>(fa, it - 1, H, small, sc, red, sVtV);
     return;
   }
   rows_gram_block<R, WSEL>(A, B, rows, W, slot_rows, rowsubj, part, blockIdx.x, nb);
@@ -1032,19 +1033,19 @@ __global__ void __launch_bounds__(256)
 
 template <int R>
 static void gram_fit(copa_plan *p, const float *A, const float *B, int64_t rows,
-                     const float *W, int wsel, int slot, bool fit, const FitArgs &fa,
-                     int fit_it, const float *H, hipStream_t s) {
+                     const float *W, int wsel, int slot, const FitArgs &fa, const float *H,
+                     hipStream_t s) {
   const int64_t units = (rows + 63) / 64;
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(p->gmaxnb, (units + 7) / 8));
-  const unsigned grid = (unsigned)nb + (fit ? 1u : 0u);
+  const unsigned grid = (unsigned)nb + 1u;
   double *p1 = gram_slot(p, slot);
   const int sr = p->slot_rows > 0 ? p->slot_rows : 1;
   if (wsel == 1)
-    k_rows_gram_fit<R, 1><<<grid, 256, 0, s>>>(A, B, rows, W, sr, p->rowsubj, p1, nb, fa,
-                                               fit_it, H, p->small, p->scal);
+    k_rows_gram_fit<R, 1><<<grid, 256, 0, s>>>(A, B, rows, W, sr, p->rowsubj, p1, nb, fa, H,
+                                               p->small, p->scal);
   else
-    k_rows_gram_fit<R, 2><<<grid, 256, 0, s>>>(A, B, rows, W, sr, p->rowsubj, p1, nb, fa,
-                                               fit_it, H, p->small, p->scal);
+    k_rows_gram_fit<R, 2><<<grid, 256, 0, s>>>(A, B, rows, W, sr, p->rowsubj, p1, nb, fa, H,
+                                               p->small, p->scal);
   k_gram_reduce<R * R><<<dim3((R * R + 3) / 4, 1), 256, 0, s>>>(p1, gram_total(p, slot), nullptr,
                                                                  nullptr, nb);
 }
@@ -1054,7 +1055,7 @@ static void gram_fit(copa_plan *p, const float *A, const float *B, int64_t rows,
 // H^T H; then the W-mode system G_W = H^TH * V^TV for the W update.
 template <int R>
 __global__ void __launch_bounds__(256)
-    k_mode_H(int it, const double *FHtot, double *small, ModeParams *modes, FitScalars *sc,
+    k_mode_H(const double *FHtot, double *small, ModeParams *modes, FitScalars *sc,
              float *H, float *DH, int kind, double lam, int iters) {
   constexpr int RR = R * R;
   constexpr int G = kWave / R;
@@ -1073,7 +1074,7 @@ __global__ void __launch_bounds__(256)
   __syncthreads();
   for (int e = t; e < RR; e += blockDim.x) small[kFH * RR + e] = sFH[e];
   bool ok = build_system<R>(sX, sY, sL, sGi, &srho, &sflag);
-  if (t == 0 && !ok) atomicMin(&sc->fail_iter, it);
+  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
   const double rho = srho;
   for (int r0 = 0; r0 < R; r0 += 4 * G) {
     const int row = r0 + wave * G + g;
@@ -1098,7 +1099,7 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   ok = build_system<R>(sX, sY, sL, sGi, &srho, &sflag);
-  if (t == 0 && !ok) atomicMin(&sc->fail_iter, it);
+  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
   for (int e = t; e < RR; e += blockDim.x) modes[1].Gi[e] = sGi[e];
   if (t == 0) modes[1].rho = srho;
 }
@@ -1218,7 +1219,7 @@ __global__ void __launch_bounds__(256)
 // <F_V, V>, |V|_1, zeros and V^T V for the FIT (added by the next launch that needs them).
 template <int R>
 __global__ void __launch_bounds__(256)
-    k_v_admm(int it, int64_t J, const float *__restrict__ FV, float *__restrict__ V,
+    k_v_admm(int64_t J, const float *__restrict__ FV, float *__restrict__ V,
              float *__restrict__ DV, float *__restrict__ Vp, int rt, int rtp,
              const double *__restrict__ WtWtot, const double *__restrict__ Psitot, double *small,
              FitScalars *sc, int kind, double lam, int iters, double *__restrict__ vpart,
@@ -1248,7 +1249,7 @@ __global__ void __launch_bounds__(256)
     }
   }
   const bool ok = build_system<R>(sHH, sW, sL, sGi, &srho, &sflag);
-  if (t == 0 && !ok) atomicMin(&sc->fail_iter, it);
+  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
   const double rho = srho;
   double dot = 0.0, l1 = 0.0, zeros = 0.0;
   double vtv[(RR + 255) / 256];
@@ -1316,8 +1317,14 @@ __global__ void k_zero(float *x, int64_t n) {
     x[e] = 0.0f;
 }
 
+// Marks the end of an outer iteration: later launches read the new index.
+__global__ void k_next_iter(FitScalars *sc) {
+  if (threadIdx.x == 0) sc->cur += 1;
+}
+
 __global__ void k_reset_scalars(FitScalars *sc) {
   if (threadIdx.x == 0) {
+    sc->cur = 0;
     sc->iter = 0;
     sc->fail_iter = INT_MAX;
     sc->rank_deficient = 0;
@@ -1455,12 +1462,12 @@ static FitArgs fit_args(const copa_plan *p) {
   return fa;
 }
 
-// Outer iteration number it of the current chunk (the device history index).
+// One outer iteration; the kernels read its index (within the chunk) from the device scalars,
+// so the same launches serve every iteration (and one captured graph replays them).
 template <int R>
-static void iteration_r(copa_plan *p, const copa_state *st, int it, hipStream_t s) {
+static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   const copa_options &o = p->opt;
   const int64_t K = p->K;
-  int32_t *rank_def = &p->scal->rank_def_slot[it & 1];
   timed(p, s, kidPass1, [&] { RT_SWITCH(p->tiles.rt, launch_pass1_rt, p, st->V, s); });
   if (K > 0)
     timed(p, s, kidProcrustes, [&] {
@@ -1468,27 +1475,26 @@ static void iteration_r(copa_plan *p, const copa_state *st, int it, hipStream_t 
         if (p->l > 0) {
           if (p->l == 7)
             k_procrustes_s<R, 7><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, rank_def);
+                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
           else
             k_procrustes_s<R, kLMax><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, rank_def);
+                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
           return;
         }
       }
       k_procrustes<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-          K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W, o.rank_rtol, rank_def);
+          K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W, o.rank_rtol, p->scal);
       if (p->n_big > 0)
         k_procrustes_wave<R><<<(unsigned)p->n_big, 64, 0, s>>>(
-            p->big_list, p->n_big, p->subj, p->T, p->Q, st->H, st->W, o.rank_rtol, rank_def);
+            p->big_list, p->n_big, p->subj, p->T, p->Q, st->H, st->W, o.rank_rtol, p->scal);
     });
   timed(p, s, kidGramFH, [&] {
     // one more block of the same launch takes the FIT of the previous outer iteration
     const FitArgs fa = fit_args(p);
-    gram_fit<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, kSlotFH, it > 0, fa,
-                it - 1, st->H, s);
+    gram_fit<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, kSlotFH, fa, st->H, s);
   });
   timed(p, s, kidModeH, [&] {
-    k_mode_H<R><<<1, 256, 0, s>>>(it, gram_total(p, kSlotFH), p->small, p->modes, p->scal,
+    k_mode_H<R><<<1, 256, 0, s>>>(gram_total(p, kSlotFH), p->small, p->modes, p->scal,
                                   st->H, st->D_H, o.prox_H, o.lambda_H, o.inner_iters);
   });
   timed(p, s, kidWadmm, [&] {
@@ -1502,10 +1508,11 @@ static void iteration_r(copa_plan *p, const copa_state *st, int it, hipStream_t 
   timed(p, s, kidPass2, [&] { RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s); });
   timed(p, s, kidVadmm, [&] {
     k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(
-        it, p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, (p->tiles.rt + 3) & ~3,
+        p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, (p->tiles.rt + 3) & ~3,
         gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->scal, o.prox_V,
         o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV));
   });
+  k_next_iter<<<1, 64, 0, s>>>(p->scal);
 }
 
 template <int R>
@@ -1523,10 +1530,10 @@ static void init_grams_r(copa_plan *p, const copa_state *st, hipStream_t s) {
                                     p->small);
 }
 
-copa_status launch_iteration(copa_plan *p, const copa_state *st, int it, hipStream_t s) {
+copa_status launch_iteration(copa_plan *p, const copa_state *st, hipStream_t s) {
   switch (p->R) {
 #define CASE(r) \
-  case r: iteration_r<r>(p, st, it, s); break;
+  case r: iteration_r<r>(p, st, s); break;
     COPA_R_LIST(CASE)
 #undef CASE
     default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
@@ -1535,10 +1542,10 @@ copa_status launch_iteration(copa_plan *p, const copa_state *st, int it, hipStre
   return COPA_OK;
 }
 
-copa_status launch_fit(copa_plan *p, const copa_state *st, int it, hipStream_t s) {
+copa_status launch_fit(copa_plan *p, const copa_state *st, hipStream_t s) {
   switch (p->R) {
 #define CASE(r) \
-  case r: k_fit<r><<<1, 256, 0, s>>>(fit_args(p), it, st->H, p->small, p->scal); break;
+  case r: k_fit<r><<<1, 256, 0, s>>>(fit_args(p), st->H, p->small, p->scal); break;
     COPA_R_LIST(CASE)
 #undef CASE
     default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
@@ -1579,6 +1586,58 @@ using namespace copa;
 
 extern "C" {
 
+// The launches of `chunk` outer iterations on stream s, and the FIT of the last one (the others
+// are taken by the next iteration's F_H launch).
+static copa_status launch_chunk(copa_plan *p, const copa_state *st, int chunk, hipStream_t s) {
+  for (int t = 0; t < chunk; ++t) {
+    copa_status cs = launch_iteration(p, st, s);
+    if (cs != COPA_OK) return cs;
+  }
+  return launch_fit(p, st, s);
+}
+
+static bool same_state(const copa_state &a, const copa_state &b) {
+  return a.H == b.H && a.W == b.W && a.V == b.V && a.D_H == b.D_H && a.D_W == b.D_W &&
+         a.D_V == b.D_V;
+}
+
+// The same work with each outer iteration replayed from one hipGraph: the iteration is captured
+// once per plan and state buffers on the plan's own stream (so that the caller's stream may be
+// the null stream) and launched on s. None of the captured launches is a memset or a copy.
+static copa_status run_chunk_graph(copa_plan *p, const copa_state *st, int chunk, hipStream_t s) {
+  if (!p->gexec || !same_state(p->gstate, *st)) {
+    if (p->gexec) {
+      COPA_HIP(hipGraphExecDestroy(p->gexec));
+      p->gexec = nullptr;
+    }
+    if (!p->cap_stream) COPA_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    COPA_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    const copa_status cs = launch_iteration(p, st, p->cap_stream);
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (cs != COPA_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return cs;
+    }
+    COPA_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    COPA_HIP(ei);
+    p->gstate = *st;
+  }
+  for (int t = 0; t < chunk; ++t) COPA_HIP(hipGraphLaunch(p->gexec, s));
+  return launch_fit(p, st, s);
+}
+
+copa_status copa_set_graph(copa_plan *p, int32_t enable) {
+  if (!p) {
+    set_error("plan is NULL");
+    return COPA_EINVAL;
+  }
+  p->use_graph = enable != 0;
+  return COPA_OK;
+}
+
 copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Qtilde,
                      copa_report *rep, void *stream) {
   if (!p || !st || iters < 0) {
@@ -1599,13 +1658,13 @@ copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Q
   while (done < iters) {
     const int chunk = std::min(iters - done, p->timing ? kTimingChunk : kHistCap);
     if (done > 0) k_reset_scalars<<<1, 64, 0, s>>>(p->scal);
-    for (int t = 0; t < chunk; ++t) {
-      cs = launch_iteration(p, st, t, s);
+    if (p->use_graph && !p->timing) {
+      cs = run_chunk_graph(p, st, chunk, s);
+      if (cs != COPA_OK) return cs;
+    } else {
+      cs = launch_chunk(p, st, chunk, s);
       if (cs != COPA_OK) return cs;
     }
-    // the FIT of the chunk's last iteration (the others are taken by the next mode-H launch)
-    cs = launch_fit(p, st, chunk - 1, s);
-    if (cs != COPA_OK) return cs;
     COPA_HIP(hipMemcpyAsync(&hs, p->scal, sizeof(FitScalars), hipMemcpyDeviceToHost, s));
     COPA_HIP(hipStreamSynchronize(s));
     if (p->timing) {

@@ -630,6 +630,8 @@ using namespace copa;
 
 static void free_plan(copa_plan *p) {
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->xc, p->C, p->rk, p->Ew, p->order, p->waves,
                   p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->cptr, p->crow, p->cinfo, p->wsplit, p->pkv, p->Vp,
                   p->gpart, p->gcount,
