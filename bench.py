@@ -16,6 +16,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -26,7 +27,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "outer AO-ADMM iters/sec + MTTKRP HBM GB/s at fixed fit vs FP64 oracle"
-SOURCES = ["copa_iter.hip", "copa_setup.hip", "copa_kernels.h", "copa_common.h"]
+SOURCES = ["copa_common.h", "copa_kernels.h", "copa_setup.hip", "copa_iter.hip", "copa_grad.hip"]
+# rocprofv3 kernel-name stem of each timed kernel
+ROCPROF_NAME = {"pass1": "k_pass1", "procrustes": "k_procrustes", "gram_FH": "k_rows_gram_fit",
+                "mode_H": "k_mode_H", "w_admm": "k_w_admm", "gram_WM": "k_rows_gram",
+                "pass2": "k_pass2c", "v_admm": "k_v_admm"}
 
 
 def kernel_source_hash():
@@ -35,6 +40,23 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, "paper_1803_04572_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (profiles/hbm_traffic_<workload>.txt: FETCH_SIZE x2 + WRITE_SIZE x1, scales from a plain copy),
+    or None when the summary is missing or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        text = fh.read()
+    m = re.search(r"^# source_hash=(\w+)", text, re.M)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"^kernel=%s\S* .*bytes_per_launch=(\d+)" % re.escape(ROCPROF_NAME[kernel]),
+                  text, re.M)
+    return int(m.group(1)) if m else None
 
 
 def algorithmic_bytes(coh, R, l, compact):
@@ -142,14 +164,7 @@ def main():
             v["GBps"] = abytes[k] / (v["avg_us"] * 1e-6) / 1e9
     dom = max((k for k in per_kernel if k in abytes), key=lambda k: per_kernel[k]["avg_us"])
     ach = per_kernel[dom]["GBps"]
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_traffic.json")
-    if os.path.exists(tfile):
-        with open(tfile) as fh:
-            t = json.load(fh)
-        if t.get("source_hash") == kernel_source_hash():
-            traffic = t.get("bytes_per_launch")
-
+    traffic = measured_traffic(dom, args.workload)
     if args.copy_probe:
         n = 64 << 20
         a = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
