@@ -86,6 +86,11 @@ typedef struct copa_options {
   double lambda_H, lambda_W, lambda_V;
   double rank_rtol;
   double basis_rtol;
+  /* Optional stop: when stop_tol > 0, copa_fit evaluates the stationarity residual (see
+   * copa_stationarity) every check_every outer iterations (default 10 when <= 0) and returns
+   * early once its largest block value is below stop_tol. 0 = fixed iteration count.          */
+  double stop_tol;
+  int32_t check_every;
 } copa_options;
 
 /* Fit state, device memory owned by the caller, FP32 row-major. In: the starting point
@@ -103,16 +108,18 @@ typedef struct copa_state {
  * (Section "Evaluation Metrics"); objective = 1/2 sum_k ||X_k - U_k S_k V^T||^2 plus the
  * l1 penalties; sparsity_V = share of exact zeros in V (SPARSITY metric).
  * rank_deficient: subjects whose Procrustes rank was below min(rows, R) in the last iteration
- * (zero entries of W, rank-deficient smoothing bases, ...).                                  */
+ * (zero entries of W, rank-deficient smoothing bases, ...). stationarity: the largest block
+ * stationarity residual at the last check (stop_tol > 0), else -1.                           */
 typedef struct copa_report {
   int32_t iters_done;
-  int32_t fail_iter; /* first iteration with a non-finite value or Cholesky failure, or -1 */
+  int32_t fail_iter; /* first iteration with a non-finite value or a failed ADMM system, or -1 */
   double fit;
   double objective;
   double sparsity_V;
   int64_t rank_deficient;
   double *fit_history;
   double *objective_history;
+  double stationarity;
 } copa_report;
 
 typedef struct copa_plan copa_plan;
@@ -160,6 +167,19 @@ void copa_plan_destroy(copa_plan *plan);
  * which removes the per-kernel launch cost. copa_set_graph(plan, 0) launches the kernels one by
  * one instead (as does per-kernel timing). Default: enabled.                                 */
 copa_status copa_set_graph(copa_plan *plan, int32_t enable);
+
+/* Stationarity residual of each factor block of the penalised reconstruction loss at (H, V, W)
+ * with Qtilde fixed (the adjoint of copa_loss_grad supplies the gradient):
+ *   r_n = || Z_n - prox_n(Z_n - dL/dZ_n / rho_n) ||_F / || Z_n ||_F,   n = H, W, V,
+ * with each block's proximity operator and weight from the plan's options and rho_n =
+ * trace(G_n) / R (G_H = W^TW * V^TV, G_W = H^TH * V^TV, G_V = H^TH * W^TW, the steps of
+ * Algorithm 1). r_n = 0 exactly at a first-order stationary point of the block. Arguments as
+ * for copa_loss_grad (device memory); res: 3 doubles (host) in the order H, W, V. Allocates its
+ * buffers on first use and synchronises `stream`. Where Q_k^T Q_k != I (subjects with fewer
+ * rows than R, or a basis of rank below R) the ADMM blocks fit Q_k^T X_k rather than X_k, and
+ * the residual of the reconstruction loss need not vanish at the fit's fixed point.          */
+copa_status copa_stationarity(copa_plan *plan, const float *H, const float *V, const float *W,
+                              const float *Qtilde, double *res, void *stream);
 
 /* Per-kernel GPU timing of copa_fit for benchmarking. copa_set_timing(plan, 1) makes later
  * copa_fit calls record a HIP event pair on `stream` around every kernel launch (events are

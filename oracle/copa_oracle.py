@@ -340,3 +340,25 @@ def loss_grad(Xs, Qts, H, V, W):
         dS.append(dSk)
         dW[k] = np.diag(dSk)
     return L, dH, dV, dW, dS
+
+
+def stationarity(Xs, Qts, H, V, W, opt):
+    """Stationarity residual of each factor block of the penalised reconstruction loss with Q held
+    fixed: r_n = ||Z_n - prox_n(Z_n - grad_n L / rho_n)||_F / ||Z_n||_F, where prox_n is that
+    block's proximity operator with its weight (Section "Examples of useful constraints") and
+    rho_n = trace(G_n) / R with G_H = W^TW * V^TV, G_W = H^TH * V^TV, G_V = H^TH * W^TW (the step
+    of Algorithm 1). r_n = 0 exactly when Z_n is a fixed point of the proximal-gradient map, i.e.
+    when Z_n satisfies the first-order conditions of its block. Returns (r_H, r_W, r_V)."""
+    H, V, W = (np.asarray(a, dtype=np.float64) for a in (H, V, W))
+    _, dH, dV, dW, _ = loss_grad(Xs, Qts, H, V, W)
+    HtH, VtV, WtW = H.T @ H, V.T @ V, W.T @ W
+    R = H.shape[0]
+    out = []
+    for Z, G, dZ, kind, lam in ((H, WtW * VtV, dH, opt.prox_H, opt.lam_H),
+                                (W, HtH * VtV, dW, opt.prox_W, opt.lam_W),
+                                (V, HtH * WtW, dV, opt.prox_V, opt.lam_V)):
+        rho = np.trace(G) / R
+        step = prox(Z - dZ / rho, kind, lam, rho)
+        nz = np.linalg.norm(Z)
+        out.append(float(np.linalg.norm(Z - step) / nz) if nz > 0 else 0.0)
+    return tuple(out)

@@ -23,7 +23,7 @@ PROX_NONE, PROX_NONNEG, PROX_L1, PROX_L0, PROX_NONNEG_L1 = 0, 1, 2, 3, 4
 SYMBOLS = ("copa_plan_create", "copa_fit", "copa_mttkrp_last", "copa_plan_basis",
            "copa_loss_grad", "copa_plan_destroy", "copa_rank_supported", "copa_status_string",
            "copa_last_error", "copa_set_timing", "copa_read_timing", "copa_kernel_name",
-           "copa_plan_query", "copa_set_graph")
+           "copa_plan_query", "copa_set_graph", "copa_stationarity")
 NUM_KERNELS = 8
 
 
@@ -37,7 +37,7 @@ class CopaOptions(ctypes.Structure):
     _fields_ = [("R", c_int32), ("inner_iters", c_int32), ("prox_H", c_int32),
                 ("prox_W", c_int32), ("prox_V", c_int32), ("lambda_H", c_double),
                 ("lambda_W", c_double), ("lambda_V", c_double), ("rank_rtol", c_double),
-                ("basis_rtol", c_double)]
+                ("basis_rtol", c_double), ("stop_tol", c_double), ("check_every", c_int32)]
 
 
 class CopaState(ctypes.Structure):
@@ -48,7 +48,8 @@ class CopaState(ctypes.Structure):
 class CopaReport(ctypes.Structure):
     _fields_ = [("iters_done", c_int32), ("fail_iter", c_int32), ("fit", c_double),
                 ("objective", c_double), ("sparsity_V", c_double), ("rank_deficient", c_int64),
-                ("fit_history", POINTER(c_double)), ("objective_history", POINTER(c_double))]
+                ("fit_history", POINTER(c_double)), ("objective_history", POINTER(c_double)),
+                ("stationarity", c_double)]
 
 
 class CopaError(RuntimeError):
@@ -76,6 +77,8 @@ def lib():
         L.copa_plan_basis.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         L.copa_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p, c_void_p, POINTER(c_double), c_void_p]
+        L.copa_stationarity.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        POINTER(c_double), c_void_p]
         L.copa_plan_destroy.argtypes = [c_void_p]
         L.copa_plan_destroy.restype = None
         L.copa_rank_supported.argtypes = [c_int32]
@@ -128,7 +131,7 @@ class Plan:
 
     def __init__(self, subj_ptr, row_ptr, col, val, days, J, l, R, inner_iters=5,
                  prox=(PROX_NONE, PROX_NONNEG, PROX_L1), lam=(0.0, 0.0, 0.1), rank_rtol=1e-6,
-                 basis_rtol=1e-10):
+                 basis_rtol=1e-10, stop_tol=0.0, check_every=10):
         K = subj_ptr.numel() - 1
         S = row_ptr.numel() - 1
         self.K, self.J, self.S, self.nnz, self.l, self.R = K, int(J), S, col.numel(), int(l), int(R)
@@ -140,7 +143,8 @@ class Plan:
         o = CopaOptions(R=self.R, inner_iters=int(inner_iters), prox_H=int(prox[0]),
                         prox_W=int(prox[1]), prox_V=int(prox[2]), lambda_H=float(lam[0]),
                         lambda_W=float(lam[1]), lambda_V=float(lam[2]),
-                        rank_rtol=float(rank_rtol), basis_rtol=float(basis_rtol))
+                        rank_rtol=float(rank_rtol), basis_rtol=float(basis_rtol),
+                        stop_tol=float(stop_tol), check_every=int(check_every))
         h = c_void_p()
         _check(lib().copa_plan_create(ctypes.byref(t), ctypes.byref(o), _stream(),
                                       ctypes.byref(h)), "copa_plan_create")
@@ -188,7 +192,7 @@ class Plan:
                                 ctypes.byref(rep), _stream())
         out = dict(iters_done=rep.iters_done, fail_iter=rep.fail_iter, fit=rep.fit,
                    objective=rep.objective, sparsity_V=rep.sparsity_V,
-                   rank_deficient=rep.rank_deficient,
+                   rank_deficient=rep.rank_deficient, stationarity=rep.stationarity,
                    fit_history=list(fh)[:rep.iters_done],
                    objective_history=list(oh)[:rep.iters_done])
         if status != OK:
@@ -223,6 +227,13 @@ class Plan:
                                     _ptr(dV), _ptr(dW), _ptr(dS), ctypes.byref(loss), _stream()),
                "copa_loss_grad")
         return loss.value, dH, dV, dW, dS
+
+    def stationarity(self, H, V, W, Qt):
+        """(r_H, r_W, r_V): stationarity residual of each factor block (copa_stationarity)."""
+        res = (c_double * 3)()
+        _check(lib().copa_stationarity(self._h, _ptr(H), _ptr(V), _ptr(W), _ptr(Qt), res,
+                                       _stream()), "copa_stationarity")
+        return tuple(res)
 
     def query(self, what):
         """Plan layout facts: 'compact' (pass 1 reads the lossless 4-byte nonzeros), 'chunks'

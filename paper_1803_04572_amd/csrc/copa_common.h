@@ -16,6 +16,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kLMax = 8;           // spline basis functions per subject (padded row width of C)
 constexpr int kNMax = 8;           // largest Procrustes eigenproblem handled one subject per lane
 constexpr int kHistCap = 1024;     // per-iteration scalars buffered on the device
+constexpr int kStatBlocks = 256;   // blocks of the stationarity residual
 constexpr int kGramSlots = 6;      // F_H, W^TW, Psi, V^TV partials; adjoint G and its second Gram
 
 // Layout of one Gram slot (R x R FP64 blocks): [maxnb block partials | total].
@@ -51,7 +52,8 @@ struct ModeParams {
 
 // Device-side scalars of the fit (one struct, zeroed per copa_fit call).
 struct FitScalars {
-  int32_t cur;             // index of the outer iteration being run (within the current chunk)
+  int32_t cur;             // index of the outer iteration being run (within the current chunk);
+                           // -1 before the chunk's first pass 1
   int32_t iter;            // iterations completed in this call
   int32_t fail_iter;       // first failing iteration or INT_MAX
   int32_t rank_deficient;  // subjects with truncated Procrustes rank (last iteration)
@@ -141,6 +143,9 @@ struct copa_plan {
   double t_ms[copa::kNumKernels] = {};
   int64_t t_cnt[copa::kNumKernels] = {};
   float *gradbuf = nullptr; // [2 x S x R] U and D rows of the adjoint (allocated on first use)
+  float *statbuf = nullptr; // dH, dV, dW and the stationarity partials (allocated on first use)
+  float *qtbuf = nullptr;   // [S x R] Qtilde for the stationarity stop (allocated on first use)
+  size_t statfloats = 0;
   double *lpart = nullptr;  // per-block loss partials of the adjoint
 };
 namespace copa {
@@ -166,6 +171,8 @@ bool rank_supported(int R);
 Tiles choose_tiles(int R, int64_t J, int lds_limit);
 
 // ---------------------------------------------------------------- (copa_grad.hip)
+copa_status launch_stationarity(copa_plan *p, const float *H, const float *V, const float *W,
+                                const float *Qt, double *res_host, hipStream_t s);
 copa_status launch_loss_grad(copa_plan *p, const float *H, const float *V, const float *W,
                              const float *Qt, float *dH, float *dV, float *dW, float *dS,
                              hipStream_t s);

@@ -282,9 +282,7 @@ static copa_status loss_grad_r(copa_plan *p, const float *H, const float *V, con
   return COPA_OK;
 }
 
-copa_status launch_loss_grad(copa_plan *p, const float *H, const float *V, const float *W,
-                             const float *Qt, float *dH, float *dV, float *dW, float *dS,
-                             hipStream_t s) {
+static copa_status ensure_grad_buffers(copa_plan *p) {
   if (!p->gradbuf) {
     // first use: U and D rows (2 S R floats), F (J R) and the per-block loss partials
     const size_t n = std::max<size_t>(1, (size_t)2 * p->S * p->R + (size_t)p->J * p->R);
@@ -297,6 +295,14 @@ copa_status launch_loss_grad(copa_plan *p, const float *H, const float *V, const
       return COPA_ENOMEM;
     }
   }
+  return COPA_OK;
+}
+
+copa_status launch_loss_grad(copa_plan *p, const float *H, const float *V, const float *W,
+                             const float *Qt, float *dH, float *dV, float *dW, float *dS,
+                             hipStream_t s) {
+  const copa_status cs = ensure_grad_buffers(p);
+  if (cs != COPA_OK) return cs;
   switch (p->R) {
 #define CASE(r) \
   case r: return loss_grad_r<r>(p, H, V, W, Qt, dH, dV, dW, dS, s);
@@ -305,6 +311,128 @@ copa_status launch_loss_grad(copa_plan *p, const float *H, const float *V, const
 #undef CASE
     default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
   }
+}
+
+// ======================================================================= stationarity residual
+// Per block: the steps rho_n = trace(G_n) / R from W^TW, V^TV (Gram totals) and H^TH (formed
+// here), then sums over this block's share of the entries of H, W and V of
+// (z - prox_n(z - g / rho_n))^2 and z^2 (g = dL/dz). part[block * 6 + 2n + {0, 1}].
+template <int R>
+__global__ void __launch_bounds__(256)
+    k_stationarity(const float *__restrict__ H, const float *__restrict__ V,
+                   const float *__restrict__ W, const float *__restrict__ dH,
+                   const float *__restrict__ dV, const float *__restrict__ dW,
+                   const double *__restrict__ VtV, const double *__restrict__ WtW, int64_t K,
+                   int64_t J, int kH, double lH, int kW, double lW, int kV, double lV,
+                   double *__restrict__ part) {
+  __shared__ double red[6][256];
+  __shared__ double srho[3];
+  const int t = threadIdx.x;
+  if (t < 3) {
+    double tr = 0.0;
+    for (int a = 0; a < R; ++a) {
+      double hh = 0.0;
+      for (int i = 0; i < R; ++i) hh += (double)H[i * R + a] * (double)H[i * R + a];
+      const double vv = VtV[a * R + a], ww = WtW[a * R + a];
+      tr += t == 0 ? ww * vv : (t == 1 ? hh * vv : hh * ww);
+    }
+    srho[t] = tr / R;
+  }
+  __syncthreads();
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int64_t nH = (int64_t)R * R, nW = K * R, nV = J * R, n = nH + nW + nV;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + t; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    int m;
+    double z, g;
+    if (e < nH) {
+      m = 0;
+      z = H[e];
+      g = dH[e];
+    } else if (e < nH + nW) {
+      m = 1;
+      z = W[e - nH];
+      g = dW[e - nH];
+    } else {
+      m = 2;
+      z = V[e - nH - nW];
+      g = dV[e - nH - nW];
+    }
+    const double rho = srho[m];
+    const int kind = m == 0 ? kH : (m == 1 ? kW : kV);
+    const double lam = m == 0 ? lH : (m == 1 ? lW : lV);
+    const double d = z - prox_sel(z - g / rho, kind, lam, lam / rho);
+    acc[2 * m] += d * d;
+    acc[2 * m + 1] += z * z;
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) red[q][t] = acc[q];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) red[q][t] += red[q][t + w];
+    __syncthreads();
+  }
+  if (t < 6) part[blockIdx.x * 6 + t] = red[t][0];
+}
+
+__global__ void k_stationarity_reduce(const double *__restrict__ part, int nb, double *res) {
+  if (threadIdx.x < 3) {
+    double num = 0.0, den = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      num += part[b * 6 + 2 * threadIdx.x];
+      den += part[b * 6 + 2 * threadIdx.x + 1];
+    }
+    res[threadIdx.x] = den > 0.0 ? sqrt(num / den) : 0.0;
+  }
+}
+
+template <int R>
+static copa_status stationarity_r(copa_plan *p, const float *H, const float *V, const float *W,
+                                  const float *Qt, hipStream_t s) {
+  float *dH = p->statbuf, *dV = dH + R * R, *dW = dV + p->J * R;
+  double *part = reinterpret_cast<double *>(p->statbuf + p->statfloats);
+  copa_status cs = loss_grad_r<R>(p, H, V, W, Qt, dH, dV, dW, nullptr, s);
+  if (cs != COPA_OK) return cs;
+  // W^T W into a slot the adjoint no longer needs (its V^T V stays in kSlotG)
+  gram<R>(p, W, W, p->K, nullptr, 0, kSlotFH, nullptr, 0, 0, s);
+  const copa_options &o = p->opt;
+  k_stationarity<R><<<kStatBlocks, 256, 0, s>>>(
+      H, V, W, dH, dV, dW, gram_total(p, kSlotG), gram_total(p, kSlotFH), p->K, p->J, o.prox_H,
+      o.lambda_H, o.prox_W, o.lambda_W, o.prox_V, o.lambda_V, part);
+  k_stationarity_reduce<<<1, 64, 0, s>>>(part, kStatBlocks, part + 6 * kStatBlocks);
+  COPA_HIP(hipGetLastError());
+  return COPA_OK;
+}
+
+copa_status launch_stationarity(copa_plan *p, const float *H, const float *V, const float *W,
+                                const float *Qt, double *res_host, hipStream_t s) {
+  copa_status cg = ensure_grad_buffers(p);
+  if (cg != COPA_OK) return cg;
+  if (!p->statbuf) {
+    p->statfloats = ((size_t)p->R * p->R + (size_t)(p->J + p->K) * p->R + 1) & ~(size_t)1;
+    const size_t bytes = p->statfloats * sizeof(float) + (6 * kStatBlocks + 3) * sizeof(double);
+    hipError_t e = hipMalloc((void **)&p->statbuf, bytes);
+    if (e != hipSuccess) {
+      p->statbuf = nullptr;
+      set_error(std::string("hipMalloc for the stationarity buffers: ") + hipGetErrorString(e));
+      return COPA_ENOMEM;
+    }
+  }
+  copa_status cs;
+  switch (p->R) {
+#define CASE(r) \
+  case r: cs = stationarity_r<r>(p, H, V, W, Qt, s); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(10) CASE(12) CASE(15)
+    CASE(16) CASE(20) CASE(24) CASE(32) CASE(40)
+#undef CASE
+    default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
+  }
+  if (cs != COPA_OK) return cs;
+  const double *res = reinterpret_cast<double *>(p->statbuf + p->statfloats) + 6 * kStatBlocks;
+  COPA_HIP(hipMemcpyAsync(res_host, res, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipStreamSynchronize(s));
+  return COPA_OK;
 }
 
 }  // namespace copa
@@ -325,4 +453,16 @@ extern "C" copa_status copa_loss_grad(copa_plan *p, const float *H, const float 
   COPA_HIP(hipMemcpyAsync(loss, p->dloss, sizeof(double), hipMemcpyDeviceToHost, s));
   COPA_HIP(hipStreamSynchronize(s));
   return COPA_OK;
+}
+
+extern "C" copa_status copa_stationarity(copa_plan *p, const float *H, const float *V,
+                                         const float *W, const float *Qt, double *res,
+                                         void *stream) {
+  if (!p || !H || !V || !Qt || !res || (p->K > 0 && !W)) {
+    set_error("NULL argument");
+    return COPA_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  COPA_HIP(hipSetDevice(p->device));
+  return launch_stationarity(p, H, V, W, Qt, res, s);
 }

@@ -61,9 +61,12 @@ __global__ void __launch_bounds__(256)
             const int32_t *__restrict__ col, const float *__restrict__ val,
             const uint32_t *__restrict__ xc,
             const float *__restrict__ C, const float *__restrict__ Vp, int64_t J, int R, int l,
-            float *__restrict__ T, float *__restrict__ FV) {
+            float *__restrict__ T, float *__restrict__ FV, FitScalars *sc) {
   constexpr int RTP = (RT + 3) & ~3;
   extern __shared__ float4 smem4[];
+  // pass 1 opens an outer iteration: advance the device iteration index (no other launch of the
+  // iteration reads it before pass 1 ends)
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) sc->cur += 1;
   // F_V is accumulated by pass 2 of this iteration: clear it here
   if (blockIdx.y == 0)
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < J * R;
@@ -1009,7 +1012,7 @@ __global__ void __launch_bounds__(256)
     k_fit(FitArgs fa, const float *H, double *small, FitScalars *sc) {
   __shared__ double red[6][256];
   __shared__ double sVtV[R * R];
-  fit_finalize<R>(fa, sc->cur - 1, H, small, sc, red, sVtV);
+  fit_finalize<R>(fa, sc->cur, H, small, sc, red, sVtV);
 }
 
 // The row Gram F_H = sum Q_row^T (T_row * w) (as k_rows_gram) with one extra block that takes
@@ -1317,14 +1320,9 @@ __global__ void k_zero(float *x, int64_t n) {
     x[e] = 0.0f;
 }
 
-// Marks the end of an outer iteration: later launches read the new index.
-__global__ void k_next_iter(FitScalars *sc) {
-  if (threadIdx.x == 0) sc->cur += 1;
-}
-
 __global__ void k_reset_scalars(FitScalars *sc) {
   if (threadIdx.x == 0) {
-    sc->cur = 0;
+    sc->cur = -1;  // pass 1 of the first iteration makes it 0
     sc->iter = 0;
     sc->fail_iter = INT_MAX;
     sc->rank_deficient = 0;
@@ -1370,7 +1368,7 @@ static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
 #define P1(SM, CP)                                                                              \
   k_pass1<RT, SM, CP><<<grid, block, lds, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,  \
                                               p->col, p->val, p->xc, p->C, p->Vp, p->J, p->R,  \
-                                              p->l, p->T, p->FV)
+                                              p->l, p->T, p->FV, p->scal)
   if (p->l > 0) {
     if (p->compact) P1(true, true); else P1(true, false);
   } else {
@@ -1462,7 +1460,7 @@ static FitArgs fit_args(const copa_plan *p) {
   return fa;
 }
 
-// One outer iteration; the kernels read its index (within the chunk) from the device scalars,
+// One outer iteration; pass 1 advances the device iteration index and the later kernels read it,
 // so the same launches serve every iteration (and one captured graph replays them).
 template <int R>
 static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
@@ -1512,7 +1510,6 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
         gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->scal, o.prox_V,
         o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV));
   });
-  k_next_iter<<<1, 64, 0, s>>>(p->scal);
 }
 
 template <int R>
@@ -1655,8 +1652,12 @@ copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Q
   std::vector<double> hf, ho;
   FitScalars hs;
   int done = 0, chunk_start = 0, fail = -1;
+  const bool check = p->opt.stop_tol > 0.0;
+  const int every = p->opt.check_every > 0 ? p->opt.check_every : 10;
+  double stat = -1.0;
   while (done < iters) {
-    const int chunk = std::min(iters - done, p->timing ? kTimingChunk : kHistCap);
+    int chunk = std::min(iters - done, p->timing ? kTimingChunk : kHistCap);
+    if (check) chunk = std::min(chunk, every);
     if (done > 0) k_reset_scalars<<<1, 64, 0, s>>>(p->scal);
     if (p->use_graph && !p->timing) {
       cs = run_chunk_graph(p, st, chunk, s);
@@ -1679,6 +1680,16 @@ copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Q
       fail = chunk_start + hs.fail_iter;
       break;
     }
+    if (check) {
+      if (!p->qtbuf) COPA_HIP(hipMalloc((void **)&p->qtbuf, std::max<size_t>(1, (size_t)p->S * p->R) * sizeof(float)));
+      cs = launch_qtilde(p, p->qtbuf, s);
+      if (cs != COPA_OK) return cs;
+      double r[3];
+      cs = launch_stationarity(p, st->H, st->V, st->W, p->qtbuf, r, s);
+      if (cs != COPA_OK) return cs;
+      stat = std::max(r[0], std::max(r[1], r[2]));
+      if (stat < p->opt.stop_tol) break;
+    }
   }
   if (Qtilde) {
     cs = launch_qtilde(p, Qtilde, s);
@@ -1688,6 +1699,7 @@ copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Q
   if (rep) {
     rep->iters_done = done;
     rep->fail_iter = fail;
+    rep->stationarity = stat;
     if (done > 0) {
       rep->fit = hs.last_fit;
       rep->objective = hs.last_obj;

@@ -635,7 +635,7 @@ static void free_plan(copa_plan *p) {
   void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->xc, p->C, p->rk, p->Ew, p->order, p->waves,
                   p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->cptr, p->crow, p->cinfo, p->wsplit, p->pkv, p->Vp,
                   p->gpart, p->gcount,
-                  p->vpart, p->wpart, p->small, p->modes, p->scal, p->dloss, p->gradbuf,
+                  p->vpart, p->wpart, p->small, p->modes, p->scal, p->dloss, p->gradbuf, p->statbuf, p->qtbuf,
                   p->lpart};
   for (void *b : bufs)
     if (b) (void)hipFree(b);

@@ -136,3 +136,41 @@ def test_autograd_function_returns_the_adjoint():
     torch.testing.assert_close(Ht.grad, 3.0 * dH, rtol=1e-5, atol=1e-6)
     torch.testing.assert_close(Vt.grad, 3.0 * dV, rtol=1e-5, atol=1e-6)
     torch.testing.assert_close(Wt.grad, 3.0 * dW, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("cfg_name,K,R,l", [("c5", 200, 10, 0), ("c2", 300, 10, 7)])
+def test_stationarity_residual_matches_oracle(cfg_name, K, R, l):
+    """Block stationarity residuals of the penalised reconstruction loss at the GPU fit's point
+    (H, V, W, Qtilde after 4 iterations) against the FP64 oracle at the same point."""
+    import torch
+    from gpu_common import run_gpu, split_rows
+    coh, _ = synth.make_config(cfg_name, K=K)
+    g = run_gpu(coh, R, l, 4)
+    plan = g["plan"]
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).cuda()  # noqa
+    res = plan.stationarity(d(g["H"]), d(g["V"]), d(g["W"]), d(g["Qt"]))
+    opt = co.Options(R=R, prox_H=co.PROX_NONE, prox_W=co.PROX_NONNEG, prox_V=co.PROX_L1,
+                     lam_V=0.1)
+    ref = co.stationarity(co.subject_matrices(coh), split_rows(coh, g["Qt"]), g["H"], g["V"],
+                          g["W"], opt)
+    print("stationarity", cfg_name, ["%.4e/%.4e" % (a, b) for a, b in zip(res, ref)], flush=True)
+    for a, b in zip(res, ref):
+        assert abs(a - b) <= 1e-3 * b + 1e-6
+
+
+def test_stationarity_stop_rule():
+    from gpu_common import run_gpu  # noqa: F401
+    from paper_1803_04572_amd import copa
+    coh, _ = synth.make_config("c5", K=200)
+    R = 10
+    for tol, every, expect in ((10.0, 3, 3), (1e-30, 4, 12)):
+        plan = copa.Plan.from_cohort(coh, R=R, l=0, stop_tol=tol, check_every=every)
+        st = plan.new_state(*synth.init_factors(coh.K, coh.J, R, 0))
+        rep, _ = plan.fit(st, 12)
+        assert rep["iters_done"] == expect, (tol, rep["iters_done"])
+        assert 0.0 <= rep["stationarity"] < 10.0
+        assert len(rep["fit_history"]) == expect
+    plan = copa.Plan.from_cohort(coh, R=R, l=0)
+    st = plan.new_state(*synth.init_factors(coh.K, coh.J, R, 0))
+    rep, _ = plan.fit(st, 3)
+    assert rep["stationarity"] == -1.0

@@ -462,6 +462,47 @@ def test_gradient_vanishes_at_planted_truth():
         assert np.abs(g).max() < 1e-10
 
 
+def test_stationarity_vanishes_at_each_block_optimum():
+    """With Q fixed and every I_k >= R (Q_k^T Q_k = I), each factor block of the penalised loss is
+    the ADMM block problem (G_n, F_n) of Algorithm 1; ADMM run long solves it, and the block's
+    stationarity residual then vanishes, while it is clearly nonzero at the starting point."""
+    coh, _ = synth.planted_cohort(K=30, J=25, R=4, ik_lo=6, ik_hi=20, seed=31)
+    R = 4
+    prob = co.build_problem(coh, 0)
+    H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 1)
+    opt = co.Options(R=R, outer_iters=3, inner_iters=5, prox_H=co.PROX_NONE,
+                     prox_W=co.PROX_NONNEG, prox_V=co.PROX_L1, lam_V=0.5)
+    res = co.copa_fit(prob, H0, W0, V0, opt)
+    Xs = co.subject_matrices(coh)
+    Qts, H, W, V = res.Qtilde, res.H, res.W, res.V
+    r0 = co.stationarity(Xs, Qts, H, V, W, opt)
+    Xd = [X.toarray() for X in Xs]
+    # V block: G_V = H^TH * W^TW, F_V = sum_k X_k^T Q_k H S_k
+    FV = sum(Xd[k].T @ Qts[k] @ H @ np.diag(W[k]) for k in range(coh.K))
+    Vs, _, _ = co.admm_update((H.T @ H) * (W.T @ W), FV, V, np.zeros_like(V), co.PROX_L1,
+                              opt.lam_V, 4000)
+    # W block: G_W = H^TH * V^TV, F_W(k, :) = diag(H^T Q_k^T X_k V)
+    FW = np.stack([np.diag(H.T @ Qts[k].T @ Xd[k] @ V) for k in range(coh.K)])
+    Ws, _, _ = co.admm_update((H.T @ H) * (V.T @ V), FW, W, np.zeros_like(W), co.PROX_NONNEG,
+                              0.0, 4000)
+    # H block: G_H = W^TW * V^TV, F_H = sum_k Q_k^T X_k V S_k
+    FH = sum(Qts[k].T @ Xd[k] @ V @ np.diag(W[k]) for k in range(coh.K))
+    Hs, _, _ = co.admm_update((W.T @ W) * (V.T @ V), FH, H, np.zeros_like(H), co.PROX_NONE,
+                              0.0, 4000)
+    assert min(r0) > 1e-4
+    assert co.stationarity(Xs, Qts, H, Vs, W, opt)[2] < 1e-7
+    assert co.stationarity(Xs, Qts, H, V, Ws, opt)[1] < 1e-7
+    assert co.stationarity(Xs, Qts, Hs, V, W, opt)[0] < 1e-7
+
+
+def test_stationarity_zero_at_planted_truth():
+    rng = np.random.default_rng(22)
+    H, V, W, Qs, Xs = _planted_exact(rng, 5, 7, 3)
+    Xsp = [sp.csr_matrix(X) for X in Xs]
+    opt = co.Options(R=3, prox_H=co.PROX_NONE, prox_W=co.PROX_NONNEG, prox_V=co.PROX_NONE)
+    assert max(co.stationarity(Xsp, Qs, H, V, W, opt)) < 1e-12
+
+
 # ------------------------------------------------------------------ symmetry
 
 
