@@ -283,11 +283,24 @@ __global__ void __launch_bounds__(512)
       const float4 ca = c4[0], cb = c4[1];
       cr[0] = ca.x; cr[1] = ca.y; cr[2] = ca.z; cr[3] = ca.w;
       cr[4] = cb.x; cr[5] = cb.y; cr[6] = cb.z; cr[7] = cb.w;
+      // the chunk's M block (at most kChunkRows x RT floats): 4 loads in flight per thread per
+      // step, from clamped addresses, stores masked
       const int nm = nsub * l * RT;
       const float *Mb = M + (int64_t)k0 * l * R + c0;
-      for (int e = t; e < nm; e += nt) {
-        const int q = e / RT, r = e - q * RT;
-        sU[e] = Mb[(int64_t)q * R + (c0 + r < R ? r : R - 1 - c0)];
+      for (int e0 = 0; e0 < nm; e0 += 4 * nt) {
+        float mv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * nt + t;
+          const int ec = e < nm ? e : nm - 1;
+          const int q = ec / RT, r = ec - q * RT;
+          mv[u] = Mb[(int64_t)q * R + (c0 + r < R ? r : R - 1 - c0)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * nt + t;
+          sU[e < nm ? e : kChunkRows * RT] = mv[u];  // spare slot past the u rows
+        }
       }
     } else {
 #pragma unroll
@@ -411,7 +424,7 @@ __global__ void __launch_bounds__(512)
 template <int RT, bool SMOOTH>
 inline void launch_pass2c(const copa_plan *p, const float *Mrows, float *F, hipStream_t s) {
   const dim3 grid((unsigned)std::min(p->nchunks, 2 * std::max(1, p->n_cu)), (unsigned)p->tiles.nt);
-  const size_t lds = ((size_t)p->J * RT + (size_t)kChunkRows * RT) * sizeof(float);
+  const size_t lds = ((size_t)p->J * RT + (size_t)kChunkRows * RT + 1) * sizeof(float);
   k_pass2c<RT, SMOOTH><<<grid, 512, lds, s>>>(p->nchunks, p->crow, p->cinfo, p->wsplit, p->pkv,
                                              p->rowsubj, p->C, Mrows, p->J, p->R,
                                              SMOOTH ? p->l : 0, F);

@@ -602,7 +602,7 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   // ---- feature-sorted chunks for pass 2 (features < 2^16 and the F_V tile plus one chunk of
   // u rows fit in LDS)
   p->p2c = p->J <= 65536 && nnz > 0 &&
-           ((int64_t)p->J * p->tiles.rt + (int64_t)kChunkRows * p->tiles.rt) * 4 <= p->lds_limit;
+           ((int64_t)p->J * p->tiles.rt + (int64_t)kChunkRows * p->tiles.rt + 1) * 4 <= p->lds_limit;
   if (p->p2c) COPA_TRY(build_sorted_chunks(X, p, s));
   COPA_TRY(dalloc(&p->vpart, (size_t)p->n_vblocks * 4));
   {
