@@ -1,0 +1,94 @@
+"""The benchmark workload at full size (50,000 subjects, 11.5M nonzeros), through the same launch
+path bench.py times (graph replay): outputs the oracle can compute one subject at a time, and
+properties that hold at any size."""
+import numpy as np
+import pytest
+
+from oracle import copa_oracle as co
+from paper_1803_04572_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full_c2():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1803_04572_amd import copa
+    coh, cfg = synth.make_config("c2")
+    plan = copa.Plan.from_cohort(coh, R=cfg["R"], l=cfg["l"], inner_iters=cfg["inner"])
+    return coh, cfg, plan
+
+
+def _procrustes_condition(A, rtol=1e-6):
+    s = np.linalg.svd(A, compute_uv=False)
+    if s.size == 0 or s[0] == 0:
+        return 1.0
+    kept = s[s > rtol * s[0]]
+    return kept[0] / kept[-1]
+
+
+def test_full_size_first_iteration_procrustes_on_sampled_subjects(full_c2):
+    """After one outer iteration from the seeded start, Qtilde_k of 200 sampled subjects equals
+    the oracle's truncated polar factor computed from the same start, subject by subject."""
+    import torch
+    coh, cfg, plan = full_c2
+    R, l = cfg["R"], cfg["l"]
+    H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
+    st = plan.new_state(H0, W0, V0)
+    rep, Qt = plan.fit(st, 1)
+    torch.cuda.synchronize()
+    Qt = Qt.double().cpu().numpy()
+    rng = np.random.default_rng(5)
+    ks = rng.choice(coh.K, 200, replace=False)
+    worst = 0.0
+    for k in ks:
+        r0, r1 = int(coh.subj_ptr[k]), int(coh.subj_ptr[k + 1])
+        sub = synth.subset_subjects(coh, [k])
+        Xk = co.subject_matrices(sub)[0]
+        C = co.smoothing_basis(coh.days[r0:r1], l)
+        Xh = np.asarray((Xk.T @ C).T)
+        A = Xh @ V0 @ np.diag(W0[k]) @ H0.T
+        Q, _, _ = co.procrustes(A)
+        kappa = _procrustes_condition(A)
+        err = np.abs(Qt[r0:r1] - C @ Q).max(initial=0.0) / (1e-5 + 1e-6 * kappa)
+        worst = max(worst, err)
+    print("full-size Qtilde sampled worst scaled error", worst, flush=True)
+    assert worst < 1.0
+
+
+def test_full_size_fit_equals_dense_reconstruction(full_c2):
+    """20 outer iterations at full size: the reported FIT (computed on the GPU from R x R
+    products) equals 1 - sum_k ||X_k - Qtilde_k H S_k V^T||^2 / ||X||^2 recomputed in FP64 by dense
+    reconstruction from the returned factors; Qtilde_k^T Qtilde_k is a projector for sampled k."""
+    import scipy.sparse as sp
+    import torch
+    coh, cfg, plan = full_c2
+    R = cfg["R"]
+    st = plan.new_state(*synth.init_factors(coh.K, coh.J, R, 0))
+    rep, Qt = plan.fit(st, 20)
+    torch.cuda.synchronize()
+    H = st["H"].double().cpu().numpy()
+    V = st["V"].double().cpu().numpy()
+    W = st["W"].double().cpu().numpy()
+    Qt = Qt.double().cpu().numpy()
+    X = sp.csr_matrix((coh.val.astype(np.float64), coh.col, coh.row_ptr), shape=(coh.S, coh.J))
+    rowsubj = np.repeat(np.arange(coh.K), np.diff(coh.subj_ptr))
+    resid = 0.0
+    step = 65536
+    for r0 in range(0, coh.S, step):
+        r1 = min(coh.S, r0 + step)
+        model = ((Qt[r0:r1] @ H) * W[rowsubj[r0:r1]]) @ V.T
+        D = X[r0:r1].toarray() - model
+        resid += float(np.einsum("ij,ij->", D, D))
+    norm2 = float(X.multiply(X).sum())
+    fit_dense = 1.0 - resid / norm2
+    rel = abs(rep["fit"] - fit_dense) / abs(fit_dense)
+    print("full-size FIT gpu", rep["fit"], "dense", fit_dense, "rel", rel, flush=True)
+    assert rel <= 1e-5
+    rng = np.random.default_rng(6)
+    for k in rng.choice(coh.K, 200, replace=False):
+        r0, r1 = int(coh.subj_ptr[k]), int(coh.subj_ptr[k + 1])
+        P = Qt[r0:r1].T @ Qt[r0:r1]
+        assert np.abs(P @ P - P).max() < 1e-5
