@@ -330,58 +330,86 @@ __device__ __forceinline__ void jacobi8(double (&A)[kNMax][kNMax], double (&V)[k
   }
 }
 
-// Same eigensolver on a packed upper triangle (N (N + 1) / 2 values), for the register-resident
-// path; N is the padded problem size.
+// Eigensolver on a packed upper triangle (N (N + 1) / 2 values), for the register-resident path;
+// N is the padded problem size.
 template <int N>
 __host__ __device__ constexpr int triN(int i, int j) {
   return i <= j ? N * i - (i * (i - 1)) / 2 + (j - i) : N * j - (j * (j - 1)) / 2 + (i - j);
 }
 
-// With INIT = false, V holds an orthogonal matrix on entry and the rotations are accumulated onto
-// it: then A must be V^T G V and on return V holds the eigenvectors of G.
-template <int N, bool INIT = true>
-__device__ __forceinline__ void jacobi_tri(double (&A)[N * (N + 1) / 2], double (&V)[N][N]) {
-  if constexpr (INIT) {
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = 0; j < N; ++j) V[i][j] = i == j ? 1.0 : 0.0;
-  }
+// Round-robin ("circle") order of the index pairs: with M players (N rounded up to even; an odd N
+// adds one that sits out), round r pairs r with M - 1 and (r + m) with (r - m) mod (M - 1) for
+// m = 1 .. M/2 - 1. Every pair meets once in M - 1 rounds and the pairs of a round are disjoint.
+__host__ __device__ constexpr int rr_lo(int M, int r, int m) {
+  const int a = m == 0 ? r : (r + m) % (M - 1), b = m == 0 ? M - 1 : (r - m + (M - 1)) % (M - 1);
+  return a < b ? a : b;
+}
+__host__ __device__ constexpr int rr_hi(int M, int r, int m) {
+  const int a = m == 0 ? r : (r + m) % (M - 1), b = m == 0 ? M - 1 : (r - m + (M - 1)) % (M - 1);
+  return a < b ? b : a;
+}
+
+// Cyclic Jacobi in round-robin order. On entry V holds an orthogonal matrix and A = V^T G V; the
+// rotations are accumulated onto V, so on return V holds the eigenvectors of G and A's diagonal
+// its eigenvalues. The rotations of one round act on disjoint index pairs, so they commute: their
+// angles are all taken from the matrix at the start of the round (independent dependency chains
+// for the scheduler) and then applied one after the other. No branches: a pair whose entry is at
+// or below the threshold gets the identity rotation. The sweep loop ends for the whole wavefront
+// once no lane has an off-diagonal entry above the threshold.
+template <int N>
+__device__ __forceinline__ void jacobi_rr(double (&A)[N * (N + 1) / 2], double (&V)[N][N]) {
+  constexpr int M = N + (N & 1);
+  constexpr int P = M / 2;
   double scale = 0.0;
 #pragma unroll
   for (int i = 0; i < N; ++i) scale += fabs(A[triN<N>(i, i)]);
   const double tiny = 1e-300 + 1e-17 * scale;
   for (int sweep = 0; sweep < 16; ++sweep) {
-    bool rotated = false;
+    bool big = false;
 #pragma unroll
-    for (int p = 0; p < N - 1; ++p) {
+    for (int p = 0; p < N - 1; ++p)
 #pragma unroll
-      for (int q = p + 1; q < N; ++q) {
+      for (int q = p + 1; q < N; ++q) big = big || fabs(A[triN<N>(p, q)]) > tiny;
+    if (!__any(big)) break;
+#pragma unroll
+    for (int r = 0; r < M - 1; ++r) {
+      double tt[P], cc[P], ss[P];
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        const int p = rr_lo(M, r, m), q = rr_hi(M, r, m);
+        if (q >= N) continue;
         const double apq = A[triN<N>(p, q)];
-        if (fabs(apq) > tiny) {
-          rotated = true;
-          double t, c, s;
-          jacobi_cs(A[triN<N>(p, p)], A[triN<N>(q, q)], apq, t, c, s);
+        const bool on = fabs(apq) > tiny;
+        double t, c, s;
+        jacobi_cs(A[triN<N>(p, p)], A[triN<N>(q, q)], on ? apq : 1.0, t, c, s);
+        tt[m] = on ? t : 0.0;
+        cc[m] = on ? c : 1.0;
+        ss[m] = on ? s : 0.0;
+      }
 #pragma unroll
-          for (int k = 0; k < N; ++k) {
-            if (k == p || k == q) continue;
-            const double akp = A[triN<N>(k, p)], akq = A[triN<N>(k, q)];
-            A[triN<N>(k, p)] = c * akp - s * akq;
-            A[triN<N>(k, q)] = s * akp + c * akq;
-          }
-          A[triN<N>(p, p)] -= t * apq;
-          A[triN<N>(q, q)] += t * apq;
-          A[triN<N>(p, q)] = 0.0;
+      for (int m = 0; m < P; ++m) {
+        const int p = rr_lo(M, r, m), q = rr_hi(M, r, m);
+        if (q >= N) continue;
+        const double t = tt[m], c = cc[m], s = ss[m];
+        const double apq = A[triN<N>(p, q)];
 #pragma unroll
-          for (int k = 0; k < N; ++k) {
-            const double vkp = V[k][p], vkq = V[k][q];
-            V[k][p] = c * vkp - s * vkq;
-            V[k][q] = s * vkp + c * vkq;
-          }
+        for (int k = 0; k < N; ++k) {
+          if (k == p || k == q) continue;
+          const double akp = A[triN<N>(k, p)], akq = A[triN<N>(k, q)];
+          A[triN<N>(k, p)] = c * akp - s * akq;
+          A[triN<N>(k, q)] = s * akp + c * akq;
+        }
+        A[triN<N>(p, p)] -= t * apq;
+        A[triN<N>(q, q)] += t * apq;
+        A[triN<N>(p, q)] = t != 0.0 ? 0.0 : apq;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - s * vkq;
+          V[k][q] = s * vkp + c * vkq;
         }
       }
     }
-    if (!rotated) break;
   }
 }
 
@@ -729,38 +757,85 @@ __global__ void __launch_bounds__(64)
   if (lane == 0 && rank < (m < R ? m : R)) atomicAdd(&sc->rank_def_slot[sc->cur & 1], 1);
 }
 
-// Smoothed subjects (l <= N <= 8 projected rows) with R <= 16: the same computation with T and A
-// held in registers and LDS, rows unrolled to N (rows at or past l are zero; N = l = 7 is the
-// usual instance, N = 8 the general one).
+// Smoothed subjects (l <= N <= 8 projected rows) with R <= 16: one subject per lane, the
+// eigenproblem in registers, A in LDS (FP64 where it fits), H in LDS as FP64 (N = l = 7 is the
+// usual instance, N = 8 the general one; rows at or past l are zero). The 64 subjects of a block
+// own one contiguous run of T rows and of Q rows, so both move through LDS (the A area, before
+// and after A is live) with coalesced 16-byte loads and stores instead of each lane touching its
+// own rows in memory. LDS stays at or below 40 KB, so four blocks fit a compute unit and a
+// 50,000-subject launch is resident at once.
+template <int R, int N>
+struct ProcS {
+  static constexpr bool kDoubleA = N * R * 64 * 8 + R * R * 8 <= 40960;
+  using AT = std::conditional_t<kDoubleA, double, float>;
+};
+
+// dst[0, n) = src[0, n) by the 64 lanes of one wavefront, 16 bytes per lane per step with up to
+// 8 steps in flight; both pointers 16-byte aligned
+__device__ __forceinline__ void copy_run(float *__restrict__ dst, const float *__restrict__ src,
+                                         int n, int lane) {
+  const int n4 = n >> 2;
+  const float4 *s4 = reinterpret_cast<const float4 *>(src);
+  float4 *d4 = reinterpret_cast<float4 *>(dst);
+  for (int e0 = 0; e0 < n4; e0 += 8 * 64) {
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 64 + lane;
+      v[u] = s4[e < n4 ? e : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 64 + lane;
+      if (e < n4) d4[e] = v[u];
+    }
+  }
+  for (int e = 4 * n4 + lane; e < n; e += 64) dst[e] = src[e];
+}
+
 template <int R, int N>
 __global__ void __launch_bounds__(64)
     k_procrustes_s(int64_t K, int l, const int32_t *__restrict__ rk, const float *__restrict__ T,
                    float *__restrict__ Q, const float *__restrict__ H, const float *__restrict__ W,
                    float *__restrict__ Ew, double rtol, FitScalars *sc) {
+  using AT = typename ProcS<R, N>::AT;
   constexpr int NT = N * (N + 1) / 2;
-  __shared__ float sH[R * R];
-  __shared__ float sA[N * R * 64];  // A of this lane's subject, element (i, c) at (i R + c) 64 + lane
+  __shared__ double sH[R * R];
+  // A of this lane's subject, element (i, c) at (i R + c) 64 + lane; before that the block's T
+  // rows and afterwards its Q rows (64 l R <= 64 N R floats)
+  __shared__ __align__(16) AT sA[N * R * 64];
+  float *sTQ = reinterpret_cast<float *>(sA);
   const int lane = threadIdx.x;
-  for (int e = lane; e < R * R; e += blockDim.x) sH[e] = H[e];
+  const int64_t k0 = (int64_t)blockIdx.x * 64;
+  const int nsub = (int)(K - k0 < 64 ? K - k0 : 64);
+  for (int e = lane; e < R * R; e += blockDim.x) sH[e] = (double)H[e];
+  copy_run(sTQ, T + k0 * l * R, nsub * l * R, lane);
   __syncthreads();
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + lane;
-  if (k >= K) return;
-  const int64_t base = k * l;
+  // lanes past the last subject redo the block's first subject and store nothing
+  const bool live = lane < nsub;
+  const int tl = live ? lane : 0;
+  const int64_t k = k0 + tl;
   {
+    float tv[N][R];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int r = 0; r < R; ++r) tv[i][r] = sTQ[(tl * l + (i < l ? i : 0)) * R + r];
+    __syncthreads();  // the T rows are in registers: the area takes A from here on
     float w[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) w[r] = W[k * R + r];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const float *t = T + (base + (i < l ? i : 0)) * R;
-      float z[R];
+      double z[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) z[r] = t[r] * w[r];
+      for (int r = 0; r < R; ++r) z[r] = (double)(tv[i][r] * w[r]);
+#pragma unroll
       for (int c = 0; c < R; ++c) {
         double s = 0.0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) s += (double)z[r] * (double)sH[c * R + r];
-        sA[(i * R + c) * 64 + lane] = i < l ? (float)s : 0.0f;
+        for (int r = 0; r < R; ++r) s += z[r] * sH[c * R + r];
+        sA[(i * R + c) * 64 + lane] = i < l ? (AT)s : (AT)0;
       }
     }
   }
@@ -796,11 +871,13 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
       for (int q = p; q < N; ++q) G[triN<N>(p, q)] += a[p] * a[q];
   }
-  jacobi_tri<N, false>(G, E);
+  jacobi_rr<N>(G, E);
+  if (live) {
 #pragma unroll
-  for (int i = 0; i < N; ++i)
+    for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < N; ++j) Ew[(int64_t)(i * kNMax + j) * K + k] = (float)E[i][j];
+      for (int j = 0; j < N; ++j) Ew[(int64_t)(i * kNMax + j) * K + k] = (float)E[i][j];
+  }
   double lmax = 0.0;
 #pragma unroll
   for (int j = 0; j < N; ++j) lmax = fmax(lmax, G[triN<N>(j, j)]);
@@ -823,26 +900,50 @@ __global__ void __launch_bounds__(64)
       for (int q = 0; q < N; ++q) s += E[i][q] * f[q] * E[j][q];
       G[triN<N>(i, j)] = s;
     }
+  float qv[N][R];
+  if (rows_side) {
+    // Q = B A, one column of A at a time
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    if (i < l) {
-      float *dst = Q + (base + i) * R;
+    for (int c = 0; c < R; ++c) {
+      double a[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) a[j] = Aat(j, c);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += G[triN<N>(i, j)] * a[j];
+        qv[i][c] = (float)s;
+      }
+    }
+  } else {
+    // Q = A B (B is R x R, padded to N with zero rows and columns), one row of A at a time
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double a[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) a[j] = j < R ? Aat(i, j < R ? j : 0) : 0.0;
+#pragma unroll
       for (int c = 0; c < R; ++c) {
         double s = 0.0;
-        if (rows_side) {
+        if (c < N) {
 #pragma unroll
-          for (int j = 0; j < N; ++j) s += G[triN<N>(i, j)] * Aat(j, c);
-        } else {
-#pragma unroll
-          for (int j = 0; j < N; ++j)
-            if (j < R && c < N) s += Aat(i, j) * G[triN<N>(j, c < N ? c : 0)];
+          for (int j = 0; j < N; ++j) s += a[j] * G[triN<N>(j, c < N ? c : 0)];
         }
-        dst[c] = (float)s;
+        qv[i][c] = (float)s;
       }
     }
   }
   const int meff = rk[k];
-  if (rank < (meff < R ? meff : R)) atomicAdd(&sc->rank_def_slot[sc->cur & 1], 1);
+  if (live && rank < (meff < R ? meff : R)) atomicAdd(&sc->rank_def_slot[sc->cur & 1], 1);
+  __syncthreads();  // A is consumed: the area takes the Q rows
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if (i < l)
+#pragma unroll
+      for (int c = 0; c < R; ++c) sTQ[(lane * l + i) * R + c] = qv[i][c];
+  __syncthreads();
+  copy_run(Q + k0 * l * R, sTQ, nsub * l * R, lane);
 }
 
 // ======================================================================= ADMM helpers
