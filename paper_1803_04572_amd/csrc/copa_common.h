@@ -229,4 +229,47 @@ __device__ __forceinline__ float xor_step_sum(float v) {
   return v + __int_as_float(y);
 }
 
+// Recursive-halving reduce-scatter over groups of G = 2^g <= 16 lanes (G wave-uniform, sub =
+// lane index within the group). v[0, E) holds each lane's partial values of E elements (E a
+// multiple of G); on return v[m], m < E / G, holds the group total of element m G + sub. Step b
+// (from the top bit down) pairs each lane with a partner that differs in bit b and agrees on
+// every higher bit (row mirror for b = 3, half-row mirror for b = 2, quad permutes for b = 1, 0,
+// all DPP): the lane keeps the half of its elements whose bit b matches its own, and adds the
+// partner's copy of that half. The four partner maps generate all 16 lanes of a row.
+template <int E, int G, int B>
+__device__ __forceinline__ void reduce_scatter_step(float (&v)[E], int sub) {
+  constexpr int g = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : 4;
+  constexpr int half = 1 << B;
+  constexpr int n = E >> (g - 1 - B);  // values held before this step
+  // bitwise selects (a select between two array elements would become a dynamic index and
+  // move the array to scratch memory)
+  const int upm = -((sub >> B) & 1);
+#pragma unroll
+  for (int i = 0; i < n / 2; ++i) {
+    const int m = i / half, s = i - m * half;
+    const int lo = m * 2 * half + s, hi = lo + half;
+    const int xl = __float_as_int(v[lo]), xh = __float_as_int(v[hi]);
+    const float keep = __int_as_float((xh & upm) | (xl & ~upm));
+    const int send = (xl & upm) | (xh & ~upm);
+    int recv;
+    if constexpr (B == 3)
+      recv = __builtin_amdgcn_mov_dpp(send, 0x140, 0xF, 0xF, false);  // row_mirror
+    else if constexpr (B == 2)
+      recv = __builtin_amdgcn_mov_dpp(send, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    else if constexpr (B == 1)
+      recv = __builtin_amdgcn_mov_dpp(send, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    else
+      recv = __builtin_amdgcn_mov_dpp(send, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    v[i] = keep + __int_as_float(recv);
+  }
+  if constexpr (B > 0) reduce_scatter_step<E, G, B - 1>(v, sub);
+}
+
+template <int E, int G>
+__device__ __forceinline__ void reduce_scatter(float (&v)[E], int sub) {
+  static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0 && E % G == 0, "group size");
+  constexpr int g = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : 4;
+  if constexpr (g > 0) reduce_scatter_step<E, G, g - 1>(v, sub);
+}
+
 }  // namespace copa

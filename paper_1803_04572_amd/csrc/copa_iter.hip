@@ -172,27 +172,54 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
           for (int r = 0; r < RT; ++r) acc[a][r] += c[a] * t[r];
       }
-      // sum over the subject's G lanes (wave-uniform G; every lane ends with the totals)
-      auto step = [&](auto mc) {
-        constexpr int Mv = decltype(mc)::value;
+      // sum over the subject's G lanes (wave-uniform G). Up to G = 16 a reduce-scatter: each
+      // lane ends with the totals of the elements e = m G + sub of the l x RT block (e = a RT + r),
+      // which it stores, so the subject's G lanes write consecutive words. Larger G: every lane
+      // sums everything (xor steps) and stores its share.
+      constexpr int E = kLMax * RT;
+      float v[E];
 #pragma unroll
-        for (int a = 0; a < kLMax; ++a)
+      for (int a = 0; a < kLMax; ++a)
 #pragma unroll
-          for (int r = 0; r < RT; ++r) acc[a][r] = xor_step_sum<Mv>(acc[a][r]);
+        for (int r = 0; r < RT; ++r) v[a * RT + r] = acc[a][r];
+      float *dst = T + (int64_t)k * l * R + c0;
+      auto scatter_store = [&](auto gc) {
+        constexpr int Gc = decltype(gc)::value;
+        reduce_scatter<E, Gc>(v, sub);
+        if (active) {
+#pragma unroll
+          for (int m = 0; m < E / Gc; ++m) {
+            const int e = m * Gc + sub, a = e / RT, r = e - a * RT;
+            if (a < l && c0 + r < R) dst[a * R + r] = v[m];
+          }
+        }
       };
-      if (G > 1) step(std::integral_constant<int, 1>{});
-      if (G > 2) step(std::integral_constant<int, 2>{});
-      if (G > 4) step(std::integral_constant<int, 4>{});
-      if (G > 8) step(std::integral_constant<int, 8>{});
-      if (G > 16) step(std::integral_constant<int, 16>{});
-      if (G > 32) step(std::integral_constant<int, 32>{});
-      if (active) {
-        float *dst = T + (int64_t)k * l * R + c0;
+      if (lg == 0) scatter_store(std::integral_constant<int, 1>{});
+      else if (lg == 1) scatter_store(std::integral_constant<int, 2>{});
+      else if (lg == 2) scatter_store(std::integral_constant<int, 4>{});
+      else if (lg == 3) scatter_store(std::integral_constant<int, 8>{});
+      else if (lg == 4 && E % 16 == 0) {
+        if constexpr (E % 16 == 0) scatter_store(std::integral_constant<int, 16>{});
+      }
+      else {
+        auto step = [&](auto mc) {
+          constexpr int Mv = decltype(mc)::value;
 #pragma unroll
-        for (int a = 0; a < kLMax; ++a)
+          for (int e = 0; e < E; ++e) v[e] = xor_step_sum<Mv>(v[e]);
+        };
+        step(std::integral_constant<int, 1>{});
+        step(std::integral_constant<int, 2>{});
+        step(std::integral_constant<int, 4>{});
+        step(std::integral_constant<int, 8>{});
+        if (G > 16) step(std::integral_constant<int, 16>{});
+        if (G > 32) step(std::integral_constant<int, 32>{});
+        if (active) {
 #pragma unroll
-          for (int r = 0; r < RT; ++r)
-            if (a < l && c0 + r < R && ((a * RT + r) & (G - 1)) == sub) dst[a * R + r] = acc[a][r];
+          for (int a = 0; a < kLMax; ++a)
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+              if (a < l && c0 + r < R && ((a * RT + r) & (G - 1)) == sub) dst[a * R + r] = v[a * RT + r];
+        }
       }
     } else if (active) {
       for (int i = r0 + sub; i < r1; i += G) {
