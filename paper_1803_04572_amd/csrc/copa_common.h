@@ -207,38 +207,17 @@ __device__ __forceinline__ float dpp_f(float old, float v) {
       __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWMASK, 0xF, false));
 }
 
-// v + (v of lane ^ M) for aligned lane groups, when the groups of M lanes below have already been
-// summed this way (then every lane of a 2M group ends with the same total): quad permutes for
-// M = 1, 2, half-row and row mirrors for M = 4, 8 (DPP, no LDS), swizzle for 16, permute for 32.
-template <int M>
-__device__ __forceinline__ float xor_step_sum(float v) {
-  const int x = __float_as_int(v);
-  int y;
-  if constexpr (M == 1)
-    y = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
-  else if constexpr (M == 2)
-    y = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
-  else if constexpr (M == 4)
-    y = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);  // row_half_mirror
-  else if constexpr (M == 8)
-    y = __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false);  // row_mirror
-  else if constexpr (M == 16)
-    y = __builtin_amdgcn_ds_swizzle(x, 0x401F);  // xor 16 within 32 lanes
-  else
-    y = __float_as_int(__shfl_xor(v, 32, kWave));
-  return v + __int_as_float(y);
-}
-
-// Recursive-halving reduce-scatter over groups of G = 2^g <= 16 lanes (G wave-uniform, sub =
+// Recursive-halving reduce-scatter over groups of G = 2^g <= 64 lanes (G wave-uniform, sub =
 // lane index within the group). v[0, E) holds each lane's partial values of E elements (E a
 // multiple of G); on return v[m], m < E / G, holds the group total of element m G + sub. Step b
 // (from the top bit down) pairs each lane with a partner that differs in bit b and agrees on
-// every higher bit (row mirror for b = 3, half-row mirror for b = 2, quad permutes for b = 1, 0,
-// all DPP): the lane keeps the half of its elements whose bit b matches its own, and adds the
-// partner's copy of that half. The four partner maps generate all 16 lanes of a row.
+// every higher bit (b = 5: xor 32 by permute; b = 4: xor 16 by swizzle; b = 3, 2: row and
+// half-row mirrors, b = 1, 0: quad permutes, all DPP): the lane keeps the half of its elements
+// whose bit b matches its own, and adds the partner's copy of that half. The partner maps
+// generate every lane of the group.
 template <int E, int G, int B>
 __device__ __forceinline__ void reduce_scatter_step(float (&v)[E], int sub) {
-  constexpr int g = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : 4;
+  constexpr int g = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
   constexpr int half = 1 << B;
   constexpr int n = E >> (g - 1 - B);  // values held before this step
   // bitwise selects (a select between two array elements would become a dynamic index and
@@ -252,7 +231,11 @@ __device__ __forceinline__ void reduce_scatter_step(float (&v)[E], int sub) {
     const float keep = __int_as_float((xh & upm) | (xl & ~upm));
     const int send = (xl & upm) | (xh & ~upm);
     int recv;
-    if constexpr (B == 3)
+    if constexpr (B == 5)
+      recv = __shfl_xor(send, 32, kWave);
+    else if constexpr (B == 4)
+      recv = __builtin_amdgcn_ds_swizzle(send, 0x401F);  // xor 16 within 32 lanes
+    else if constexpr (B == 3)
       recv = __builtin_amdgcn_mov_dpp(send, 0x140, 0xF, 0xF, false);  // row_mirror
     else if constexpr (B == 2)
       recv = __builtin_amdgcn_mov_dpp(send, 0x141, 0xF, 0xF, false);  // row_half_mirror
@@ -267,8 +250,8 @@ __device__ __forceinline__ void reduce_scatter_step(float (&v)[E], int sub) {
 
 template <int E, int G>
 __device__ __forceinline__ void reduce_scatter(float (&v)[E], int sub) {
-  static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0 && E % G == 0, "group size");
-  constexpr int g = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : 4;
+  static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0 && E % G == 0, "group size");
+  constexpr int g = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
   if constexpr (g > 0) reduce_scatter_step<E, G, g - 1>(v, sub);
 }
 

@@ -172,54 +172,35 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
           for (int r = 0; r < RT; ++r) acc[a][r] += c[a] * t[r];
       }
-      // sum over the subject's G lanes (wave-uniform G). Up to G = 16 a reduce-scatter: each
-      // lane ends with the totals of the elements e = m G + sub of the l x RT block (e = a RT + r),
-      // which it stores, so the subject's G lanes write consecutive words. Larger G: every lane
-      // sums everything (xor steps) and stores its share.
+      // sum over the subject's G lanes (wave-uniform G) by a reduce-scatter: each lane ends
+      // with the totals of the elements e = m G + sub of the l x RT block (e = a RT + r; the
+      // element list is padded with zeros to a multiple of G), which it stores, so the
+      // subject's G lanes write consecutive words
       constexpr int E = kLMax * RT;
-      float v[E];
-#pragma unroll
-      for (int a = 0; a < kLMax; ++a)
-#pragma unroll
-        for (int r = 0; r < RT; ++r) v[a * RT + r] = acc[a][r];
       float *dst = T + (int64_t)k * l * R + c0;
       auto scatter_store = [&](auto gc) {
         constexpr int Gc = decltype(gc)::value;
-        reduce_scatter<E, Gc>(v, sub);
+        constexpr int Ep = (E + Gc - 1) / Gc * Gc;
+        float v[Ep];
+#pragma unroll
+        for (int e = 0; e < Ep; ++e) v[e] = e < E ? acc[e / RT][e % RT] : 0.0f;
+        reduce_scatter<Ep, Gc>(v, sub);
         if (active) {
 #pragma unroll
-          for (int m = 0; m < E / Gc; ++m) {
+          for (int m = 0; m < Ep / Gc; ++m) {
             const int e = m * Gc + sub, a = e / RT, r = e - a * RT;
-            if (a < l && c0 + r < R) dst[a * R + r] = v[m];
+            if (e < E && a < l && c0 + r < R) dst[a * R + r] = v[m];
           }
         }
       };
-      if (lg == 0) scatter_store(std::integral_constant<int, 1>{});
-      else if (lg == 1) scatter_store(std::integral_constant<int, 2>{});
-      else if (lg == 2) scatter_store(std::integral_constant<int, 4>{});
-      else if (lg == 3) scatter_store(std::integral_constant<int, 8>{});
-      else if (lg == 4 && E % 16 == 0) {
-        if constexpr (E % 16 == 0) scatter_store(std::integral_constant<int, 16>{});
-      }
-      else {
-        auto step = [&](auto mc) {
-          constexpr int Mv = decltype(mc)::value;
-#pragma unroll
-          for (int e = 0; e < E; ++e) v[e] = xor_step_sum<Mv>(v[e]);
-        };
-        step(std::integral_constant<int, 1>{});
-        step(std::integral_constant<int, 2>{});
-        step(std::integral_constant<int, 4>{});
-        step(std::integral_constant<int, 8>{});
-        if (G > 16) step(std::integral_constant<int, 16>{});
-        if (G > 32) step(std::integral_constant<int, 32>{});
-        if (active) {
-#pragma unroll
-          for (int a = 0; a < kLMax; ++a)
-#pragma unroll
-            for (int r = 0; r < RT; ++r)
-              if (a < l && c0 + r < R && ((a * RT + r) & (G - 1)) == sub) dst[a * R + r] = v[a * RT + r];
-        }
+      switch (lg) {
+        case 0: scatter_store(std::integral_constant<int, 1>{}); break;
+        case 1: scatter_store(std::integral_constant<int, 2>{}); break;
+        case 2: scatter_store(std::integral_constant<int, 4>{}); break;
+        case 3: scatter_store(std::integral_constant<int, 8>{}); break;
+        case 4: scatter_store(std::integral_constant<int, 16>{}); break;
+        case 5: scatter_store(std::integral_constant<int, 32>{}); break;
+        default: scatter_store(std::integral_constant<int, 64>{}); break;
       }
     } else if (active) {
       for (int i = r0 + sub; i < r1; i += G) {
