@@ -207,6 +207,10 @@ __device__ __forceinline__ float dpp_f(float old, float v) {
       __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWMASK, 0xF, false));
 }
 
+// Row width of an LDS factor tile: RT floats rounded up to a multiple of 4, so that a row moves
+// with 16-byte LDS accesses (three instead of five for RT = 10).
+__host__ __device__ constexpr int row4(int rt) { return (rt + 3) & ~3; }
+
 // Recursive-halving reduce-scatter over groups of G = 2^g <= 64 lanes (G wave-uniform, sub =
 // lane index within the group). v[0, E) holds each lane's partial values of E elements (E a
 // multiple of G); on return v[m], m < E / G, holds the group total of element m G + sub. Step b

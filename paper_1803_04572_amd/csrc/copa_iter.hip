@@ -42,7 +42,7 @@ Tiles choose_tiles(int R, int64_t J, int lds_limit) {
   int nt = (R + 15) / 16;
   for (;; ++nt) {
     int rt = (R + nt - 1) / nt;
-    int rtp = (rt + 3) & ~3;
+    int rtp = row4(rt);
     if ((int64_t)J * rtp * 4 + 16 <= lds_limit || rt == 1) return Tiles{nt, rt};
   }
 }
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256)
             const uint32_t *__restrict__ xc,
             const float *__restrict__ C, const float *__restrict__ Vp, int64_t J, int R, int l,
             float *__restrict__ T, float *__restrict__ FV, FitScalars *sc) {
-  constexpr int RTP = (RT + 3) & ~3;
+  constexpr int RTP = row4(RT);
   extern __shared__ float4 smem4[];
   // pass 1 opens an outer iteration: advance the device iteration index (no other launch of the
   // iteration reads it before pass 1 ends)
@@ -1469,7 +1469,7 @@ __global__ void __launch_bounds__(256)
 // ======================================================================= host launchers
 template <int RT>
 static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
-  constexpr int RTP = (RT + 3) & ~3;
+  constexpr int RTP = row4(RT);
   size_t lds = (size_t)p->J * RTP * sizeof(float) + sizeof(float4);  // + the spare slot
   const int per_cu = std::max(1, std::min(4, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
   const int nb = std::max(1, std::min((p->n_waves + 3) / 4, p->n_cu * per_cu));
@@ -1615,7 +1615,7 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   timed(p, s, kidPass2, [&] { RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s); });
   timed(p, s, kidVadmm, [&] {
     k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(
-        p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, (p->tiles.rt + 3) & ~3,
+        p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, row4(p->tiles.rt),
         gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->scal, o.prox_V,
         o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV));
   });
@@ -1630,7 +1630,7 @@ static void init_grams_r(copa_plan *p, const copa_state *st, hipStream_t s) {
         p->Ew, p->K);
   if (p->J > 0)
     k_pad_V<R><<<(unsigned)((p->J * R + 255) / 256), 256, 0, s>>>(
-        st->V, p->Vp, p->J, p->tiles.rt, (p->tiles.rt + 3) & ~3);
+        st->V, p->Vp, p->J, p->tiles.rt, row4(p->tiles.rt));
   gram<R>(p, st->W, st->W, p->K, nullptr, 0, kSlotWtW, st->V, p->J, kSlotVtV, s);
   k_init_small<R><<<1, 256, 0, s>>>(gram_total(p, kSlotWtW), gram_total(p, kSlotVtV), 1,
                                     p->small);

@@ -237,12 +237,14 @@ __global__ void __launch_bounds__(512)
              const int32_t *__restrict__ rowsubj,
              const float *__restrict__ C, const float *__restrict__ M, int64_t J, int R, int l,
              float *__restrict__ FV) {
+  // F_V tile and u rows with rows padded to RTP floats (16-byte LDS accesses; the pad stays 0)
+  constexpr int RTP = row4(RT);
   extern __shared__ float4 smem4[];
   float *sF = reinterpret_cast<float *>(smem4);
-  float *sU = sF + J * RT;  // u rows of the chunk; first holds the chunk's M block
+  float *sU = sF + J * RTP;  // u rows of the chunk; first holds the chunk's M block (RT wide)
   const int c0 = blockIdx.y * RT;
   const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wave = t >> 6;
-  for (int64_t e = t; e < J * RT; e += nt) sF[e] = 0.0f;
+  for (int64_t e = t; e < J * RTP; e += nt) sF[e] = 0.0f;
   int nr0 = 0, nr1 = 0, nk0 = 0, nns = 0, ns0 = 0, ns1 = 0;
   auto fetch = [&](int cc) {
     if (cc < nchunks) {
@@ -275,7 +277,9 @@ __global__ void __launch_bounds__(512)
     const int tc = t < n ? t : 0;
     float cr[kLMax];
     int kl = 0;
-    float u[RT];
+    float u[RTP];
+#pragma unroll
+    for (int r = RT; r < RTP; ++r) u[r] = 0.0f;
     if constexpr (SMOOTH) {
       const int64_t i = r0 + tc;
       kl = rowsubj[i] - k0;
@@ -321,13 +325,28 @@ __global__ void __launch_bounds__(512)
       __syncthreads();
     }
     if (t < n) {
+      float4 *d4 = reinterpret_cast<float4 *>(sU + t * RTP);
 #pragma unroll
-      for (int r = 0; r < RT; ++r) sU[t * RT + r] = u[r];
+      for (int q = 0; q < RTP / 4; ++q)
+        d4[q] = make_float4(u[4 * q], u[4 * q + 1], u[4 * q + 2], u[4 * q + 3]);
     }
     __syncthreads();
-    float acc[RT], head[RT];
+    // sF[j] += v over a padded row (pad entries of v are zero)
+    auto add_row = [&](int j, const float *v) {
+      float4 *f4 = reinterpret_cast<float4 *>(sF + j * RTP);
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
+      for (int q = 0; q < RTP / 4; ++q) {
+        float4 f = f4[q];
+        f.x += v[4 * q];
+        f.y += v[4 * q + 1];
+        f.z += v[4 * q + 2];
+        f.w += v[4 * q + 3];
+        f4[q] = f;
+      }
+    };
+    float acc[RTP], head[RTP];
+#pragma unroll
+    for (int r = 0; r < RTP; ++r) {
       acc[r] = 0.0f;
       head[r] = 0.0f;
     }
@@ -347,24 +366,29 @@ __global__ void __launch_bounds__(512)
         const uint32_t key = kv[q];
         const int j = (int)(key >> 16);
         const float x = xv[q];
-        const float *ur = sU + (key & 0xffffu) * RT;
+        const float4 *ur = reinterpret_cast<const float4 *>(sU + (key & 0xffffu) * RTP);
         if (j != cur) {
           if (nseg == 1) {
             hkey = cur;
 #pragma unroll
-            for (int r = 0; r < RT; ++r) head[r] = acc[r];
+            for (int r = 0; r < RTP; ++r) head[r] = acc[r];
           } else if (nseg > 1) {
             // a segment that starts and ends inside this lane's run: no other lane has it
-#pragma unroll
-            for (int r = 0; r < RT; ++r) sF[cur * RT + r] += acc[r];
+            add_row(cur, acc);
           }
           cur = j;
           ++nseg;
 #pragma unroll
-          for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
+          for (int r = 0; r < RTP; ++r) acc[r] = 0.0f;
         }
 #pragma unroll
-        for (int r = 0; r < RT; ++r) acc[r] += x * ur[r];
+        for (int qq = 0; qq < RTP / 4; ++qq) {
+          const float4 uv = ur[qq];
+          acc[4 * qq] += x * uv.x;
+          acc[4 * qq + 1] += x * uv.y;
+          acc[4 * qq + 2] += x * uv.z;
+          acc[4 * qq + 3] += x * uv.w;
+        }
       }
     }
     // tail segment (cur, acc); the first key of this lane's run is hkey (several segments) or cur
@@ -382,7 +406,7 @@ __global__ void __launch_bounds__(512)
 #pragma unroll
         for (int r = 0; r < RT; ++r) acc[r] += vp[r];
       }
-    };
+    };  // (the pad entries of acc stay zero)
     seg_step(std::integral_constant<int, 0x111>{}, std::integral_constant<int, 0xF>{});
     seg_step(std::integral_constant<int, 0x112>{}, std::integral_constant<int, 0xF>{});
     seg_step(std::integral_constant<int, 0x114>{}, std::integral_constant<int, 0xF>{});
@@ -391,30 +415,28 @@ __global__ void __launch_bounds__(512)
     seg_step(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
     const int knext = dpp_i<0x130>(-1, first);   // lane + 1
     const int kprev1 = dpp_i<0x138>(-1, cur);    // lane - 1
-    float carry[RT];
+    float carry[RTP];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) carry[r] = dpp_f<0x138>(0.0f, acc[r]);
+    for (int r = 0; r < RTP; ++r) carry[r] = r < RT ? dpp_f<0x138>(0.0f, acc[r]) : 0.0f;
     if (nseg > 1) {
       // head segment: complete once the previous lane's tail (if same feature) is added
       const bool join = lane > 0 && kprev1 == hkey;
 #pragma unroll
-      for (int r = 0; r < RT; ++r) sF[hkey * RT + r] += head[r] + (join ? carry[r] : 0.0f);
+      for (int r = 0; r < RTP; ++r) head[r] += join ? carry[r] : 0.0f;
+      add_row(hkey, head);
     }
     if (cur >= 0) {
       // tail: flushed unless the next lane's run starts with the same feature
       const bool cont = lane < 63 && knext == cur;
-      if (!cont) {
-#pragma unroll
-        for (int r = 0; r < RT; ++r) sF[cur * RT + r] += acc[r];
-      }
+      if (!cont) add_row(cur, acc);
     }
   }
   __syncthreads();
-  for (int64_t e = t; e < J * RT; e += nt) {
-    const int64_t j = e / RT;
-    const int r = (int)(e - j * RT);
+  for (int64_t e = t; e < J * RTP; e += nt) {
+    const int64_t j = e / RTP;
+    const int r = (int)(e - j * RTP);
     const float v = sF[e];
-    if (c0 + r < R && v != 0.0f) unsafeAtomicAdd(&FV[j * R + c0 + r], v);
+    if (r < RT && c0 + r < R && v != 0.0f) unsafeAtomicAdd(&FV[j * R + c0 + r], v);
   }
 }
 
@@ -424,7 +446,7 @@ __global__ void __launch_bounds__(512)
 template <int RT, bool SMOOTH>
 inline void launch_pass2c(const copa_plan *p, const float *Mrows, float *F, hipStream_t s) {
   const dim3 grid((unsigned)std::min(p->nchunks, 2 * std::max(1, p->n_cu)), (unsigned)p->tiles.nt);
-  const size_t lds = ((size_t)p->J * RT + (size_t)kChunkRows * RT + 1) * sizeof(float);
+  const size_t lds = ((size_t)p->J * row4(RT) + (size_t)kChunkRows * row4(RT) + 4) * sizeof(float);
   k_pass2c<RT, SMOOTH><<<grid, 512, lds, s>>>(p->nchunks, p->crow, p->cinfo, p->wsplit, p->pkv,
                                              p->rowsubj, p->C, Mrows, p->J, p->R,
                                              SMOOTH ? p->l : 0, F);

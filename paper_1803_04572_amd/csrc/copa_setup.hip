@@ -428,7 +428,7 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   COPA_HIP(hipGetDevice(&p->device));
   int lds = 0;
   COPA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
-  p->lds_limit = std::min(lds, 65536);
+  p->lds_limit = lds;  // 160 KB per workgroup on gfx950
 
   const int64_t K = p->K, S = p->S, nnz = p->nnz;
   // ---- content checks on the device
@@ -574,7 +574,7 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   // ---- iteration buffers
   const int R = p->R;
   p->tiles = choose_tiles(R, p->J, p->lds_limit);
-  if ((int64_t)p->J * ((p->tiles.rt + 3) & ~3) * 4 + 16 > p->lds_limit) {
+  if ((int64_t)p->J * (row4(p->tiles.rt)) * 4 + 16 > p->lds_limit) {
     set_error("J too large for the LDS-staged factor tile of this build");
     return COPA_EUNSUPPORTED;
   }
@@ -584,7 +584,7 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   COPA_TRY(dalloc(&p->FW, K * R));
   COPA_TRY(dalloc(&p->FV, p->J * R));
   {
-    const int rtp = (p->tiles.rt + 3) & ~3;
+    const int rtp = row4(p->tiles.rt);
     COPA_TRY(dalloc(&p->Vp, (size_t)p->tiles.nt * p->J * rtp));
     COPA_HIP(hipMemsetAsync(p->Vp, 0, (size_t)p->tiles.nt * p->J * rtp * sizeof(float), s));
   }
@@ -602,7 +602,8 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   // ---- feature-sorted chunks for pass 2 (features < 2^16 and the F_V tile plus one chunk of
   // u rows fit in LDS)
   p->p2c = p->J <= 65536 && nnz > 0 &&
-           ((int64_t)p->J * p->tiles.rt + (int64_t)kChunkRows * p->tiles.rt + 1) * 4 <= p->lds_limit;
+           ((int64_t)p->J * row4(p->tiles.rt) + (int64_t)kChunkRows * row4(p->tiles.rt) + 4) * 4 <=
+               p->lds_limit;
   if (p->p2c) COPA_TRY(build_sorted_chunks(X, p, s));
   COPA_TRY(dalloc(&p->vpart, (size_t)p->n_vblocks * 4));
   {
