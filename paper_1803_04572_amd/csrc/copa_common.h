@@ -116,9 +116,11 @@ struct copa_plan {
   uint2 *pkv = nullptr;      // [nnz] (feature << 16 | row within chunk, value bits)
   int n_cu = 0;
   // Gram slots (gstride doubles each): F_H, W^TW, Psi, V^TV partials of the V update, and two
-  // more for the adjoint; a slot holds gmaxnb block partials and their total.
+  // more for the adjoint; a slot holds gcap block partials and then their total. Row-Gram
+  // launches use at most gmaxnb blocks, the V update n_vblocks.
   double *gpart = nullptr;
   int gmaxnb = 0;
+  int gcap = 0;  // partials a slot holds (largest block count of any launch writing them)
   int64_t gstride = 0;
   int32_t *gcount = nullptr;  // [8] last-block counters of the row Grams
   double *vpart = nullptr;  // [blocks x 4] V-ADMM scalar partials
@@ -153,7 +155,7 @@ enum { kSlotFH = 0, kSlotWtW = 1, kSlotPsi = 2, kSlotVtV = 3, kSlotG = 4, kSlotG
 inline double *gram_slot(const copa_plan *p, int slot) { return p->gpart + (int64_t)slot * p->gstride; }
 // The reduced R x R total of a slot after a k_rows_gram launch.
 inline double *gram_total(const copa_plan *p, int slot) {
-  return gram_slot(p, slot) + gram_total_offset(p->gmaxnb) * p->R * p->R;
+  return gram_slot(p, slot) + gram_total_offset(p->gcap) * p->R * p->R;
 }
 }  // namespace copa
 

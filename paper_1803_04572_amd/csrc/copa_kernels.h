@@ -185,10 +185,19 @@ __global__ void __launch_bounds__(256)
   }
   const int t = threadIdx.x, lane = t & 63;
   const int e = blockIdx.x * 4 + (t >> 6);
-  double s = 0.0;
-  if (e < RR)
-    for (int b = lane; b < nb; b += 64) s += part[(int64_t)b * RR + e];
-  red[t] = s;
+  const int ec = e < RR ? e : RR - 1;
+  // eight partials in flight per thread (clamped addresses, masked values), summed in a fixed order
+  double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b0 = lane; b0 < nb; b0 += 8 * 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + u * 64;
+      const double x = part[(int64_t)(b < nb ? b : 0) * RR + ec];
+      s8[u] += b < nb ? x : 0.0;
+    }
+  }
+  const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+  red[t] = e < RR ? s : 0.0;
   __syncthreads();
   for (int w = 32; w > 0; w >>= 1) {
     if (lane < w) red[t] += red[t + w];

@@ -595,7 +595,8 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
     const int64_t rb = 4 * (kWave / R);
     p->n_vblocks = (int)std::max<int64_t>(1, std::min<int64_t>((p->J + rb - 1) / rb, 4 * std::max(1, p->n_cu)));
   }
-  p->gstride = (std::max<int64_t>(p->gmaxnb, p->n_vblocks) + 1) * R * R;
+  p->gcap = std::max(p->gmaxnb, p->n_vblocks);
+  p->gstride = ((int64_t)p->gcap + 1) * R * R;
   COPA_TRY(dalloc(&p->gpart, (size_t)kGramSlots * p->gstride));
   COPA_TRY(dalloc(&p->gcount, 8));
   COPA_HIP(hipMemsetAsync(p->gcount, 0, 8 * sizeof(int32_t), s));
