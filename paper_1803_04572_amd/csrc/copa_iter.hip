@@ -154,15 +154,18 @@ __global__ void __launch_bounds__(256)
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const float x = xv[u];
-            const float4 *v4 = reinterpret_cast<const float4 *>(sV + cj[u] * RTP);
+            // a slot that no lane of the wavefront uses is skipped (no LDS gathers)
+            if (u == 0 || eb + u < e1) {
+              const float x = xv[u];
+              const float4 *v4 = reinterpret_cast<const float4 *>(sV + cj[u] * RTP);
 #pragma unroll
-            for (int q = 0; q < RTP / 4; ++q) {
-              const float4 v = v4[q];
-              if (4 * q + 0 < RT) t[4 * q + 0] += x * v.x;
-              if (4 * q + 1 < RT) t[4 * q + 1] += x * v.y;
-              if (4 * q + 2 < RT) t[4 * q + 2] += x * v.z;
-              if (4 * q + 3 < RT) t[4 * q + 3] += x * v.w;
+              for (int q = 0; q < RTP / 4; ++q) {
+                const float4 v = v4[q];
+                if (4 * q + 0 < RT) t[4 * q + 0] += x * v.x;
+                if (4 * q + 1 < RT) t[4 * q + 1] += x * v.y;
+                if (4 * q + 2 < RT) t[4 * q + 2] += x * v.z;
+                if (4 * q + 3 < RT) t[4 * q + 3] += x * v.w;
+              }
             }
           }
         }
