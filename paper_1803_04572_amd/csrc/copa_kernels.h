@@ -311,8 +311,11 @@ __global__ void __launch_bounds__(512)
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
+          // M rows staged RTP apart (16-byte reads below); the spare slot past the u rows takes
+          // the out-of-range lanes
           const int e = e0 + u * nt + t;
-          sU[e < nm ? e : kChunkRows * RT] = mv[u];  // spare slot past the u rows
+          const int q = e / RT;
+          sU[e < nm ? q * RTP + (e - q * RT) : kChunkRows * RTP] = mv[u];
         }
       }
     } else {
@@ -322,15 +325,25 @@ __global__ void __launch_bounds__(512)
     fetch(c + gridDim.x);
     if constexpr (SMOOTH) {
       __syncthreads();
-      // basis columns at or past l are zero: clamp the M row instead of branching
+      // basis columns at or past l are zero: those M rows are skipped (l is uniform)
 #pragma unroll
-      for (int r = 0; r < RT; ++r) u[r] = 0.0f;
+      for (int r = 0; r < RTP; ++r) u[r] = 0.0f;
 #pragma unroll
       for (int q = 0; q < kLMax; ++q) {
-        const float *mr = sU + (kl * l + (q < l ? q : l - 1)) * RT;
+        if (q < l) {
+          const float4 *m4 = reinterpret_cast<const float4 *>(sU + (kl * l + q) * RTP);
 #pragma unroll
-        for (int r = 0; r < RT; ++r) u[r] += cr[q] * mr[r];
+          for (int qq = 0; qq < RTP / 4; ++qq) {
+            const float4 mv = m4[qq];
+            u[4 * qq] += cr[q] * mv.x;
+            u[4 * qq + 1] += cr[q] * mv.y;
+            u[4 * qq + 2] += cr[q] * mv.z;
+            u[4 * qq + 3] += cr[q] * mv.w;
+          }
+        }
       }
+#pragma unroll
+      for (int r = RT; r < RTP; ++r) u[r] = 0.0f;  // the staged rows' pad columns are not set
       __syncthreads();
     }
     if (t < n) {
