@@ -1077,7 +1077,21 @@ __device__ __forceinline__ void fit_finalize(const FitArgs &fa, int it, const fl
     l1 += fa.vpart[b * 4 + 1];
     zeros += fa.vpart[b * 4 + 2];
   }
-  for (int b = t; b < fa.nwb; b += blockDim.x) wl1 += fa.wl1part[b];
+  // the W-update partials (one per block of that launch, thousands at large K): eight loads in
+  // flight per thread, from clamped addresses
+  {
+    double w8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int nt = blockDim.x;
+    for (int b0 = t; b0 < fa.nwb; b0 += 8 * nt) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int b = b0 + u * nt;
+        const double x = fa.wl1part[b < fa.nwb ? b : 0];
+        w8[u] += b < fa.nwb ? x : 0.0;
+      }
+    }
+    wl1 = ((w8[0] + w8[1]) + (w8[2] + w8[3])) + ((w8[4] + w8[5]) + (w8[6] + w8[7]));
+  }
   for (int e = t; e < RR; e += blockDim.x) {
     hl1 += fabs((double)H[e]);
     quad += small[kPsi * RR + e] * sVtV[e];
