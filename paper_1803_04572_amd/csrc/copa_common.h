@@ -213,6 +213,51 @@ __device__ __forceinline__ float dpp_f(float old, float v) {
 // with 16-byte LDS accesses (three instead of five for RT = 10).
 __host__ __device__ constexpr int row4(int rt) { return (rt + 3) & ~3; }
 
+// v[0, RT) from a 16-byte aligned LDS row, reading no pad: 16-byte reads for whole groups of
+// four, then 8 and 4 bytes for the rest (RT = 10: 40 bytes in three reads instead of 48)
+template <int RT>
+__device__ __forceinline__ void lds_row(const float *row, float (&v)[RT]) {
+  constexpr int B = RT / 4 * 4;
+  const float4 *r4 = reinterpret_cast<const float4 *>(row);
+#pragma unroll
+  for (int q = 0; q < RT / 4; ++q) {
+    const float4 a = r4[q];
+    v[4 * q] = a.x;
+    v[4 * q + 1] = a.y;
+    v[4 * q + 2] = a.z;
+    v[4 * q + 3] = a.w;
+  }
+  if constexpr (RT - B >= 2) {
+    const float2 a = *reinterpret_cast<const float2 *>(row + B);
+    v[B] = a.x;
+    v[B + 1] = a.y;
+  }
+  if constexpr ((RT - B) & 1) v[RT - 1] = row[RT - 1];
+}
+
+// row[0, RT) += v[0, RT) on a 16-byte aligned LDS row with the same access widths as lds_row
+template <int RT>
+__device__ __forceinline__ void lds_row_add(float *row, const float *v) {
+  constexpr int B = RT / 4 * 4;
+  float4 *r4 = reinterpret_cast<float4 *>(row);
+#pragma unroll
+  for (int q = 0; q < RT / 4; ++q) {
+    float4 a = r4[q];
+    a.x += v[4 * q];
+    a.y += v[4 * q + 1];
+    a.z += v[4 * q + 2];
+    a.w += v[4 * q + 3];
+    r4[q] = a;
+  }
+  if constexpr (RT - B >= 2) {
+    float2 a = *reinterpret_cast<float2 *>(row + B);
+    a.x += v[B];
+    a.y += v[B + 1];
+    *reinterpret_cast<float2 *>(row + B) = a;
+  }
+  if constexpr ((RT - B) & 1) row[RT - 1] += v[RT - 1];
+}
+
 // Recursive-halving reduce-scatter over groups of G = 2^g <= 64 lanes (G wave-uniform, sub =
 // lane index within the group). v[0, E) holds each lane's partial values of E elements (E a
 // multiple of G); on return v[m], m < E / G, holds the group total of element m G + sub. Step b

@@ -157,15 +157,10 @@ __global__ void __launch_bounds__(256)
             // a slot that no lane of the wavefront uses is skipped (no LDS gathers)
             if (u == 0 || eb + u < e1) {
               const float x = xv[u];
-              const float4 *v4 = reinterpret_cast<const float4 *>(sV + cj[u] * RTP);
+              float v[RT];
+              lds_row<RT>(sV + cj[u] * RTP, v);
 #pragma unroll
-              for (int q = 0; q < RTP / 4; ++q) {
-                const float4 v = v4[q];
-                if (4 * q + 0 < RT) t[4 * q + 0] += x * v.x;
-                if (4 * q + 1 < RT) t[4 * q + 1] += x * v.y;
-                if (4 * q + 2 < RT) t[4 * q + 2] += x * v.z;
-                if (4 * q + 3 < RT) t[4 * q + 3] += x * v.w;
-              }
+              for (int r = 0; r < RT; ++r) t[r] += x * v[r];
             }
           }
         }

@@ -331,15 +331,10 @@ __global__ void __launch_bounds__(512)
 #pragma unroll
       for (int q = 0; q < kLMax; ++q) {
         if (q < l) {
-          const float4 *m4 = reinterpret_cast<const float4 *>(sU + (kl * l + q) * RTP);
+          float mv[RT];
+          lds_row<RT>(sU + (kl * l + q) * RTP, mv);
 #pragma unroll
-          for (int qq = 0; qq < RTP / 4; ++qq) {
-            const float4 mv = m4[qq];
-            u[4 * qq] += cr[q] * mv.x;
-            u[4 * qq + 1] += cr[q] * mv.y;
-            u[4 * qq + 2] += cr[q] * mv.z;
-            u[4 * qq + 3] += cr[q] * mv.w;
-          }
+          for (int r = 0; r < RT; ++r) u[r] += cr[q] * mv[r];
         }
       }
 #pragma unroll
@@ -353,19 +348,8 @@ __global__ void __launch_bounds__(512)
         d4[q] = make_float4(u[4 * q], u[4 * q + 1], u[4 * q + 2], u[4 * q + 3]);
     }
     __syncthreads();
-    // sF[j] += v over a padded row (pad entries of v are zero)
-    auto add_row = [&](int j, const float *v) {
-      float4 *f4 = reinterpret_cast<float4 *>(sF + j * RTP);
-#pragma unroll
-      for (int q = 0; q < RTP / 4; ++q) {
-        float4 f = f4[q];
-        f.x += v[4 * q];
-        f.y += v[4 * q + 1];
-        f.z += v[4 * q + 2];
-        f.w += v[4 * q + 3];
-        f4[q] = f;
-      }
-    };
+    // sF[j] += v over the RT live entries of a padded row
+    auto add_row = [&](int j, const float *v) { lds_row_add<RT>(sF + j * RTP, v); };
     float acc[RTP], head[RTP];
 #pragma unroll
     for (int r = 0; r < RTP; ++r) {
@@ -388,7 +372,7 @@ __global__ void __launch_bounds__(512)
         const uint32_t key = kv[q];
         const int j = (int)(key >> 16);
         const float x = xv[q];
-        const float4 *ur = reinterpret_cast<const float4 *>(sU + (key & 0xffffu) * RTP);
+        const float *ur = sU + (key & 0xffffu) * RTP;
         if (j != cur) {
           if (nseg == 1) {
             hkey = cur;
@@ -403,14 +387,10 @@ __global__ void __launch_bounds__(512)
 #pragma unroll
           for (int r = 0; r < RTP; ++r) acc[r] = 0.0f;
         }
+        float uv[RT];
+        lds_row<RT>(ur, uv);
 #pragma unroll
-        for (int qq = 0; qq < RTP / 4; ++qq) {
-          const float4 uv = ur[qq];
-          acc[4 * qq] += x * uv.x;
-          acc[4 * qq + 1] += x * uv.y;
-          acc[4 * qq + 2] += x * uv.z;
-          acc[4 * qq + 3] += x * uv.w;
-        }
+        for (int r = 0; r < RT; ++r) acc[r] += x * uv[r];
       }
     }
     // tail segment (cur, acc); the first key of this lane's run is hkey (several segments) or cur
