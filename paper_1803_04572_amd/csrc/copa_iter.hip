@@ -225,15 +225,12 @@ __global__ void __launch_bounds__(256)
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const float x = xv[u];
-            const float4 *v4 = reinterpret_cast<const float4 *>(sV + (int64_t)cj[u] * RTP);
+            if (u == 0 || eb + u < e1) {  // slots no lane uses skip their gathers
+              const float x = xv[u];
+              float v[RT];
+              lds_row<RT>(sV + (int64_t)cj[u] * RTP, v);
 #pragma unroll
-            for (int q = 0; q < RTP / 4; ++q) {
-              const float4 v = v4[q];
-              t[4 * q + 0] += x * v.x;
-              t[4 * q + 1] += x * v.y;
-              t[4 * q + 2] += x * v.z;
-              t[4 * q + 3] += x * v.w;
+              for (int r = 0; r < RT; ++r) t[r] += x * v[r];
             }
           }
         }
