@@ -89,6 +89,30 @@ def test_fit_parity(cfg_name, K, R, l, iters):
     assert min(cong.values()) >= CONGRUENCE_MIN
 
 
+@pytest.mark.parametrize("J,chunked", [(8000, True), (9800, False)])
+@pytest.mark.parametrize("l", [7, 0])
+def test_wide_feature_space_parity(J, chunked, l):
+    """Thousands of features at R = 10: the V tile no longer fits one workgroup's LDS, so both
+    passes run three column tiles of 4, 4 and 2 columns; at J = 9800 the pass-2 F_V tile plus one
+    chunk of u rows does not fit either and pass 2 takes its unchunked form. All fit the oracle."""
+    from paper_1803_04572_amd import copa
+    K, R, iters = 150, 10, 5
+    ik = np.random.default_rng(11).integers(3, 40, size=K)
+    coh = synth.ehr_cohort(K, J, ik, 7, 1.1, 11)
+    plan = copa.Plan.from_cohort(coh, R=R, l=l)
+    assert (plan.query("chunks") > 0) == chunked
+    g = run_gpu(coh, R, l, iters)
+    o, prob = run_oracle(coh, R, l, iters)
+    fit_rel = abs(g["rep"]["fit"] - o.fit[-1]) / abs(o.fit[-1])
+    cong = dict(H=congruence(g["H"], o.H), V=congruence(g["V"], o.V), W=congruence(g["W"], o.W),
+                U=congruence(stacked_U(split_rows(coh, g["Qt"]), g["H"]),
+                             stacked_U(o.Qtilde, o.H)))
+    _report(f"wide J={J} l={l}", fit_gpu=g["rep"]["fit"], fit_oracle=o.fit[-1], fit_rel=fit_rel,
+            **{f"cong_{k}": v for k, v in cong.items()})
+    assert fit_rel <= FIT_RTOL
+    assert min(cong.values()) >= CONGRUENCE_MIN
+
+
 @pytest.mark.parametrize("scale,compact", [(1.0, 1), (1.1, 0)])
 def test_value_storage_forms(scale, compact):
     """Integer counts are stored in the lossless 4-byte form (feature id + bfloat16 value); other
