@@ -130,9 +130,15 @@ def main():
         sys.exit(2)
     copa.lib()  # fails loudly when libcopa.so is missing
 
+    def progress(msg):
+        print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+    progress(f"generating {args.workload}")
     coh, cfg = synth.make_config(args.workload)
     R, l = cfg["R"], cfg["l"]
+    progress(f"K={coh.K} S={coh.S} nnz={coh.nnz}; creating the plan")
     plan = copa.Plan.from_cohort(coh, R=R, l=l, inner_iters=cfg["inner"])
+    progress("plan ready")
     H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
     state = plan.new_state(H0, W0, V0)
     torch.cuda.synchronize()

@@ -66,17 +66,37 @@ def bspline_value(i, d, t, beta):
     return a + b
 
 
+def spline_table(t, beta, d):
+    """All basis functions of degree d on knots beta at the points t (n x (len(beta)-1-d)): the
+    same recursion as bspline_value, run level by level over arrays instead of one point and one
+    function at a time."""
+    t = np.asarray(t, dtype=np.float64)[:, None]
+    lo, hi = beta[:-1][None, :], beta[1:][None, :]
+    m = ((lo <= t) & (t < hi)).astype(np.float64)          # degree 0, half-open pieces
+    last = np.flatnonzero(beta[1:] > beta[:-1])
+    if last.size:                                          # the last nonempty piece is closed
+        j = last[-1]
+        m[:, j] = np.where(t[:, 0] == beta[j + 1], 1.0, m[:, j])
+    for dd in range(1, d + 1):
+        n = len(beta) - 1 - dd
+        i = np.arange(n)
+        den_a = beta[i + dd] - beta[i]
+        den_b = beta[i + dd + 1] - beta[i + 1]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            a = np.where(den_a > 0, (t - beta[i][None, :]) / np.where(den_a > 0, den_a, 1.0), 0.0)
+            b = np.where(den_b > 0, (beta[i + dd + 1][None, :] - t) / np.where(den_b > 0, den_b, 1.0),
+                         0.0)
+        m = a * m[:, :n] + b * m[:, 1:n + 1]
+    return m
+
+
 def spline_basis(days, l):
     """M_k (I_k x l): the l basis functions evaluated at the subject's visit days."""
     days = np.asarray(days, dtype=np.float64)
     t1, tn = float(days.min()), float(days.max())
     d = min(3, l - 1)
     beta = spline_knots(t1, tn, l, d)
-    M = np.zeros((days.size, l))
-    for r, t in enumerate(days):
-        for i in range(l):
-            M[r, i] = bspline_value(i, d, float(t), beta)
-    return M
+    return spline_table(days, beta, d)
 
 
 def smoothing_basis(days, l, tol=1e-10):

@@ -43,6 +43,20 @@ def test_bspline_partition_of_unity_and_scipy(l):
     np.testing.assert_allclose(M, ref, atol=1e-13)
 
 
+@pytest.mark.parametrize("l", [2, 3, 4, 7, 8])
+def test_spline_table_equals_pointwise_recursion(l):
+    """The array form of the recursion gives the pointwise recursion's values bit for bit, also at
+    knots and at both ends of the interval."""
+    rng = np.random.default_rng(100 + l)
+    d = min(3, l - 1)
+    beta = co.spline_knots(0.0, 700.0, l, d)
+    t = np.concatenate([beta, rng.uniform(0.0, 700.0, 50)])
+    M = co.spline_table(t, beta, d)
+    ref = np.array([[co.bspline_value(i, d, float(x), beta) for i in range(l)] for x in t])
+    assert M.shape == ref.shape
+    assert np.array_equal(M, ref)
+
+
 def test_smoothing_basis_degenerate_and_rank():
     C = co.smoothing_basis(np.array([5.0, 5.0, 5.0]), 7)
     np.testing.assert_allclose(C, np.ones((3, 1)) / np.sqrt(3))
@@ -533,3 +547,27 @@ def test_subject_and_feature_permutation_equivariance():
     res = co.copa_fit(co.build_problem(cf, l), H0, W0, V0[fp], opt)
     np.testing.assert_allclose(res.V, base.V[fp], atol=1e-9)
     np.testing.assert_allclose(res.H, base.H, atol=1e-9)
+
+
+# ------------------------------------------------------------------ sharded oracle (full sizes)
+
+
+@pytest.mark.parametrize("cfg_name,K,R,l", [("c2", 120, 10, 7), ("c5", 90, 5, 0)])
+def test_sharded_oracle_equals_one_process(cfg_name, K, R, l):
+    """The sharded driver that writes the full-size reference trajectories runs the same steps as
+    copa_fit: same FIT, objective, sparsity and factors up to summation order."""
+    from oracle import fullsize
+    coh, cfg = synth.make_config(cfg_name, K=K)
+    H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
+    opt = co.Options(R=R, outer_iters=3)
+    ref = co.copa_fit(co.build_problem(coh, l), H0, W0, V0, opt)
+    got = fullsize.copa_fit_sharded(coh, l, H0, W0, V0, opt, workers=3, want_Q=True)
+    np.testing.assert_allclose(got["fit"], ref.fit, rtol=1e-12)
+    np.testing.assert_allclose(got["objective"], ref.objective, rtol=1e-12)
+    assert got["sparsity"] == ref.sparsity
+    for a, b in ((got["H"], ref.H), (got["V"], ref.V), (got["W"], ref.W), (got["D_W"], ref.D_W)):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-10 * max(1.0, np.abs(b).max()))
+    for qa, qb in zip(got["Q"], ref.Q):
+        np.testing.assert_allclose(qa, qb, atol=1e-9)
+    assert got["rank_deficient"][-1] == sum(
+        int(r < min(x.shape[0], R)) for r, x in zip(ref.ranks, co.build_problem(coh, l).Xh))
