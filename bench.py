@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "outer AO-ADMM iters/sec + MTTKRP HBM GB/s at fixed fit vs FP64 oracle"
-SOURCES = ["copa_common.h", "copa_kernels.h", "copa_setup.hip", "copa_iter.hip", "copa_grad.hip"]
+CSRC = os.path.join(ROOT, "paper_1803_04572_amd", "csrc")
 # rocprofv3 kernel-name stem of each timed kernel
 ROCPROF_NAME = {"pass1": "k_pass1", "procrustes": "k_procrustes", "gram_FH": "k_rows_gram_fit",
                 "mode_H": "k_mode_H", "w_admm": "k_w_admm", "gram_WM": "k_rows_gram",
@@ -36,8 +36,8 @@ ROCPROF_NAME = {"pass1": "k_pass1", "procrustes": "k_procrustes", "gram_FH": "k_
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in SOURCES:
-        with open(os.path.join(ROOT, "paper_1803_04572_amd", "csrc", f), "rb") as fh:
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

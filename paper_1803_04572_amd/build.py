@@ -14,7 +14,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcopa.so")
-SOURCES = ["copa_setup.hip", "copa_iter.hip", "copa_grad.hip"]
+SOURCES = ["copa_iter_rd.hip", "copa_iter_rf.hip", "copa_iter_re.hip", "copa_iter_rc.hip",
+           "copa_iter_rb.hip", "copa_iter_ra.hip", "copa_setup.hip", "copa_iter.hip",
+           "copa_grad.hip"]
 ARCH = os.environ.get("COPA_OFFLOAD_ARCH", "gfx950")
 # packed FP32 instructions are kept out of every kernel (-packed-fp32-ops)
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",

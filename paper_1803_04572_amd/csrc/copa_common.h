@@ -66,6 +66,7 @@ struct FitScalars {
 struct Tiles {
   int nt;  // number of column tiles of R
   int rt;  // tile width
+  int cg;  // pass 1: tiles one block stages together, one lane group of 64 / cg lanes per tile
 };
 
 }  // namespace copa
@@ -78,7 +79,8 @@ struct copa_plan {
   int slot_rows;   // smoothed: l rows per subject; unsmoothed: rows follow the visit rows
   int64_t rows_total;  // rows of the T/Q/M row spaces
   copa_options opt;
-  copa::Tiles tiles;
+  copa::Tiles tiles;   // pass 1 (and the V update's padded image of V)
+  copa::Tiles tiles2;  // pass 2 over the feature-sorted chunks: F_V and u-row column tiles
   int lds_limit;
 
   // packed tensor
@@ -95,6 +97,8 @@ struct copa_plan {
   int32_t *order = nullptr;  // [K] subjects by decreasing visit count
   copa::WaveEntry *waves = nullptr;
   int32_t n_waves = 0;
+  copa::WaveEntry *waves1 = nullptr;  // pass-1 wave list for lane groups of 64 / tiles.cg lanes
+  int32_t n_waves1 = 0;
   int32_t n_big = 0;         // unsmoothed subjects whose eigenproblem exceeds kNMax
   int32_t *big_list = nullptr;
   double normX2 = 0.0;
@@ -171,6 +175,8 @@ copa_status harvest_timing(copa_plan *p);
 extern const char *const kernel_names[kNumKernels];
 bool rank_supported(int R);
 Tiles choose_tiles(int R, int64_t J, int lds_limit);
+Tiles choose_tiles2(int R, int64_t J, int lds_limit);
+bool pass2_width_supported(int rt);
 
 // ---------------------------------------------------------------- (copa_grad.hip)
 copa_status launch_stationarity(copa_plan *p, const float *H, const float *V, const float *W,

@@ -229,25 +229,36 @@ __global__ void k_zero_f(float *x, int64_t n) {
 
 // F += X^T U with U given per visit row (the plain-rows mode of the streaming scatter).
 template <int RT>
-static void scatter_rt(copa_plan *p, const float *U, float *F, hipStream_t s) {
-  if (p->p2c) {
-    launch_pass2c<RT, false>(p, U, F, s);
-  } else {
-    dim3 grid((unsigned)((p->n_waves + 3) / 4), (unsigned)p->tiles.nt), block(256);
-    k_pass2<RT, false><<<grid, block, 0, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
-                                              p->col, p->val, p->C, U, p->J, p->R, 0, F);
-  }
+static void scatter_c_rt(copa_plan *p, const float *U, float *F, hipStream_t s) {
+  launch_pass2c<RT, false>(p, U, F, s);
+}
+template <int RT>
+static void scatter_u_rt(copa_plan *p, const float *U, float *F, hipStream_t s) {
+  dim3 grid((unsigned)((p->n_waves + 3) / 4), (unsigned)p->tiles.nt), block(256);
+  k_pass2<RT, false><<<grid, block, 0, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
+                                            p->col, p->val, p->C, U, p->J, p->R, 0, F);
 }
 
 template <int R>
 static void launch_scatter_rows(copa_plan *p, const float *U, float *F, hipStream_t s) {
-  switch (p->tiles.rt) {
+  if (p->p2c) {
+    switch (p->tiles2.rt) {
 #define CASE(rt) \
-  case rt: scatter_rt<rt>(p, U, F, s); break;
-    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11)
-    CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
+  case rt: if constexpr (rt <= R) scatter_c_rt<rt>(p, U, F, s); break;
+      CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11)
+      CASE(12) CASE(13) CASE(14) CASE(15) CASE(16) CASE(20) CASE(24) CASE(32) CASE(40)
 #undef CASE
-    default: break;
+      default: break;
+    }
+  } else {
+    switch (p->tiles.rt) {
+#define CASE(rt) \
+  case rt: scatter_u_rt<rt>(p, U, F, s); break;
+      CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11)
+      CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
+#undef CASE
+      default: break;
+    }
   }
 }
 

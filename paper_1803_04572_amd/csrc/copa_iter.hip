@@ -17,16 +17,9 @@
 //   mode_V_prep G_V = H^TH * W^TW, rho, FP64 Cholesky
 //   v_admm      inner ADMM on V rows, FIT/penalty/sparsity partials
 //   gram(V), finalize  V^T V, FIT = 1 - (|X|^2 - 2<F_V,V> + <Psi, V^T V>) / |X|^2
-#include <climits>
-#include <type_traits>
-
-#include "copa_common.h"
-#include "copa_kernels.h"
+#include "copa_iter_impl.h"
 
 namespace copa {
-
-#define COPA_R_LIST(X) \
-  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(15) X(16) X(20) X(24) X(32) X(40)
 
 bool rank_supported(int R) {
   switch (R) {
@@ -38,1514 +31,45 @@ bool rank_supported(int R) {
   }
 }
 
+// Pass 1: column tiles of at most 16 (the width of the per-lane accumulators). A block stages cg
+// tiles together and gives each a lane group of 64 / cg lanes, so X is streamed nt / cg times;
+// the tiling with the fewest streams wins (then the fewest tiles).
 Tiles choose_tiles(int R, int64_t J, int lds_limit) {
-  int nt = (R + 15) / 16;
-  for (;; ++nt) {
-    int rt = (R + nt - 1) / nt;
-    int rtp = row4(rt);
-    if ((int64_t)J * rtp * 4 + 16 <= lds_limit || rt == 1) return Tiles{nt, rt};
-  }
-}
-
-// small-buffer layout (FP64 R x R each)
-enum { kFH = 0, kHtH = 1, kWtW = 2, kVtV = 3, kPsi = 4 };
-
-// ======================================================================= streaming pass 1
-// Persistent blocks of 4 waves; each block stages one column tile of V (kept padded to RTP
-// columns per row by the V update) in LDS once, then its waves walk the wave list: each wave takes
-// `cnt` subjects and G lanes per subject stride over the subject's visit rows.
-template <int RT, bool SMOOTH, bool COMPACT>
-__global__ void __launch_bounds__(256)
-    k_pass1(const WaveEntry *__restrict__ waves, int n_waves, const int32_t *__restrict__ order,
-            const int32_t *__restrict__ subj, const int32_t *__restrict__ row,
-            const int32_t *__restrict__ col, const float *__restrict__ val,
-            const uint32_t *__restrict__ xc,
-            const float *__restrict__ C, const float *__restrict__ Vp, int64_t J, int R, int l,
-            float *__restrict__ T, float *__restrict__ FV, FitScalars *sc) {
-  constexpr int RTP = row4(RT);
-  extern __shared__ float4 smem4[];
-  // pass 1 opens an outer iteration: advance the device iteration index (no other launch of the
-  // iteration reads it before pass 1 ends)
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) sc->cur += 1;
-  // F_V is accumulated by pass 2 of this iteration: clear it here
-  if (blockIdx.y == 0)
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < J * R;
-         e += (int64_t)gridDim.x * blockDim.x)
-      FV[e] = 0.0f;
-  {
-    // stage the tile with 8 loads in flight per thread
-    const float4 *src = reinterpret_cast<const float4 *>(Vp + (int64_t)blockIdx.y * J * RTP);
-    const int64_t n4 = J * RTP / 4;
-    for (int64_t e0 = 0; e0 < n4; e0 += 8 * (int64_t)blockDim.x) {
-      float4 tmp[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int64_t e = e0 + u * blockDim.x + threadIdx.x;
-        tmp[u] = src[e < n4 ? e : 0];
+  Tiles best{0, 0, 0};
+  int best_streams = INT_MAX;
+  for (int nt = (R + 15) / 16; nt <= R && best_streams > 1; ++nt) {
+    const int rt = (R + nt - 1) / nt;
+    if ((nt - 1) * rt >= R) continue;  // the last tile would be empty
+    const int64_t tile = J * row4(rt) * 4;
+    for (int cg : {4, 2, 1}) {
+      if (nt % cg != 0 || cg * tile + 16 > lds_limit) continue;
+      if (nt / cg < best_streams) {
+        best = Tiles{nt, rt, cg};
+        best_streams = nt / cg;
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        // out-of-range lanes write the spare slot after the tile (no branch, so that the 8 loads
-        // above stay in flight together)
-        const int64_t e = e0 + u * blockDim.x + threadIdx.x;
-        smem4[e < n4 ? e : n4] = tmp[u];
-      }
+      break;
     }
   }
-  __syncthreads();
-  const float *sV = reinterpret_cast<const float *>(smem4);
-  const int c0 = blockIdx.y * RT;
-  const int lane = threadIdx.x & 63;
-  for (int wv = blockIdx.x * 4 + (threadIdx.x >> 6); wv < n_waves; wv += gridDim.x * 4) {
-    const WaveEntry we = waves[wv];
-    const int lg = we.lg_count & 255, cnt = we.lg_count >> 8;
-    const int G = 1 << lg, sidx = lane >> lg, sub = lane & (G - 1);
-    const bool active = sidx < cnt;
-    const int k = active ? order[we.first + sidx] : 0;
-    const int r0 = active ? subj[k] : 0, r1 = active ? subj[k + 1] : 0;
-    if constexpr (SMOOTH) {
-      float acc[kLMax][RT];
-#pragma unroll
-      for (int a = 0; a < kLMax; ++a)
-#pragma unroll
-        for (int r = 0; r < RT; ++r) acc[a][r] = 0.0f;
-      // two-stage pipeline over this lane's rows: the next row's bounds and basis row are
-      // requested while the current row's nonzeros are loaded and used
-      int i = r0 + sub;
-      int e0n = 0, e1n = 0;
-      float4 can = make_float4(0.f, 0.f, 0.f, 0.f), cbn = can;
-      if (i < r1) {
-        e0n = row[i];
-        e1n = row[i + 1];
-        const float4 *c4 = reinterpret_cast<const float4 *>(C + (int64_t)i * kLMax);
-        can = c4[0];
-        cbn = c4[1];
-      }
-      for (; i < r1; i += G) {
-        const int e0 = e0n, e1 = e1n;
-        const float4 ca = can, cb = cbn;
-        {
-          const int in = i + G < r1 ? i + G : r1 - 1;  // always a valid row of this subject
-          e0n = row[in];
-          e1n = row[in + 1];
-          const float4 *c4 = reinterpret_cast<const float4 *>(C + (int64_t)in * kLMax);
-          can = c4[0];
-          cbn = c4[1];
-        }
-        float t[RT];
-#pragma unroll
-        for (int r = 0; r < RT; ++r) t[r] = 0.0f;
-        for (int eb = e0; eb < e1; eb += 8) {
-          int cj[8];
-          float xv[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const bool ok = eb + u < e1;
-            const unsigned ec = (unsigned)(ok ? eb + u : e0);
-            if constexpr (COMPACT) {
-              const uint32_t w = xc[ec];
-              cj[u] = (int)(w & 0xffffu);
-              xv[u] = ok ? __uint_as_float(w & 0xffff0000u) : 0.0f;
-            } else {
-              cj[u] = col[ec];
-              const float x = val[ec];
-              xv[u] = ok ? x : 0.0f;
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            // a slot that no lane of the wavefront uses is skipped (no LDS gathers)
-            if (u == 0 || eb + u < e1) {
-              const float x = xv[u];
-              float v[RT];
-              lds_row<RT>(sV + cj[u] * RTP, v);
-#pragma unroll
-              for (int r = 0; r < RT; ++r) t[r] += x * v[r];
-            }
-          }
-        }
-        const float c[kLMax] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
-#pragma unroll
-        for (int a = 0; a < kLMax; ++a)
-#pragma unroll
-          for (int r = 0; r < RT; ++r) acc[a][r] += c[a] * t[r];
-      }
-      // sum over the subject's G lanes (wave-uniform G) by a reduce-scatter: each lane ends
-      // with the totals of the elements e = m G + sub of the l x RT block (e = a RT + r; the
-      // element list is padded with zeros to a multiple of G), which it stores, so the
-      // subject's G lanes write consecutive words
-      constexpr int E = kLMax * RT;
-      float *dst = T + (int64_t)k * l * R + c0;
-      auto scatter_store = [&](auto gc) {
-        constexpr int Gc = decltype(gc)::value;
-        constexpr int Ep = (E + Gc - 1) / Gc * Gc;
-        float v[Ep];
-#pragma unroll
-        for (int e = 0; e < Ep; ++e) v[e] = e < E ? acc[e / RT][e % RT] : 0.0f;
-        reduce_scatter<Ep, Gc>(v, sub);
-        if (active) {
-#pragma unroll
-          for (int m = 0; m < Ep / Gc; ++m) {
-            const int e = m * Gc + sub, a = e / RT, r = e - a * RT;
-            if (e < E && a < l && c0 + r < R) dst[a * R + r] = v[m];
-          }
-        }
-      };
-      switch (lg) {
-        case 0: scatter_store(std::integral_constant<int, 1>{}); break;
-        case 1: scatter_store(std::integral_constant<int, 2>{}); break;
-        case 2: scatter_store(std::integral_constant<int, 4>{}); break;
-        case 3: scatter_store(std::integral_constant<int, 8>{}); break;
-        case 4: scatter_store(std::integral_constant<int, 16>{}); break;
-        case 5: scatter_store(std::integral_constant<int, 32>{}); break;
-        default: scatter_store(std::integral_constant<int, 64>{}); break;
-      }
-    } else if (active) {
-      for (int i = r0 + sub; i < r1; i += G) {
-        float t[RTP];
-#pragma unroll
-        for (int r = 0; r < RTP; ++r) t[r] = 0.0f;
-        const int e0 = row[i], e1 = row[i + 1];
-        for (int eb = e0; eb < e1; eb += 8) {
-          int cj[8];
-          float xv[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const bool ok = eb + u < e1;
-            const unsigned ec = (unsigned)(ok ? eb + u : e0);
-            if constexpr (COMPACT) {
-              const uint32_t w = xc[ec];
-              cj[u] = (int)(w & 0xffffu);
-              xv[u] = ok ? __uint_as_float(w & 0xffff0000u) : 0.0f;
-            } else {
-              cj[u] = col[ec];
-              const float x = val[ec];
-              xv[u] = ok ? x : 0.0f;
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            if (u == 0 || eb + u < e1) {  // slots no lane uses skip their gathers
-              const float x = xv[u];
-              float v[RT];
-              lds_row<RT>(sV + (int64_t)cj[u] * RTP, v);
-#pragma unroll
-              for (int r = 0; r < RT; ++r) t[r] += x * v[r];
-            }
-          }
-        }
-        float *dst = T + (int64_t)i * R + c0;
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-          if (c0 + r < R) dst[r] = t[r];
-      }
-    }
-  }
+  if (best.nt == 0) best = Tiles{R, 1, 1};  // build_plan rejects J when even this does not fit
+  return best;
 }
 
-// V (J x R) -> padded column tiles Vp[tile][j][0..RTP) (padding stays zero)
-template <int R>
-__global__ void k_pad_V(const float *__restrict__ V, float *__restrict__ Vp, int64_t J, int rt,
-                        int rtp) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= J * R) return;
-  const int64_t j = e / R;
-  const int c = (int)(e - j * R);
-  Vp[((int64_t)(c / rt) * J + j) * rtp + c % rt] = V[e];
-}
+// Widths pass 2 has kernels for.
+bool pass2_width_supported(int rt) { return rt >= 1 && (rt <= 16 || rt == 20 || rt == 24 || rt == 32 || rt == 40); }
 
-// ======================================================================= Procrustes
-// Reciprocal and reciprocal square root in FP64 from the hardware estimates plus two Newton
-// steps each (a few ulp; far shorter dependency chains than IEEE division and sqrt).
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
+// Pass 2 keeps a block's F_V tile and one chunk of u rows in LDS: the fewest column tiles whose
+// width has a kernel and fits; nt = 0 when none fits (pass 2 then runs unchunked).
+Tiles choose_tiles2(int R, int64_t J, int lds_limit) {
+  for (int nt = 1; nt <= R; ++nt) {
+    const int rt = (R + nt - 1) / nt;
+    if ((nt - 1) * rt >= R || !pass2_width_supported(rt)) continue;
+    if ((J + kChunkRows) * row4(rt) * 4 + 16 <= (int64_t)lds_limit) return Tiles{nt, rt, 1};
+  }
+  return Tiles{0, 0, 0};
 }
-__device__ __forceinline__ double rsq_nr(double x) {
-  const double h = 0.5 * x;
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * fma(-h * y, y, 1.5);
-  y = y * fma(-h * y, y, 1.5);
-  return y;
-}
-// Jacobi rotation of the pair (p, q): t = tan(theta) of the smaller angle that annihilates
-// a_pq, c = cos(theta), s = sin(theta). |tau| < 1e17 because a_pq is above the threshold, so
-// 1 + tau^2 does not overflow.
-__device__ __forceinline__ void jacobi_cs(double app, double aqq, double apq, double &t, double &c,
-                                          double &s) {
-  const double tau = (aqq - app) * rcp_nr(2.0 * apq);
-  const double x = fma(tau, tau, 1.0);
-  const double h = x * rsq_nr(x);  // sqrt(1 + tau^2)
-  t = copysign(rcp_nr(fabs(tau) + h), tau);
-  c = rsq_nr(fma(t, t, 1.0));
-  s = t * c;
-}
-
-// Symmetric eigenproblem of size <= kNMax in registers (cyclic Jacobi, FP64). A is stored as a
-// full array but only compile-time indices are used; on return A's diagonal holds the
-// eigenvalues and V the eigenvectors (columns).
-__device__ __forceinline__ void jacobi8(double (&A)[kNMax][kNMax], double (&V)[kNMax][kNMax]) {
-#pragma unroll
-  for (int i = 0; i < kNMax; ++i)
-#pragma unroll
-    for (int j = 0; j < kNMax; ++j) V[i][j] = i == j ? 1.0 : 0.0;
-  double scale = 0.0;
-#pragma unroll
-  for (int i = 0; i < kNMax; ++i) scale += fabs(A[i][i]);
-  const double tiny = 1e-300 + 1e-17 * scale;
-  for (int sweep = 0; sweep < 16; ++sweep) {
-    bool rotated = false;
-#pragma unroll
-    for (int p = 0; p < kNMax - 1; ++p) {
-#pragma unroll
-      for (int q = p + 1; q < kNMax; ++q) {
-        const double apq = A[p][q];
-        if (fabs(apq) > tiny) {
-          rotated = true;
-          double t, c, s;
-          jacobi_cs(A[p][p], A[q][q], apq, t, c, s);
-#pragma unroll
-          for (int k = 0; k < kNMax; ++k) {
-            if (k == p || k == q) continue;
-            const double akp = A[k][p], akq = A[k][q];
-            const double nkp = c * akp - s * akq, nkq = s * akp + c * akq;
-            A[k][p] = nkp;
-            A[p][k] = nkp;
-            A[k][q] = nkq;
-            A[q][k] = nkq;
-          }
-          A[p][p] -= t * apq;
-          A[q][q] += t * apq;
-          A[p][q] = 0.0;
-          A[q][p] = 0.0;
-#pragma unroll
-          for (int k = 0; k < kNMax; ++k) {
-            const double vkp = V[k][p], vkq = V[k][q];
-            V[k][p] = c * vkp - s * vkq;
-            V[k][q] = s * vkp + c * vkq;
-          }
-        }
-      }
-    }
-    if (!rotated) break;
-  }
-}
-
-// Eigensolver on a packed upper triangle (N (N + 1) / 2 values), for the register-resident path;
-// N is the padded problem size.
-template <int N>
-__host__ __device__ constexpr int triN(int i, int j) {
-  return i <= j ? N * i - (i * (i - 1)) / 2 + (j - i) : N * j - (j * (j - 1)) / 2 + (i - j);
-}
-
-// Round-robin ("circle") order of the index pairs: with M players (N rounded up to even; an odd N
-// adds one that sits out), round r pairs r with M - 1 and (r + m) with (r - m) mod (M - 1) for
-// m = 1 .. M/2 - 1. Every pair meets once in M - 1 rounds and the pairs of a round are disjoint.
-__host__ __device__ constexpr int rr_lo(int M, int r, int m) {
-  const int a = m == 0 ? r : (r + m) % (M - 1), b = m == 0 ? M - 1 : (r - m + (M - 1)) % (M - 1);
-  return a < b ? a : b;
-}
-__host__ __device__ constexpr int rr_hi(int M, int r, int m) {
-  const int a = m == 0 ? r : (r + m) % (M - 1), b = m == 0 ? M - 1 : (r - m + (M - 1)) % (M - 1);
-  return a < b ? b : a;
-}
-
-// Cyclic Jacobi in round-robin order. On entry V holds an orthogonal matrix and A = V^T G V; the
-// rotations are accumulated onto V, so on return V holds the eigenvectors of G and A's diagonal
-// its eigenvalues. The rotations of one round act on disjoint index pairs, so they commute: their
-// angles are all taken from the matrix at the start of the round (independent dependency chains
-// for the scheduler) and then applied one after the other. No branches: a pair whose entry is at
-// or below the threshold gets the identity rotation. The sweep loop ends for the whole wavefront
-// once no lane has an off-diagonal entry above the threshold.
-template <int N>
-__device__ __forceinline__ void jacobi_rr(double (&A)[N * (N + 1) / 2], double (&V)[N][N]) {
-  constexpr int M = N + (N & 1);
-  constexpr int P = M / 2;
-  double scale = 0.0;
-#pragma unroll
-  for (int i = 0; i < N; ++i) scale += fabs(A[triN<N>(i, i)]);
-  const double tiny = 1e-300 + 1e-17 * scale;
-  for (int sweep = 0; sweep < 16; ++sweep) {
-    bool big = false;
-#pragma unroll
-    for (int p = 0; p < N - 1; ++p)
-#pragma unroll
-      for (int q = p + 1; q < N; ++q) big = big || fabs(A[triN<N>(p, q)]) > tiny;
-    if (!__any(big)) break;
-#pragma unroll
-    for (int r = 0; r < M - 1; ++r) {
-      double tt[P], cc[P], ss[P];
-#pragma unroll
-      for (int m = 0; m < P; ++m) {
-        const int p = rr_lo(M, r, m), q = rr_hi(M, r, m);
-        if (q >= N) continue;
-        const double apq = A[triN<N>(p, q)];
-        const bool on = fabs(apq) > tiny;
-        double t, c, s;
-        jacobi_cs(A[triN<N>(p, p)], A[triN<N>(q, q)], on ? apq : 1.0, t, c, s);
-        tt[m] = on ? t : 0.0;
-        cc[m] = on ? c : 1.0;
-        ss[m] = on ? s : 0.0;
-      }
-#pragma unroll
-      for (int m = 0; m < P; ++m) {
-        const int p = rr_lo(M, r, m), q = rr_hi(M, r, m);
-        if (q >= N) continue;
-        const double t = tt[m], c = cc[m], s = ss[m];
-        const double apq = A[triN<N>(p, q)];
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-          if (k == p || k == q) continue;
-          const double akp = A[triN<N>(k, p)], akq = A[triN<N>(k, q)];
-          A[triN<N>(k, p)] = c * akp - s * akq;
-          A[triN<N>(k, q)] = s * akp + c * akq;
-        }
-        A[triN<N>(p, p)] -= t * apq;
-        A[triN<N>(q, q)] += t * apq;
-        A[triN<N>(p, q)] = t != 0.0 ? 0.0 : apq;
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-          const double vkp = V[k][p], vkq = V[k][q];
-          V[k][p] = c * vkp - s * vkq;
-          V[k][q] = s * vkp + c * vkq;
-        }
-      }
-    }
-  }
-}
-
-// E <- E (3 I - E^T E) / 2: one Newton-Schulz step towards the nearest orthogonal matrix, taking
-// an FP32-rounded orthogonal matrix (deviation ~1e-7) to FP64 orthogonality (~1e-14).
-template <int N>
-__device__ __forceinline__ void orthonormalize(double (&E)[N][N]) {
-  double Nm[N * (N + 1) / 2];
-#pragma unroll
-  for (int p = 0; p < N; ++p)
-#pragma unroll
-    for (int q = p; q < N; ++q) {
-      double s = 0.0;
-#pragma unroll
-      for (int i = 0; i < N; ++i) s += E[i][p] * E[i][q];
-      Nm[triN<N>(p, q)] = s;
-    }
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    double r[N];
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      double s = 0.0;
-#pragma unroll
-      for (int p = 0; p < N; ++p) s += E[i][p] * Nm[triN<N>(p, q)];
-      r[q] = 1.5 * E[i][q] - 0.5 * s;
-    }
-#pragma unroll
-    for (int q = 0; q < N; ++q) E[i][q] = r[q];
-  }
-}
-
-__global__ void k_eye8(float *__restrict__ Ew, int64_t K) {
-  const int64_t n = K * kNMax * kNMax;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ent = e / K;
-    Ew[e] = (ent / kNMax == ent % kNMax) ? 1.0f : 0.0f;
-  }
-}
-
-// One subject per lane, eigenproblem size n = min(m, R) <= kNMax.
-// A rows a_i = (t_i * w) H^T are computed in FP64 and kept as FP32 in the M buffer (free until
-// the W update). Rows side (m <= R): Gram A A^T, Q = (A A^T)^{+1/2} A. Columns side (m > R):
-// Gram A^T A, Q = A (A^T A)^{+1/2}. Eigenvalues at or below rtol^2 * lambda_max are dropped.
-template <int R>
-__global__ void __launch_bounds__(64)
-    k_procrustes(int64_t K, int l, const int32_t *__restrict__ subj,
-                 const int32_t *__restrict__ rk, const float *__restrict__ T,
-                 float *__restrict__ Q, float *__restrict__ Abuf, const float *__restrict__ H,
-                 const float *__restrict__ W, double rtol, FitScalars *sc) {
-  __shared__ float sH[R * R];
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sH[e] = H[e];
-  __syncthreads();
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
-  int64_t base;
-  int m, meff;
-  if (l > 0) {
-    base = k * l;
-    m = l;
-    meff = rk[k];
-  } else {
-    base = subj[k];
-    m = subj[k + 1] - subj[k];
-    meff = m;
-  }
-  if ((m < R ? m : R) > kNMax) return;  // one wavefront per subject handles these
-  float w[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) w[r] = W[k * R + r];
-  const bool rows_side = m <= R;
-  double G[kNMax][kNMax];
-#pragma unroll
-  for (int i = 0; i < kNMax; ++i)
-#pragma unroll
-    for (int j = 0; j < kNMax; ++j) G[i][j] = 0.0;
-  // stage 1: A rows; columns-side Gram on the fly
-  for (int i = 0; i < m; ++i) {
-    const float *t = T + (base + i) * R;
-    float z[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) z[r] = t[r] * w[r];
-    float a[R];
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      double s = 0.0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) s += (double)z[r] * (double)sH[c * R + r];
-      a[c] = (float)s;
-    }
-    float *dst = Abuf + (base + i) * R;
-#pragma unroll
-    for (int c = 0; c < R; ++c) dst[c] = a[c];
-    if (!rows_side) {
-#pragma unroll
-      for (int p = 0; p < kNMax; ++p)
-#pragma unroll
-        for (int q = 0; q < kNMax; ++q)
-          if (p < R && q < R && q >= p) G[p][q] += (double)a[p < R ? p : 0] * a[q < R ? q : 0];
-    }
-  }
-  if (rows_side) {
-#pragma unroll
-    for (int p = 0; p < kNMax; ++p) {
-      if (p < m) {
-        const float *ap = Abuf + (base + p) * R;
-#pragma unroll
-        for (int q = 0; q < kNMax; ++q) {
-          if (q >= p && q < m) {
-            const float *aq = Abuf + (base + q) * R;
-            double s = 0.0;
-#pragma unroll
-            for (int c = 0; c < R; ++c) s += (double)ap[c] * aq[c];
-            G[p][q] = s;
-          }
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int p = 0; p < kNMax; ++p)
-#pragma unroll
-    for (int q = 0; q < p; ++q) G[p][q] = G[q][p];
-  double E[kNMax][kNMax];
-  jacobi8(G, E);
-  double lmax = 0.0;
-#pragma unroll
-  for (int j = 0; j < kNMax; ++j) lmax = fmax(lmax, G[j][j]);
-  double f[kNMax];
-  int rank = 0;
-#pragma unroll
-  for (int j = 0; j < kNMax; ++j) {
-    const bool keep = lmax > 0.0 && G[j][j] > rtol * rtol * lmax;
-    f[j] = keep ? 1.0 / sqrt(G[j][j]) : 0.0;
-    rank += keep ? 1 : 0;
-  }
-  // B = E diag(f) E^T  (overwrite G)
-#pragma unroll
-  for (int i = 0; i < kNMax; ++i)
-#pragma unroll
-    for (int j = 0; j < kNMax; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < kNMax; ++q) s += E[i][q] * f[q] * E[j][q];
-      G[i][j] = s;
-    }
-  if (rows_side) {
-    // q_i = sum_j B(i,j) a_j
-#pragma unroll
-    for (int i = 0; i < kNMax; ++i) {
-      if (i < m) {
-        double acc[R];
-#pragma unroll
-        for (int c = 0; c < R; ++c) acc[c] = 0.0;
-#pragma unroll
-        for (int j = 0; j < kNMax; ++j) {
-          if (j < m) {
-            const float *aj = Abuf + (base + j) * R;
-            const double b = G[i][j];
-#pragma unroll
-            for (int c = 0; c < R; ++c) acc[c] += b * aj[c];
-          }
-        }
-        float *dst = Q + (base + i) * R;
-#pragma unroll
-        for (int c = 0; c < R; ++c) dst[c] = (float)acc[c];
-      }
-    }
-  } else {
-    for (int i = 0; i < m; ++i) {
-      const float *ai = Abuf + (base + i) * R;
-      float a[R];
-#pragma unroll
-      for (int c = 0; c < R; ++c) a[c] = ai[c];
-      float *dst = Q + (base + i) * R;
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < kNMax; ++j)
-          if (j < R) s += (double)a[j < R ? j : 0] * G[j][c < kNMax ? c : 0];
-        dst[c] = (float)s;
-      }
-    }
-  }
-  if (rank < (meff < R ? meff : R)) atomicAdd(&sc->rank_def_slot[sc->cur & 1], 1);
-}
-
-// Unsmoothed subjects whose eigenproblem n = min(I_k, R) exceeds what a lane holds: one
-// wavefront per subject, n x n Gram and eigenvectors in LDS (FP64), cyclic Jacobi with every lane
-// updating one row/column per rotation. Rows side (I_k <= R): A = T S H^T (I_k x R) in LDS,
-// Gram A A^T, Q = B A. Columns side (I_k > R): Gamma = sum_i t_i^T t_i streamed, Gram
-// H S Gamma S H^T, N = S H^T B and Q rows q_i = t_i N.
-template <int R>
-__global__ void __launch_bounds__(64)
-    k_procrustes_wave(const int32_t *__restrict__ list, int nlist,
-                      const int32_t *__restrict__ subj, const float *__restrict__ T,
-                      float *__restrict__ Q, const float *__restrict__ H,
-                      const float *__restrict__ W, double rtol, FitScalars *sc) {
-  __shared__ double sG[R * R];
-  __shared__ double sE[R * R];
-  __shared__ double sA[R * R];  // A (rows side) or Gamma, then N (columns side)
-  __shared__ double sw[R];
-  __shared__ double sf[R];
-  __shared__ float sH[R * R];
-  const int lane = threadIdx.x;
-  if ((int)blockIdx.x >= nlist) return;
-  const int k = list[blockIdx.x];
-  const int r0 = subj[k], m = subj[k + 1] - r0;
-  const bool rows_side = m <= R;
-  const int n = rows_side ? m : R;
-  for (int e = lane; e < R * R; e += 64) sH[e] = H[e];
-  for (int e = lane; e < R; e += 64) sw[e] = W[(int64_t)k * R + e];
-  __syncthreads();
-  if (rows_side) {
-    // A(i, c) = sum_r t_i[r] w_r H(c, r)
-    for (int e = lane; e < m * R; e += 64) {
-      const int i = e / R, c = e % R;
-      const float *t = T + (int64_t)(r0 + i) * R;
-      double s = 0.0;
-      for (int r = 0; r < R; ++r) s += (double)t[r] * sw[r] * (double)sH[c * R + r];
-      sA[i * R + c] = (double)(float)s;
-    }
-    __syncthreads();
-    for (int e = lane; e < n * n; e += 64) {
-      const int p = e / n, q = e % n;
-      double s = 0.0;
-      for (int c = 0; c < R; ++c) s += sA[p * R + c] * sA[q * R + c];
-      sG[p * n + q] = s;
-    }
-  } else {
-    // Gamma = T^T T (lane a owns row a), then Z = Gamma o (w w^T) and G = H Z H^T
-    double acc[R];
-    for (int b = 0; b < R; ++b) acc[b] = 0.0;
-    for (int i = 0; i < m; ++i) {
-      const float *t = T + (int64_t)(r0 + i) * R;
-      const double ta = lane < R ? (double)t[lane] : 0.0;
-#pragma unroll
-      for (int b = 0; b < R; ++b) acc[b] += ta * (double)t[b];
-    }
-    if (lane < R)
-      for (int b = 0; b < R; ++b) sA[lane * R + b] = acc[b] * sw[lane] * sw[b];
-    __syncthreads();
-    // sE <- H Z
-    for (int e = lane; e < R * R; e += 64) {
-      const int a = e / R, b = e % R;
-      double s = 0.0;
-      for (int c = 0; c < R; ++c) s += (double)sH[a * R + c] * sA[c * R + b];
-      sE[e] = s;
-    }
-    __syncthreads();
-    for (int e = lane; e < R * R; e += 64) {
-      const int a = e / R, b = e % R;
-      double s = 0.0;
-      for (int c = 0; c < R; ++c) s += sE[a * R + c] * (double)sH[b * R + c];
-      sG[a * R + b] = s;
-    }
-  }
-  __syncthreads();
-  for (int e = lane; e < n * n; e += 64) sE[e] = (e / n == e % n) ? 1.0 : 0.0;
-  double scale = 0.0;
-  for (int i = 0; i < n; ++i) scale += fabs(sG[i * n + i]);
-  const double tiny = 1e-300 + 1e-17 * scale;
-  __syncthreads();
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    bool rotated = false;
-    for (int p = 0; p < n - 1; ++p) {
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = sG[p * n + q];
-        if (fabs(apq) > tiny) {
-          rotated = true;
-          const double app = sG[p * n + p], aqq = sG[q * n + q];
-          double t, c, s;
-          jacobi_cs(app, aqq, apq, t, c, s);
-          __syncthreads();
-          if (lane < n && lane != p && lane != q) {
-            const double gkp = sG[lane * n + p], gkq = sG[lane * n + q];
-            const double np_ = c * gkp - s * gkq, nq_ = s * gkp + c * gkq;
-            sG[lane * n + p] = np_;
-            sG[p * n + lane] = np_;
-            sG[lane * n + q] = nq_;
-            sG[q * n + lane] = nq_;
-          }
-          if (lane < n) {
-            const double vkp = sE[lane * n + p], vkq = sE[lane * n + q];
-            sE[lane * n + p] = c * vkp - s * vkq;
-            sE[lane * n + q] = s * vkp + c * vkq;
-          }
-          if (lane == 0) {
-            sG[p * n + p] = app - t * apq;
-            sG[q * n + q] = aqq + t * apq;
-            sG[p * n + q] = 0.0;
-            sG[q * n + p] = 0.0;
-          }
-          __syncthreads();
-        }
-      }
-    }
-    if (!rotated) break;
-  }
-  double lmax = 0.0;
-  for (int j = 0; j < n; ++j) lmax = fmax(lmax, sG[j * n + j]);
-  int rank = 0;
-  for (int j = 0; j < n; ++j) rank += (lmax > 0.0 && sG[j * n + j] > rtol * rtol * lmax) ? 1 : 0;
-  if (lane < n) {
-    const double lj = sG[lane * n + lane];
-    sf[lane] = (lmax > 0.0 && lj > rtol * rtol * lmax) ? 1.0 / sqrt(lj) : 0.0;
-  }
-  __syncthreads();
-  // B = E diag(f) E^T (n x n) into sG
-  for (int e = lane; e < n * n; e += 64) {
-    const int i = e / n, j = e % n;
-    double s = 0.0;
-    for (int q = 0; q < n; ++q) s += sE[i * n + q] * sf[q] * sE[j * n + q];
-    sG[e] = s;
-  }
-  __syncthreads();
-  if (rows_side) {
-    // Q = B A
-    for (int e = lane; e < m * R; e += 64) {
-      const int i = e / R, c = e % R;
-      double s = 0.0;
-      for (int j = 0; j < m; ++j) s += sG[i * n + j] * sA[j * R + c];
-      Q[(int64_t)(r0 + i) * R + c] = (float)s;
-    }
-  } else {
-    // N = S H^T B (R x R) into sA, then q_i = t_i N
-    for (int e = lane; e < R * R; e += 64) {
-      const int a = e / R, b = e % R;
-      double s = 0.0;
-      for (int c = 0; c < R; ++c) s += (double)sH[c * R + a] * sG[c * R + b];
-      sA[e] = sw[a] * s;
-    }
-    __syncthreads();
-    for (int i = 0; i < m; ++i) {
-      const float *t = T + (int64_t)(r0 + i) * R;
-      if (lane < R) {
-        double s = 0.0;
-        for (int r = 0; r < R; ++r) s += (double)t[r] * sA[r * R + lane];
-        Q[(int64_t)(r0 + i) * R + lane] = (float)s;
-      }
-    }
-  }
-  if (lane == 0 && rank < (m < R ? m : R)) atomicAdd(&sc->rank_def_slot[sc->cur & 1], 1);
-}
-
-// Smoothed subjects (l <= N <= 8 projected rows) with R <= 16: one subject per lane, the
-// eigenproblem in registers, A in LDS (FP64 where it fits), H in LDS as FP64 (N = l = 7 is the
-// usual instance, N = 8 the general one; rows at or past l are zero). The 64 subjects of a block
-// own one contiguous run of T rows and of Q rows, so both move through LDS (the A area, before
-// and after A is live) with coalesced 16-byte loads and stores instead of each lane touching its
-// own rows in memory. LDS stays at or below 40 KB, so four blocks fit a compute unit and a
-// 50,000-subject launch is resident at once.
-template <int R, int N>
-struct ProcS {
-  static constexpr bool kDoubleA = N * R * 64 * 8 + R * R * 8 <= 40960;
-  using AT = std::conditional_t<kDoubleA, double, float>;
-};
-
-// dst[0, n) = src[0, n) by the 64 lanes of one wavefront, 16 bytes per lane per step with up to
-// 8 steps in flight; both pointers 16-byte aligned
-__device__ __forceinline__ void copy_run(float *__restrict__ dst, const float *__restrict__ src,
-                                         int n, int lane) {
-  const int n4 = n >> 2;
-  const float4 *s4 = reinterpret_cast<const float4 *>(src);
-  float4 *d4 = reinterpret_cast<float4 *>(dst);
-  for (int e0 = 0; e0 < n4; e0 += 8 * 64) {
-    float4 v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * 64 + lane;
-      v[u] = s4[e < n4 ? e : 0];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * 64 + lane;
-      if (e < n4) d4[e] = v[u];
-    }
-  }
-  for (int e = 4 * n4 + lane; e < n; e += 64) dst[e] = src[e];
-}
-
-template <int R, int N>
-__global__ void __launch_bounds__(64)
-    k_procrustes_s(int64_t K, int l, const int32_t *__restrict__ rk, const float *__restrict__ T,
-                   float *__restrict__ Q, const float *__restrict__ H, const float *__restrict__ W,
-                   float *__restrict__ Ew, double rtol, FitScalars *sc) {
-  using AT = typename ProcS<R, N>::AT;
-  constexpr int NT = N * (N + 1) / 2;
-  __shared__ double sH[R * R];
-  // A of this lane's subject, element (i, c) at (i R + c) 64 + lane; before that the block's T
-  // rows and afterwards its Q rows (64 l R <= 64 N R floats)
-  __shared__ __align__(16) AT sA[N * R * 64];
-  float *sTQ = reinterpret_cast<float *>(sA);
-  const int lane = threadIdx.x;
-  const int64_t k0 = (int64_t)blockIdx.x * 64;
-  const int nsub = (int)(K - k0 < 64 ? K - k0 : 64);
-  for (int e = lane; e < R * R; e += blockDim.x) sH[e] = (double)H[e];
-  copy_run(sTQ, T + k0 * l * R, nsub * l * R, lane);
-  __syncthreads();
-  // lanes past the last subject redo the block's first subject and store nothing
-  const bool live = lane < nsub;
-  const int tl = live ? lane : 0;
-  const int64_t k = k0 + tl;
-  {
-    float tv[N][R];
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int r = 0; r < R; ++r) tv[i][r] = sTQ[(tl * l + (i < l ? i : 0)) * R + r];
-    __syncthreads();  // the T rows are in registers: the area takes A from here on
-    float w[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) w[r] = W[k * R + r];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double z[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) z[r] = (double)(tv[i][r] * w[r]);
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        double s = 0.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) s += z[r] * sH[c * R + r];
-        sA[(i * R + c) * 64 + lane] = i < l ? (AT)s : (AT)0;
-      }
-    }
-  }
-  auto Aat = [&](int i, int c) -> double { return (double)sA[(i * R + c) * 64 + lane]; };
-  const bool rows_side = l <= R;
-  // Warm start: the Gram's eigenvectors change little between outer iterations, so the Jacobi
-  // sweeps run on E^T G E with E = last iteration's eigenvectors (identity on the first), made
-  // orthogonal to FP64 precision first. G = A A^T (rows side) or A^T A (columns side) is summed
-  // from the rotated vectors E^T v over the columns (rows) v of A.
-  double E[N][N];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = 0; j < N; ++j) E[i][j] = (double)Ew[(int64_t)(i * kNMax + j) * K + k];
-  orthonormalize<N>(E);
-  double G[NT];
-#pragma unroll
-  for (int e = 0; e < NT; ++e) G[e] = 0.0;
-  const int nv = rows_side ? R : N;
-  for (int c = 0; c < nv; ++c) {
-    double v[N], a[N];
-#pragma unroll
-    for (int p = 0; p < N; ++p) v[p] = rows_side ? Aat(p, c) : (p < R ? Aat(c, p) : 0.0);
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      double s = 0.0;
-#pragma unroll
-      for (int p = 0; p < N; ++p) s += E[p][q] * v[p];
-      a[q] = s;
-    }
-#pragma unroll
-    for (int p = 0; p < N; ++p)
-#pragma unroll
-      for (int q = p; q < N; ++q) G[triN<N>(p, q)] += a[p] * a[q];
-  }
-  jacobi_rr<N>(G, E);
-  if (live) {
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = 0; j < N; ++j) Ew[(int64_t)(i * kNMax + j) * K + k] = (float)E[i][j];
-  }
-  double lmax = 0.0;
-#pragma unroll
-  for (int j = 0; j < N; ++j) lmax = fmax(lmax, G[triN<N>(j, j)]);
-  double f[N];
-  int rank = 0;
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    const double lj = G[triN<N>(j, j)];
-    const bool keep = lmax > 0.0 && lj > rtol * rtol * lmax;
-    f[j] = keep ? rsq_nr(lj) : 0.0;
-    rank += keep ? 1 : 0;
-  }
-  // B = E diag(f) E^T (symmetric) into the triangle
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = i; j < N; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < N; ++q) s += E[i][q] * f[q] * E[j][q];
-      G[triN<N>(i, j)] = s;
-    }
-  float qv[N][R];
-  if (rows_side) {
-    // Q = B A, one column of A at a time
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      double a[N];
-#pragma unroll
-      for (int j = 0; j < N; ++j) a[j] = Aat(j, c);
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) s += G[triN<N>(i, j)] * a[j];
-        qv[i][c] = (float)s;
-      }
-    }
-  } else {
-    // Q = A B (B is R x R, padded to N with zero rows and columns), one row of A at a time
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double a[N];
-#pragma unroll
-      for (int j = 0; j < N; ++j) a[j] = j < R ? Aat(i, j < R ? j : 0) : 0.0;
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        double s = 0.0;
-        if (c < N) {
-#pragma unroll
-          for (int j = 0; j < N; ++j) s += a[j] * G[triN<N>(j, c < N ? c : 0)];
-        }
-        qv[i][c] = (float)s;
-      }
-    }
-  }
-  const int meff = rk[k];
-  if (live && rank < (meff < R ? meff : R)) atomicAdd(&sc->rank_def_slot[sc->cur & 1], 1);
-  __syncthreads();  // A is consumed: the area takes the Q rows
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-    if (i < l)
-#pragma unroll
-      for (int c = 0; c < R; ++c) sTQ[(lane * l + i) * R + c] = qv[i][c];
-  __syncthreads();
-  copy_run(Q + k0 * l * R, sTQ, nsub * l * R, lane);
-}
-
-// ======================================================================= ADMM helpers
-// sGi <- (X * Y + rho I)^{-1} (Hadamard product, FP64, full R x R), rho = trace(X * Y) / R
-// (Algorithm 1). The first wavefront runs Gauss-Jordan elimination on [G + rho I | I], lane i
-// holding row i; at step j lane j puts the live part of its row in LDS and every lane reads it
-// back (wavefront-local, in order). No pivoting is needed because the matrix is symmetric
-// positive definite, and the rho shift bounds its condition number by R + 1, so the explicit
-// inverse is as accurate as triangular solves and turns every later ADMM step into one
-// matrix-vector product. Whole block (sL: R x R LDS scratch). Returns false (and leaves
-// Gi = I, rho = 1) when a pivot is not positive and finite.
-template <int R>
-__device__ __forceinline__ bool build_system(const double *__restrict__ X,
-                                             const double *__restrict__ Y, double *sL,
-                                             double *sGi, double *srho, int *sflag) {
-  static_assert(R <= kWave, "one row per lane");
-  __shared__ double spiv[R + 1];
-  const int t = threadIdx.x;
-  for (int e = t; e < R * R; e += blockDim.x) sL[e] = X[e] * Y[e];
-  __syncthreads();
-  if (t < kWave) {
-    const int row = t < R ? t : 0;
-    double tr = 0.0;
-#pragma unroll
-    for (int i = 0; i < R; ++i) tr += sL[i * R + i];
-    const double rho = tr / R;
-    bool ok = isfinite(rho) && rho > 0.0;
-    double a[R], b[R];
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      a[c] = sL[row * R + c] + (c == row ? rho : 0.0);
-      b[c] = c == row ? 1.0 : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      // live part of pivot row j: a[j..R-1] and b[0..j] (R + 1 values)
-      if (t == j) {
-#pragma unroll
-        for (int c = j; c < R; ++c) spiv[c - j] = a[c];
-#pragma unroll
-        for (int c = 0; c <= j; ++c) spiv[R - j + c] = b[c];
-      }
-      __builtin_amdgcn_wave_barrier();
-      const double piv = spiv[0];
-      ok = ok && piv > 0.0 && isfinite(piv);
-      const double inv = rcp_nr(piv > 0.0 ? piv : 1.0);
-      const bool me = t == j;
-      const double f = me ? 0.0 : a[j] * inv;
-#pragma unroll
-      for (int c = j + 1; c < R; ++c) a[c] = me ? a[c] * inv : a[c] - f * spiv[c - j];
-#pragma unroll
-      for (int c = 0; c <= j; ++c) b[c] = me ? b[c] * inv : b[c] - f * spiv[R - j + c];
-      __builtin_amdgcn_wave_barrier();
-    }
-    if (t < R) {
-#pragma unroll
-      for (int c = 0; c < R; ++c) sGi[t * R + c] = ok ? b[c] : (c == t ? 1.0 : 0.0);
-    }
-    if (t == 0) {
-      *srho = ok ? rho : 1.0;
-      *sflag = ok ? 0 : 1;
-    }
-  }
-  __syncthreads();
-  return *sflag == 0;
-}
-
-// ======================================================================= ADMM on rows by lanes
-// One factor row spread over R lanes of a wavefront (lane c holds column c): the inner ADMM
-// steps of Algorithm 1, Z = (F + rho (Zb + D)) (G + rho I)^{-1}, Zb = prox(Z - D), D += Zb - Z,
-// with the row vector exchanged through this group's LDS slot xrow (wavefront-local: LDS
-// operations of one wavefront complete in order, so a compiler barrier is enough).
-template <int R>
-__device__ __forceinline__ void admm_lanes(double F, float &Zb, float &D,
-                                           const double *__restrict__ sGi, double rho, int kind,
-                                           double lam, int iters, double *xrow, int c) {
-  const double thr = lam / rho;
-  for (int it = 0; it < iters; ++it) {
-    xrow[c] = F + rho * ((double)Zb + (double)D);
-    __builtin_amdgcn_wave_barrier();
-    double z = 0.0;
-#pragma unroll
-    for (int k = 0; k < R; ++k) z += xrow[k] * sGi[k * R + c];
-    __builtin_amdgcn_wave_barrier();
-    const double zb = prox_sel(z - (double)D, kind, lam, thr);
-    D = (float)((double)D + zb - z);
-    Zb = (float)zb;
-  }
-}
-
-// ======================================================================= FIT of an iteration
-// Inputs of the FIT and objective of outer iteration `it`, left as per-block partials by the V
-// update and the W update of that iteration.
-struct FitArgs {
-  const double *vpart;    // [nvb x 4] <F_V, V>, |V|_1, zeros
-  const double *vtvpart;  // [nvb x R x R] V^T V
-  int nvb;
-  const double *wl1part;  // [nwb] |W|_1
-  int nwb;
-  double normX2;
-  int64_t J;
-  int proxV, proxW, proxH;
-  double lamV, lamW, lamH;
-};
-
-// Whole block (256 threads; red: 6 x 256 doubles of LDS, sVtV: R x R of LDS). Adds the partials
-// in block order, stores V^T V, and evaluates
-//   FIT = 1 - (|X|^2 - 2 <F_V, V> + <Psi, V^T V>) / |X|^2   (Section "Evaluation Metrics")
-// and the objective with the l1 penalties, with H = the factor of that iteration.
-template <int R>
-__device__ __forceinline__ void fit_finalize(const FitArgs &fa, int it, const float *H,
-                                             double *small, FitScalars *sc, double (*red)[256],
-                                             double *sVtV) {
-  constexpr int RR = R * R;
-  const int t = threadIdx.x;
-  block_reduce_parts<RR>(fa.vtvpart, fa.nvb, sVtV, red[0]);
-  double dot = 0.0, l1 = 0.0, zeros = 0.0, wl1 = 0.0, hl1 = 0.0, quad = 0.0;
-  for (int b = t; b < fa.nvb; b += blockDim.x) {
-    dot += fa.vpart[b * 4 + 0];
-    l1 += fa.vpart[b * 4 + 1];
-    zeros += fa.vpart[b * 4 + 2];
-  }
-  // the W-update partials (one per block of that launch, thousands at large K): eight loads in
-  // flight per thread, from clamped addresses
-  {
-    double w8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int nt = blockDim.x;
-    for (int b0 = t; b0 < fa.nwb; b0 += 8 * nt) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int b = b0 + u * nt;
-        const double x = fa.wl1part[b < fa.nwb ? b : 0];
-        w8[u] += b < fa.nwb ? x : 0.0;
-      }
-    }
-    wl1 = ((w8[0] + w8[1]) + (w8[2] + w8[3])) + ((w8[4] + w8[5]) + (w8[6] + w8[7]));
-  }
-  for (int e = t; e < RR; e += blockDim.x) {
-    hl1 += fabs((double)H[e]);
-    quad += small[kPsi * RR + e] * sVtV[e];
-    small[kVtV * RR + e] = sVtV[e];
-  }
-  red[0][t] = dot;
-  red[1][t] = l1;
-  red[2][t] = zeros;
-  red[3][t] = quad;
-  red[4][t] = wl1;
-  red[5][t] = hl1;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w)
-#pragma unroll
-      for (int q = 0; q < 6; ++q) red[q][t] += red[q][t + w];
-    __syncthreads();
-  }
-  if (t == 0) {
-    const double resid = fa.normX2 - 2.0 * red[0][0] + red[3][0];
-    const double fit = fa.normX2 > 0.0 ? 1.0 - resid / fa.normX2 : 0.0;
-    auto pen = [](int k, double la, double v) {
-      return (k == COPA_PROX_L1 || k == COPA_PROX_NONNEG_L1) ? la * v : 0.0;
-    };
-    const double obj = 0.5 * resid + pen(fa.proxV, fa.lamV, red[1][0]) +
-                       pen(fa.proxW, fa.lamW, red[4][0]) + pen(fa.proxH, fa.lamH, red[5][0]);
-    if (!isfinite(fit) || !isfinite(obj)) atomicMin(&sc->fail_iter, it);
-    if (it < kHistCap) {
-      sc->hist_fit[it] = fit;
-      sc->hist_obj[it] = obj;
-    }
-    sc->last_fit = fit;
-    sc->last_obj = obj;
-    sc->last_sparsity = fa.J > 0 ? red[2][0] / ((double)fa.J * R) : 0.0;
-    sc->rank_deficient = sc->rank_def_slot[it & 1];
-    sc->rank_def_slot[it & 1] = 0;
-    sc->iter = it + 1;
-  }
-  __syncthreads();
-}
-
-template <int R>
-__global__ void __launch_bounds__(256)
-    k_fit(FitArgs fa, const float *H, double *small, FitScalars *sc) {
-  __shared__ double red[6][256];
-  __shared__ double sVtV[R * R];
-  fit_finalize<R>(fa, sc->cur, H, small, sc, red, sVtV);
-}
-
-// The row Gram F_H = sum Q_row^T (T_row * w) (as k_rows_gram) with one extra block that takes
-// the FIT of the previous outer iteration meanwhile (when the current iteration is not the first
-// of its chunk).
-template <int R, int WSEL>
-__global__ void __launch_bounds__(256)
-    k_rows_gram_fit(const float *__restrict__ A, const float *__restrict__ B, int64_t rows,
-                    const float *__restrict__ W, int slot_rows,
-                    const int32_t *__restrict__ rowsubj, double *__restrict__ part, int nb,
-                    FitArgs fa, const float *__restrict__ H, double *small, FitScalars *sc) {
-  if ((int)blockIdx.x == nb) {
-    __shared__ double red[6][256];
-    __shared__ double sVtV[R * R];
-    const int it = sc->cur;
-    if (it > 0) fit_finalize<R>(fa, it - 1, H, small, sc, red, sVtV);
-    return;
-  }
-  rows_gram_block<R, WSEL>(A, B, rows, W, slot_rows, rowsubj, part, blockIdx.x, nb);
-}
-
-template <int R>
-static void gram_fit(copa_plan *p, const float *A, const float *B, int64_t rows,
-                     const float *W, int wsel, int slot, const FitArgs &fa, const float *H,
-                     hipStream_t s) {
-  const int64_t units = (rows + 63) / 64;
-  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(p->gmaxnb, (units + 7) / 8));
-  const unsigned grid = (unsigned)nb + 1u;
-  double *p1 = gram_slot(p, slot);
-  const int sr = p->slot_rows > 0 ? p->slot_rows : 1;
-  if (wsel == 1)
-    k_rows_gram_fit<R, 1><<<grid, 256, 0, s>>>(A, B, rows, W, sr, p->rowsubj, p1, nb, fa, H,
-                                               p->small, p->scal);
-  else
-    k_rows_gram_fit<R, 2><<<grid, 256, 0, s>>>(A, B, rows, W, sr, p->rowsubj, p1, nb, fa, H,
-                                               p->small, p->scal);
-  k_gram_reduce<R * R><<<dim3((R * R + 3) / 4, 1), 256, 0, s>>>(p1, gram_total(p, slot), nullptr,
-                                                                 nullptr, nb);
-}
-
-// ======================================================================= mode H (one block)
-// G_H = W^TW * V^TV, rho, (G_H + rho I)^{-1}; inner ADMM on the R rows of H (R lanes per row);
-// H^T H; then the W-mode system G_W = H^TH * V^TV for the W update.
-template <int R>
-__global__ void __launch_bounds__(256)
-    k_mode_H(const double *FHtot, double *small, ModeParams *modes, FitScalars *sc,
-             float *H, float *DH, int kind, double lam, int iters) {
-  constexpr int RR = R * R;
-  constexpr int G = kWave / R;
-  __shared__ double sFH[RR], sX[RR], sY[RR], sL[RR], sGi[RR];
-  __shared__ double xch[4][G + 1][R];
-  __shared__ float sH[RR];
-  __shared__ double srho;
-  __shared__ int sflag;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int g = lane / R, c = lane % R;
-  for (int e = t; e < RR; e += blockDim.x) {
-    sFH[e] = FHtot[e];
-    sX[e] = small[kWtW * RR + e];
-    sY[e] = small[kVtV * RR + e];
-  }
-  __syncthreads();
-  for (int e = t; e < RR; e += blockDim.x) small[kFH * RR + e] = sFH[e];
-  bool ok = build_system<R>(sX, sY, sL, sGi, &srho, &sflag);
-  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
-  const double rho = srho;
-  for (int r0 = 0; r0 < R; r0 += 4 * G) {
-    const int row = r0 + wave * G + g;
-    const bool act = g < G && row < R;
-    const int rc = act ? row : 0;
-    float Zb = H[rc * R + c], D = DH[rc * R + c];
-    admm_lanes<R>(sFH[rc * R + c], Zb, D, sGi, rho, kind, lam, iters, xch[wave][g], c);
-    if (act) {
-      H[row * R + c] = Zb;
-      DH[row * R + c] = D;
-      sH[row * R + c] = Zb;
-    }
-  }
-  __syncthreads();
-  for (int e = t; e < RR; e += blockDim.x) {
-    const int a = e / R, b = e % R;
-    double v = 0.0;
-#pragma unroll
-    for (int i = 0; i < R; ++i) v += (double)sH[i * R + a] * (double)sH[i * R + b];
-    sX[e] = v;
-    small[kHtH * RR + e] = v;
-  }
-  __syncthreads();
-  ok = build_system<R>(sX, sY, sL, sGi, &srho, &sflag);
-  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
-  for (int e = t; e < RR; e += blockDim.x) modes[1].Gi[e] = sGi[e];
-  if (t == 0) modes[1].rho = srho;
-}
-
-// ======================================================================= mode W (R lanes/subject)
-// One subject per group of R lanes (lane c holds column c): F_W(k, c) = sum_i (q_i H)(c) t_i(c)
-// (the q rows exchanged through wavefront-local LDS), the inner ADMM steps on W's row k, then the
-// M rows (q_i H) * w_k for pass 2 and the Psi Gram; per-block |W|_1 for the objective.
-template <int R>
-__global__ void __launch_bounds__(256)
-    k_w_admm(int64_t K, int l, const int32_t *__restrict__ subj, const int32_t *__restrict__ rk,
-             const float *__restrict__ T, const float *__restrict__ Q, float *__restrict__ M,
-             const float *__restrict__ H, float *__restrict__ W, float *__restrict__ DW,
-             float *__restrict__ FW, const ModeParams *__restrict__ modes, int kind, double lam,
-             int iters, double *__restrict__ l1part) {
-  constexpr int G = kWave / R;
-  __shared__ double sGi[R * R];
-  __shared__ float sH[R * R];
-  __shared__ float xq[4][G + 1][kLMax][R];
-  __shared__ double xch[4][G + 1][R];
-  __shared__ double sred[256];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int g = lane / R, c = lane % R;
-  for (int e = t; e < R * R; e += blockDim.x) {
-    sGi[e] = modes[1].Gi[e];
-    sH[e] = H[e];
-  }
-  const int64_t k = ((int64_t)blockIdx.x * 4 + wave) * G + g;
-  const bool act = g < G && k < K;
-  const int64_t kc = act ? k : 0;
-  float Zb = W[kc * R + c], D = DW[kc * R + c];
-  int64_t base;
-  int m;
-  if (l > 0) {
-    base = kc * l;
-    m = rk[kc];
-  } else {
-    base = subj[kc];
-    m = subj[kc + 1] - subj[kc];
-  }
-  if (!act) m = 0;
-  __syncthreads();
-  const double rho = modes[1].rho;
-  double F = 0.0;
-  float qh[kLMax];  // smoothed: (q_i H)(c) of the l rows, kept for the M rows
-  float(&xg)[kLMax][R] = xq[wave][g];
-  if (l > 0) {
-    float qv[kLMax], tv[kLMax];
-#pragma unroll
-    for (int i = 0; i < kLMax; ++i) {
-      const int64_t ri = base + (i < l ? i : 0);
-      qv[i] = Q[ri * R + c];
-      tv[i] = T[ri * R + c];
-    }
-#pragma unroll
-    for (int i = 0; i < kLMax; ++i) xg[i][c] = qv[i];
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int i = 0; i < kLMax; ++i) {
-      double p = 0.0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) p += (double)xg[i][r] * (double)sH[r * R + c];
-      F += i < m ? p * (double)tv[i] : 0.0;
-      qh[i] = (float)p;
-    }
-  } else {
-    for (int i = 0; i < m; ++i) {
-      const float qv = Q[(base + i) * R + c], tv = T[(base + i) * R + c];
-      __builtin_amdgcn_wave_barrier();
-      xg[0][c] = qv;
-      __builtin_amdgcn_wave_barrier();
-      double p = 0.0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) p += (double)xg[0][r] * (double)sH[r * R + c];
-      F += p * (double)tv;
-    }
-  }
-  if (act) FW[k * R + c] = (float)F;
-  admm_lanes<R>(F, Zb, D, sGi, rho, kind, lam, iters, xch[wave][g], c);
-  double l1 = 0.0;
-  if (act) {
-    W[k * R + c] = Zb;
-    DW[k * R + c] = D;
-    l1 = fabs((double)Zb);
-  }
-  // M rows = (q_i H) * w_new
-  if (l > 0) {
-    if (act) {
-#pragma unroll
-      for (int i = 0; i < kLMax; ++i)
-        if (i < l) M[(base + i) * R + c] = (float)((double)qh[i] * (double)Zb);
-    }
-  } else {
-    for (int i = 0; i < m; ++i) {
-      const float qv = Q[(base + i) * R + c];
-      __builtin_amdgcn_wave_barrier();
-      xg[0][c] = qv;
-      __builtin_amdgcn_wave_barrier();
-      double p = 0.0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) p += (double)xg[0][r] * (double)sH[r * R + c];
-      M[(base + i) * R + c] = (float)(p * (double)Zb);
-    }
-  }
-  sred[t] = l1;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) sred[t] += sred[t + w];
-    __syncthreads();
-  }
-  if (t == 0) l1part[blockIdx.x] = sred[0];
-}
-
-// ======================================================================= mode V
-// Every block: G_V = H^TH * W^TW, rho, (G_V + rho I)^{-1}; then its V rows, R lanes per row
-// (inner ADMM, l1 prox), the padded V tile copy for the next pass 1, and per-block partials of
-// <F_V, V>, |V|_1, zeros and V^T V for the FIT (added by the next launch that needs them).
-template <int R>
-__global__ void __launch_bounds__(256)
-    k_v_admm(int64_t J, const float *__restrict__ FV, float *__restrict__ V,
-             float *__restrict__ DV, float *__restrict__ Vp, int rt, int rtp,
-             const double *__restrict__ WtWtot, const double *__restrict__ Psitot, double *small,
-             FitScalars *sc, int kind, double lam, int iters, double *__restrict__ vpart,
-             double *__restrict__ vtvpart) {
-  constexpr int RR = R * R;
-  constexpr int G = kWave / R;
-  constexpr int RB = 4 * G;  // rows per block pass
-  __shared__ double sW[RR], sPsi[RR], sHH[RR], sL[RR], sGi[RR];
-  __shared__ double xch[4][G + 1][R];
-  __shared__ float sV[RB][R];
-  __shared__ double red[3][256];
-  __shared__ double srho;
-  __shared__ int sflag;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int g = lane / R, c = lane % R;
-  const int slot = wave * G + g;
-  for (int e = t; e < RR; e += blockDim.x) {
-    sW[e] = WtWtot[e];
-    sPsi[e] = Psitot[e];
-    sHH[e] = small[kHtH * RR + e];
-  }
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    for (int e = t; e < RR; e += blockDim.x) {
-      small[kWtW * RR + e] = sW[e];
-      small[kPsi * RR + e] = sPsi[e];
-    }
-  }
-  const bool ok = build_system<R>(sHH, sW, sL, sGi, &srho, &sflag);
-  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
-  const double rho = srho;
-  double dot = 0.0, l1 = 0.0, zeros = 0.0;
-  double vtv[(RR + 255) / 256];
-#pragma unroll
-  for (int u = 0; u < (RR + 255) / 256; ++u) vtv[u] = 0.0;
-  for (int64_t j0 = (int64_t)blockIdx.x * RB; j0 < J; j0 += (int64_t)gridDim.x * RB) {
-    const int64_t j = j0 + slot;
-    const bool act = g < G && j < J;
-    const int64_t jc = act ? j : 0;
-    const double F = FV[jc * R + c];
-    float Zb = V[jc * R + c], D = DV[jc * R + c];
-    admm_lanes<R>(F, Zb, D, sGi, rho, kind, lam, iters, xch[wave][g], c);
-    if (act) {
-      V[j * R + c] = Zb;
-      DV[j * R + c] = D;
-      Vp[((int64_t)(c / rt) * J + j) * rtp + c % rt] = Zb;
-      dot += F * (double)Zb;
-      l1 += fabs((double)Zb);
-      zeros += Zb == 0.0f ? 1.0 : 0.0;
-    }
-    if (g < G) sV[slot][c] = act ? Zb : 0.0f;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < (RR + 255) / 256; ++u) {
-      const int e = t + 256 * u;
-      if (e < RR) {
-        const int a = e / R, b = e % R;
-        double v = 0.0;
-#pragma unroll
-        for (int s = 0; s < RB; ++s) v += (double)sV[s][a] * (double)sV[s][b];
-        vtv[u] += v;
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < (RR + 255) / 256; ++u) {
-    const int e = t + 256 * u;
-    if (e < RR) vtvpart[(int64_t)blockIdx.x * RR + e] = vtv[u];
-  }
-  red[0][t] = dot;
-  red[1][t] = l1;
-  red[2][t] = zeros;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w)
-      for (int q = 0; q < 3; ++q) red[q][t] += red[q][t + w];
-    __syncthreads();
-  }
-  if (t < 3) vpart[blockIdx.x * 4 + t] = red[t][0];
-}
-
-template <int R>
-__global__ void __launch_bounds__(256)
-    k_init_small(const double *__restrict__ partW, const double *__restrict__ partV, int nb,
-                 double *small) {
-  __shared__ double scratch[256];
-  block_reduce_parts<R * R>(partW, nb, small + kWtW * R * R, scratch);
-  block_reduce_parts<R * R>(partV, nb, small + kVtV * R * R, scratch);
-}
-
-__global__ void k_zero(float *x, int64_t n) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    x[e] = 0.0f;
-}
-
-__global__ void k_reset_scalars(FitScalars *sc) {
-  if (threadIdx.x == 0) {
-    sc->cur = -1;  // pass 1 of the first iteration makes it 0
-    sc->iter = 0;
-    sc->fail_iter = INT_MAX;
-    sc->rank_deficient = 0;
-    sc->rank_def_slot[0] = 0;
-    sc->rank_def_slot[1] = 0;
-  }
-}
-
-// Qtilde rows: c_i Q_k (smoothed) or the Q row itself
-template <int R>
-__global__ void __launch_bounds__(256)
-    k_qtilde(int64_t S, int l, const int32_t *__restrict__ rowsubj, const float *__restrict__ C,
-             const float *__restrict__ Q, float *__restrict__ Qt) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= S) return;
-  if (l > 0) {
-    const int64_t k = rowsubj[i];
-    float c[kLMax];
-#pragma unroll
-    for (int a = 0; a < kLMax; ++a) c[a] = C[i * kLMax + a];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      float s = 0.0f;
-#pragma unroll
-      for (int a = 0; a < kLMax; ++a)
-        if (a < l) s += c[a] * Q[(k * l + a) * R + r];
-      Qt[i * R + r] = s;
-    }
-  } else {
-#pragma unroll
-    for (int r = 0; r < R; ++r) Qt[i * R + r] = Q[i * R + r];
-  }
-}
-
-// ======================================================================= host launchers
-template <int RT>
-static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
-  constexpr int RTP = row4(RT);
-  size_t lds = (size_t)p->J * RTP * sizeof(float) + sizeof(float4);  // + the spare slot
-  const int per_cu = std::max(1, std::min(4, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
-  const int nb = std::max(1, std::min((p->n_waves + 3) / 4, p->n_cu * per_cu));
-  dim3 grid((unsigned)nb, (unsigned)p->tiles.nt), block(256);
-#define P1(SM, CP)                                                                              \
-  k_pass1<RT, SM, CP><<<grid, block, lds, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,  \
-                                              p->col, p->val, p->xc, p->C, p->Vp, p->J, p->R,  \
-                                              p->l, p->T, p->FV, p->scal)
-  if (p->l > 0) {
-    if (p->compact) P1(true, true); else P1(true, false);
-  } else {
-    if (p->compact) P1(false, true); else P1(false, false);
-  }
-#undef P1
-}
-
-template <int RT>
-static void launch_pass2_rt(copa_plan *p, hipStream_t s) {
-  if (p->p2c) {
-    if (p->l > 0)
-      launch_pass2c<RT, true>(p, p->M, p->FV, s);
-    else
-      launch_pass2c<RT, false>(p, p->M, p->FV, s);
-  } else {
-    dim3 grid((unsigned)((p->n_waves + 3) / 4), (unsigned)p->tiles.nt), block(256);
-    if (p->l > 0)
-      k_pass2<RT, true><<<grid, block, 0, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
-                                              p->col, p->val, p->C, p->M, p->J, p->R, p->l,
-                                              p->FV);
-    else
-      k_pass2<RT, false><<<grid, block, 0, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row,
-                                               p->col, p->val, p->C, p->M, p->J, p->R, p->l,
-                                               p->FV);
-  }
-}
-
-#define RT_SWITCH(rt, FN, ...)                                                               \
-  switch (rt) {                                                                              \
-    case 1: FN<1>(__VA_ARGS__); break;   case 2: FN<2>(__VA_ARGS__); break;                   \
-    case 3: FN<3>(__VA_ARGS__); break;   case 4: FN<4>(__VA_ARGS__); break;                   \
-    case 5: FN<5>(__VA_ARGS__); break;   case 6: FN<6>(__VA_ARGS__); break;                   \
-    case 7: FN<7>(__VA_ARGS__); break;   case 8: FN<8>(__VA_ARGS__); break;                   \
-    case 9: FN<9>(__VA_ARGS__); break;   case 10: FN<10>(__VA_ARGS__); break;                 \
-    case 11: FN<11>(__VA_ARGS__); break; case 12: FN<12>(__VA_ARGS__); break;                 \
-    case 13: FN<13>(__VA_ARGS__); break; case 14: FN<14>(__VA_ARGS__); break;                 \
-    case 15: FN<15>(__VA_ARGS__); break; case 16: FN<16>(__VA_ARGS__); break;                 \
-    default: break;                                                                          \
-  }
 
 const char *const kernel_names[kNumKernels] = {"pass1",  "procrustes", "gram_FH", "mode_H",
                                                "w_admm", "gram_WM",    "pass2",   "v_admm"};
-
-enum { kidPass1, kidProcrustes, kidGramFH, kidModeH, kidWadmm, kidGramWM, kidPass2, kidVadmm };
-
-// Records a HIP event pair around one launch when the plan's timing is on.
-template <typename F>
-static inline void timed(copa_plan *p, hipStream_t s, int kid, F &&launch) {
-  if (p->timing && p->ev_used + 2 <= (int)p->ev_pool.size()) {
-    (void)hipEventRecord(p->ev_pool[p->ev_used], s);
-    launch();
-    (void)hipEventRecord(p->ev_pool[p->ev_used + 1], s);
-    p->ev_kid.push_back(kid);
-    p->ev_used += 2;
-  } else {
-    launch();
-  }
-}
 
 copa_status harvest_timing(copa_plan *p) {
   for (size_t e = 0; e < p->ev_kid.size(); ++e) {
@@ -1559,96 +83,10 @@ copa_status harvest_timing(copa_plan *p) {
   return COPA_OK;
 }
 
-static FitArgs fit_args(const copa_plan *p) {
-  const copa_options &o = p->opt;
-  FitArgs fa;
-  fa.vpart = p->vpart;
-  fa.vtvpart = gram_slot(p, kSlotVtV);
-  fa.nvb = p->n_vblocks;
-  fa.wl1part = p->wpart;
-  fa.nwb = p->n_wblocks;
-  fa.normX2 = p->normX2;
-  fa.J = p->J;
-  fa.proxV = o.prox_V;
-  fa.proxW = o.prox_W;
-  fa.proxH = o.prox_H;
-  fa.lamV = o.lambda_V;
-  fa.lamW = o.lambda_W;
-  fa.lamH = o.lambda_H;
-  return fa;
-}
-
-// One outer iteration; pass 1 advances the device iteration index and the later kernels read it,
-// so the same launches serve every iteration (and one captured graph replays them).
-template <int R>
-static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
-  const copa_options &o = p->opt;
-  const int64_t K = p->K;
-  timed(p, s, kidPass1, [&] { RT_SWITCH(p->tiles.rt, launch_pass1_rt, p, st->V, s); });
-  if (K > 0)
-    timed(p, s, kidProcrustes, [&] {
-      if constexpr (R <= 16) {
-        if (p->l > 0) {
-          if (p->l == 7)
-            k_procrustes_s<R, 7><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
-          else
-            k_procrustes_s<R, kLMax><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
-          return;
-        }
-      }
-      k_procrustes<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-          K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W, o.rank_rtol, p->scal);
-      if (p->n_big > 0)
-        k_procrustes_wave<R><<<(unsigned)p->n_big, 64, 0, s>>>(
-            p->big_list, p->n_big, p->subj, p->T, p->Q, st->H, st->W, o.rank_rtol, p->scal);
-    });
-  timed(p, s, kidGramFH, [&] {
-    // one more block of the same launch takes the FIT of the previous outer iteration
-    const FitArgs fa = fit_args(p);
-    gram_fit<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, kSlotFH, fa, st->H, s);
-  });
-  timed(p, s, kidModeH, [&] {
-    k_mode_H<R><<<1, 256, 0, s>>>(gram_total(p, kSlotFH), p->small, p->modes, p->scal,
-                                  st->H, st->D_H, o.prox_H, o.lambda_H, o.inner_iters);
-  });
-  timed(p, s, kidWadmm, [&] {
-    k_w_admm<R><<<(unsigned)p->n_wblocks, 256, 0, s>>>(K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W,
-                                   st->D_W, p->FW, p->modes, o.prox_W, o.lambda_W,
-                                   o.inner_iters, p->wpart);
-  });
-  timed(p, s, kidGramWM, [&] {
-    gram<R>(p, st->W, st->W, K, nullptr, 0, kSlotWtW, p->M, p->rows_total, kSlotPsi, s);
-  });
-  timed(p, s, kidPass2, [&] { RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s); });
-  timed(p, s, kidVadmm, [&] {
-    k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(
-        p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, row4(p->tiles.rt),
-        gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->scal, o.prox_V,
-        o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV));
-  });
-}
-
-template <int R>
-static void init_grams_r(copa_plan *p, const copa_state *st, hipStream_t s) {
-  constexpr int RR = R * R;
-  k_reset_scalars<<<1, 64, 0, s>>>(p->scal);
-  if (p->Ew && p->K > 0)
-    k_eye8<<<(unsigned)std::min<int64_t>(4096, (p->K * kNMax * kNMax + 255) / 256), 256, 0, s>>>(
-        p->Ew, p->K);
-  if (p->J > 0)
-    k_pad_V<R><<<(unsigned)((p->J * R + 255) / 256), 256, 0, s>>>(
-        st->V, p->Vp, p->J, p->tiles.rt, row4(p->tiles.rt));
-  gram<R>(p, st->W, st->W, p->K, nullptr, 0, kSlotWtW, st->V, p->J, kSlotVtV, s);
-  k_init_small<R><<<1, 256, 0, s>>>(gram_total(p, kSlotWtW), gram_total(p, kSlotVtV), 1,
-                                    p->small);
-}
-
 copa_status launch_iteration(copa_plan *p, const copa_state *st, hipStream_t s) {
   switch (p->R) {
 #define CASE(r) \
-  case r: iteration_r<r>(p, st, s); break;
+  case r: RankOps<r>::iteration(p, st, s); break;
     COPA_R_LIST(CASE)
 #undef CASE
     default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
@@ -1660,7 +98,7 @@ copa_status launch_iteration(copa_plan *p, const copa_state *st, hipStream_t s) 
 copa_status launch_fit(copa_plan *p, const copa_state *st, hipStream_t s) {
   switch (p->R) {
 #define CASE(r) \
-  case r: k_fit<r><<<1, 256, 0, s>>>(fit_args(p), st->H, p->small, p->scal); break;
+  case r: RankOps<r>::fit(p, st, s); break;
     COPA_R_LIST(CASE)
 #undef CASE
     default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
@@ -1672,7 +110,7 @@ copa_status launch_fit(copa_plan *p, const copa_state *st, hipStream_t s) {
 copa_status launch_init_grams(copa_plan *p, const copa_state *st, hipStream_t s) {
   switch (p->R) {
 #define CASE(r) \
-  case r: init_grams_r<r>(p, st, s); break;
+  case r: RankOps<r>::init_grams(p, st, s); break;
     COPA_R_LIST(CASE)
 #undef CASE
     default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
@@ -1683,10 +121,9 @@ copa_status launch_init_grams(copa_plan *p, const copa_state *st, hipStream_t s)
 
 copa_status launch_qtilde(copa_plan *p, float *Qt, hipStream_t s) {
   if (p->S == 0) return COPA_OK;
-  const unsigned nb = (unsigned)((p->S + 255) / 256);
   switch (p->R) {
 #define CASE(r) \
-  case r: k_qtilde<r><<<nb, 256, 0, s>>>(p->S, p->l, p->rowsubj, p->C, p->Q, Qt); break;
+  case r: RankOps<r>::qtilde(p, Qt, s); break;
     COPA_R_LIST(CASE)
 #undef CASE
     default: set_error("unsupported R"); return COPA_EUNSUPPORTED;

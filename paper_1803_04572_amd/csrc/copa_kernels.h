@@ -447,7 +447,7 @@ __global__ void __launch_bounds__(512)
 // each chunk's subjects; otherwise u_i is row i of Mrows (R wide).
 template <int RT, bool SMOOTH>
 inline void launch_pass2c(const copa_plan *p, const float *Mrows, float *F, hipStream_t s) {
-  const dim3 grid((unsigned)std::min(p->nchunks, 2 * std::max(1, p->n_cu)), (unsigned)p->tiles.nt);
+  const dim3 grid((unsigned)std::min(p->nchunks, 2 * std::max(1, p->n_cu)), (unsigned)p->tiles2.nt);
   const size_t lds = ((size_t)p->J * row4(RT) + (size_t)kChunkRows * row4(RT) + 4) * sizeof(float);
   k_pass2c<RT, SMOOTH><<<grid, 512, lds, s>>>(p->nchunks, p->crow, p->cinfo, p->wsplit, p->pkv,
                                              p->rowsubj, p->C, Mrows, p->J, p->R,

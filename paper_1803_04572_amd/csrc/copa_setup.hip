@@ -526,15 +526,26 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
     return hs[a + 1] - hs[a] > hs[b + 1] - hs[b];
   });
-  std::vector<WaveEntry> waves;
-  for (int64_t i = 0; i < K;) {
-    int64_t ik = hs[ord[i] + 1] - hs[ord[i]];
-    int lg = 0;
-    while ((1 << lg) < kWave && (int64_t)(1 << lg) * 4 < ik) ++lg;
-    int cnt = (int)std::min<int64_t>(kWave >> lg, K - i);
-    waves.push_back(WaveEntry{(int32_t)i, lg | (cnt << 8)});
-    i += cnt;
+  // pass-1 tiling first: its lane groups set the lanes a pass-1 wave gives its subjects
+  const int R = p->R;
+  p->tiles = choose_tiles(R, p->J, p->lds_limit);
+  if ((int64_t)p->J * (row4(p->tiles.rt)) * 4 + 16 > p->lds_limit) {
+    set_error("J too large for the LDS-staged factor tile of this build");
+    return COPA_EUNSUPPORTED;
   }
+  auto wave_list = [&](int lanes) {
+    std::vector<WaveEntry> w;
+    for (int64_t i = 0; i < K;) {
+      int64_t ik = hs[ord[i] + 1] - hs[ord[i]];
+      int lg = 0;
+      while ((1 << lg) < lanes && (int64_t)(1 << lg) * 4 < ik) ++lg;
+      int cnt = (int)std::min<int64_t>(lanes >> lg, K - i);
+      w.push_back(WaveEntry{(int32_t)i, lg | (cnt << 8)});
+      i += cnt;
+    }
+    return w;
+  };
+  std::vector<WaveEntry> waves = wave_list(kWave);
   p->n_waves = (int32_t)waves.size();
   COPA_TRY(dalloc(&p->order, K));
   COPA_TRY(dalloc(&p->waves, waves.size()));
@@ -543,6 +554,15 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   if (!waves.empty())
     COPA_HIP(hipMemcpyAsync(p->waves, waves.data(), waves.size() * sizeof(WaveEntry),
                             hipMemcpyHostToDevice, s));
+  {
+    std::vector<WaveEntry> w1 = wave_list(kWave / p->tiles.cg);
+    p->n_waves1 = (int32_t)w1.size();
+    COPA_TRY(dalloc(&p->waves1, w1.size()));
+    if (!w1.empty())
+      COPA_HIP(hipMemcpyAsync(p->waves1, w1.data(), w1.size() * sizeof(WaveEntry),
+                              hipMemcpyHostToDevice, s));
+    COPA_HIP(hipStreamSynchronize(s));  // w1 leaves scope
+  }
 
   COPA_TRY(dalloc(&p->rowsubj, S));
   if (K > 0) {
@@ -572,12 +592,6 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   }
 
   // ---- iteration buffers
-  const int R = p->R;
-  p->tiles = choose_tiles(R, p->J, p->lds_limit);
-  if ((int64_t)p->J * (row4(p->tiles.rt)) * 4 + 16 > p->lds_limit) {
-    set_error("J too large for the LDS-staged factor tile of this build");
-    return COPA_EUNSUPPORTED;
-  }
   COPA_TRY(dalloc(&p->T, p->rows_total * R));
   COPA_TRY(dalloc(&p->Q, p->rows_total * R));
   COPA_TRY(dalloc(&p->M, p->rows_total * R));
@@ -602,9 +616,8 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   COPA_HIP(hipMemsetAsync(p->gcount, 0, 8 * sizeof(int32_t), s));
   // ---- feature-sorted chunks for pass 2 (features < 2^16 and the F_V tile plus one chunk of
   // u rows fit in LDS)
-  p->p2c = p->J <= 65536 && nnz > 0 &&
-           ((int64_t)p->J * row4(p->tiles.rt) + (int64_t)kChunkRows * row4(p->tiles.rt) + 4) * 4 <=
-               p->lds_limit;
+  p->tiles2 = choose_tiles2(R, p->J, p->lds_limit);
+  p->p2c = p->J <= 65536 && nnz > 0 && p->tiles2.nt > 0;
   if (p->p2c) COPA_TRY(build_sorted_chunks(X, p, s));
   COPA_TRY(dalloc(&p->vpart, (size_t)p->n_vblocks * 4));
   {
@@ -634,7 +647,7 @@ static void free_plan(copa_plan *p) {
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-  void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->xc, p->C, p->rk, p->Ew, p->order, p->waves,
+  void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->xc, p->C, p->rk, p->Ew, p->order, p->waves, p->waves1,
                   p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->cptr, p->crow, p->cinfo, p->wsplit, p->pkv, p->Vp,
                   p->gpart, p->gcount,
                   p->vpart, p->wpart, p->small, p->modes, p->scal, p->dloss, p->gradbuf, p->statbuf, p->qtbuf,
