@@ -4,7 +4,13 @@ One step = one outer iteration of Algorithm 1 over the whole cohort (Procrustes,
 MTTKRPs, the three ADMM factor updates and the FIT), launched by copa_fit from libcopa.so.
 Inputs are synthetic EHR-shaped tensors already resident in HBM when the timed region starts.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--steps K] [--warmup W] [--workload c4] [--R R]
+
+The default workload is the largest configuration that fits one GPU (800,000 subjects, 80M
+nonzeros, R = 20). The timed fit starts from the seeded initial point; its FIT history is checked
+against the FP64 oracle's trajectory on the same inputs (tests/golden/fullsize_<workload>_R<R>.json,
+written by the oracle's sharded driver), and `value` is withheld (null) when the final FIT
+differs by more than 1e-5 relative or a factor's congruence is below 0.999.
 
 Prints one JSON line. Per-kernel times come from HIP events recorded by the library on the
 stream its kernels run on (copa_set_timing); `roofline` describes the kernel with the largest
@@ -61,13 +67,18 @@ def measured_traffic(kernel, workload):
 
 def algorithmic_bytes(coh, R, l, compact):
     """Bytes each kernel of one outer iteration must move at least (inputs read once, outputs
-    written once), for FP32 factors. Pass 1 streams the CSR nonzeros (4 B each in the lossless
-    compact form: 16-bit feature id + bfloat16 value; else 8 B) with 4-B row offsets; pass 2 streams
-    the feature-sorted (key, value) pairs (8 B) and one subject id per row; smoothed passes read the
-    l basis coefficients of each row. rows = projected rows (K*l smoothed, S plain)."""
+    written once), for FP32 factors:
+      * X per pass: 4 B per nonzero in pass 1 when the nonzeros are stored in the lossless compact
+        form (16-bit feature id + bfloat16 value), else 8 B; 8 B per nonzero in pass 2 (feature-
+        sorted key and value); 4 B per visit row (row offset, resp. the row's subject);
+      * smoothing per pass: the basis evaluated from each row's visit day (4 B per row) and a
+        per-subject l x l transform (4 l^2 B per subject); the library streams stored FP32 basis
+        rows instead, which moves more than this;
+      * the per-subject row spaces T, Q, M (rows = K l smoothed, S plain; R floats per row),
+        W and V, read and written as each kernel needs them."""
     K, J, S, nnz = coh.K, coh.J, coh.S, coh.nnz
     rows = K * l if l > 0 else S
-    basis = S * l * 4 if l > 0 else 0
+    basis = (S * 4 + K * l * l * 4) if l > 0 else 0
     x1 = nnz * (4 if compact else 8) + (S + 1) * 4 + (K + 1) * 4 + basis
     x2 = nnz * 8 + S * 4 + basis
     return {
@@ -82,30 +93,60 @@ def algorithmic_bytes(coh, R, l, compact):
     }
 
 
-def cpu_baseline(cfg_name, R, l, K_full, n_subjects=10000, iters=10):
+def cpu_baseline(cfg_name, R, l, K_full, n_subjects, iters=3):
     """The FP64 oracle, as it is, on a bounded sample of the same workload: `iters` outer
-    iterations on a cohort of `n_subjects` drawn with the same recipe, scaled by subject count."""
-    try:
-        from threadpoolctl import threadpool_limits
-    except ImportError:  # pragma: no cover
-        threadpool_limits = None
+    iterations on a cohort of `n_subjects` drawn with the same recipe, its subjects split over the
+    host's cores (the oracle's sharded driver, one BLAS thread per worker), scaled by subject
+    count. Only the iterations are timed (not the per-subject setup)."""
     from oracle import copa_oracle as co
+    from oracle import fullsize
     from paper_1803_04572_amd import synth
-    coh, cfg = synth.make_config(cfg_name, K=n_subjects)
-    import contextlib
-    ctx = threadpool_limits(limits=1) if threadpool_limits else contextlib.nullcontext()
-    with ctx:
-        prob = co.build_problem(coh, l)
-        H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
-        opt = co.Options(R=R, outer_iters=iters, inner_iters=cfg["inner"])
-        t0 = time.perf_counter()
-        co.copa_fit(prob, H0, W0, V0, opt)
-        dt = time.perf_counter() - t0
-    per_iter_full = dt / iters * (K_full / n_subjects)
-    return {"value": 1.0 / per_iter_full, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} outer iterations on a {n_subjects}-subject cohort of the same "
-                      f"recipe ({dt:.1f} s), scaled by K={K_full}/{n_subjects}; FP64 NumPy, "
-                      f"one thread"}
+    workers = max(1, min(16, os.cpu_count() or 1))
+    coh, cfg = synth.make_config(cfg_name, K=min(n_subjects, K_full))
+    H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
+    opt = co.Options(R=R, outer_iters=iters, inner_iters=cfg["inner"])
+    marks = []
+    fullsize.copa_fit_sharded(coh, l, H0, W0, V0, opt, workers=workers,
+                              progress=lambda msg: marks.append(time.perf_counter()))
+    dt = marks[-1] - marks[0]  # from "shards ready" to the last iteration
+    per_iter_full = dt / iters * (K_full / coh.K)
+    return {"value": 1.0 / per_iter_full, "unit": "iters/s", "cores": workers, "kind": "oracle",
+            "sample": f"{iters} outer iterations on a {coh.K}-subject cohort of the same recipe "
+                      f"({dt:.1f} s), scaled by K={K_full}/{coh.K}; FP64 NumPy/SciPy, subjects "
+                      f"split over {workers} worker processes with one BLAS thread each"}
+
+
+def golden_check(workload, R, coh, fit_history, H, V, tol):
+    """Compares a fit started from the seeded initial point with the FP64 oracle's trajectory on
+    the same inputs, stored by tests/golden/make_fullsize_golden.py. None when no trajectory is
+    stored for this workload."""
+    path = os.path.join(ROOT, "tests", "golden", f"fullsize_{workload}_R{R}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        g = json.load(fh)
+    if (g["K"], g["J"], g["S"], g["nnz"]) != (coh.K, coh.J, coh.S, coh.nnz):
+        return None
+    n = min(len(fit_history), len(g["fit"]))
+    ref = np.array(g["fit"][:n])
+    got = np.array(fit_history[:n])
+    rel = np.abs(got - ref) / np.abs(ref)
+    out = {"iters_compared": n, "fit_gpu": float(got[-1]), "fit_oracle": float(ref[-1]),
+           "fit_rel": float(rel[-1]), "fit_rel_max_history": float(rel.max()), "tol": tol,
+           "passed": bool(rel[-1] <= tol), "oracle_file": os.path.relpath(path, ROOT)}
+    if n == len(g["fit"]) and H is not None:
+        z = np.load(os.path.join(ROOT, "tests", "golden", f"fullsize_{workload}_R{R}.npz"))
+
+        def cong(A, B):
+            num = np.abs(np.sum(A * B, axis=0))
+            den = np.linalg.norm(A, axis=0) * np.linalg.norm(B, axis=0)
+            c = np.where(den > 0, num / np.where(den > 0, den, 1.0),
+                         np.where((np.linalg.norm(A, axis=0) == 0) & (np.linalg.norm(B, axis=0) == 0), 1.0, 0.0))
+            return float(c.min())
+        out["congruence_H"] = cong(H, z["H"])
+        out["congruence_V"] = cong(V, z["V"])
+        out["passed"] = out["passed"] and min(out["congruence_H"], out["congruence_V"]) >= 0.999
+    return out
 
 
 def main():
@@ -113,7 +154,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--R", type=int, default=None, help="rank (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (HBM counter scaling)")
@@ -135,23 +177,45 @@ def main():
 
     progress(f"generating {args.workload}")
     coh, cfg = synth.make_config(args.workload)
-    R, l = cfg["R"], cfg["l"]
-    progress(f"K={coh.K} S={coh.S} nnz={coh.nnz}; creating the plan")
+    R, l = args.R or cfg["R"], cfg["l"]
+    progress(f"K={coh.K} S={coh.S} nnz={coh.nnz} R={R}; creating the plan")
     plan = copa.Plan.from_cohort(coh, R=R, l=l, inner_iters=cfg["inner"])
     progress("plan ready")
     H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
+    init = plan.new_state(H0, W0, V0)
     state = plan.new_state(H0, W0, V0)
     torch.cuda.synchronize()
 
+    # warm-up (captures the iteration graph for these state buffers), then back to the start
     plan.fit(state, args.warmup, qtilde=False)
+    for k in ("H", "W", "V", "D_H", "D_W", "D_V"):
+        state[k].copy_(init[k])
     torch.cuda.synchronize()
+    progress("timed run")
     t0 = time.perf_counter()
-    rep, _ = plan.fit(state, args.steps, qtilde=False)
+    rep, _ = plan.fit(state, args.steps, qtilde=False, fresh=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = args.steps / dt
 
-    # same number of steps again with HIP events around every kernel launch
+    # validity gate: the timed fit against the FP64 oracle's trajectory from the same start
+    gold_iters = cfg["outer"]
+    if args.steps >= gold_iters:
+        hist = rep["fit_history"]
+        Hf = Vf = None
+        if args.steps == gold_iters:
+            Hf = state["H"].double().cpu().numpy()
+            Vf = state["V"].double().cpu().numpy()
+    else:  # an untimed fit of the full length from the same start
+        chk = plan.new_state(H0, W0, V0)
+        rc, _ = plan.fit(chk, gold_iters, qtilde=False, fresh=True)
+        hist = rc["fit_history"]
+        Hf, Vf = chk["H"].double().cpu().numpy(), chk["V"].double().cpu().numpy()
+        del chk
+    gate = golden_check(args.workload, R, coh, hist, Hf, Vf, tol=1e-5)
+    progress(f"gate: {gate}")
+
+    # the same number of steps again with HIP events around every kernel launch
     plan.set_timing(True)
     t1 = time.perf_counter()
     rep_t, _ = plan.fit(state, args.steps, qtilde=False)
@@ -170,7 +234,7 @@ def main():
             v["GBps"] = abytes[k] / (v["avg_us"] * 1e-6) / 1e9
     dom = max((k for k in per_kernel if k in abytes), key=lambda k: per_kernel[k]["avg_us"])
     ach = per_kernel[dom]["GBps"]
-    traffic = measured_traffic(dom, args.workload)
+    traffic = measured_traffic(dom, args.workload if args.R is None else f"{args.workload}_R{R}")
     if args.copy_probe:
         n = 64 << 20
         a = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
@@ -178,15 +242,21 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+    del plan, state, init
+    torch.cuda.empty_cache()
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, R, l, coh.K)
+    cpu = None
+    if not args.no_cpu_baseline:
+        progress("cpu baseline")
+        cpu = cpu_baseline(args.workload, R, l, coh.K, n_subjects=40_000)
 
     mttkrp = {k: {"GBps": round(per_kernel[k]["GBps"], 1),
                   "frac_hbm": round(per_kernel[k]["GBps"] / HBM_PEAK_GBS, 4)}
               for k in ("pass1", "pass2") if k in per_kernel}
+    passed = gate is not None and gate["passed"]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": value if passed else None,
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -197,12 +267,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {cfg['name']}", "K": coh.K, "J": coh.J,
-                   "R": R, "l": l, "S": coh.S, "nnz": coh.nnz, "inner_iters": cfg["inner"],
+        "config": {"workload": f"{args.workload}: {cfg['name'].replace(' R=' + str(cfg['R']), '')} R={R}",
+                   "K": coh.K, "J": coh.J, "R": R, "l": l, "S": coh.S, "nnz": coh.nnz,
+                   "outer_iters": gold_iters, "inner_iters": cfg["inner"],
                    "constraints": "H free, W nonneg, V l1 (lambda 0.1), cubic spline smoothing",
                    "nonzeros": "compact 4-byte (lossless)" if compact else "fp32 8-byte"},
+        "gate": gate,
+        "value_if_ungated": value,
         "fit": rep["fit"],
-        "fit_after_timed_steps": rep_t["fit"],
         "mttkrp_hbm": mttkrp,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),

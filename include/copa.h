@@ -62,7 +62,12 @@ typedef enum {
  *   row_ptr  [S+1]  nonzero offsets per visit row, row_ptr[0] = 0, row_ptr[S] = nnz
  *   col      [nnz]  feature ids in [0, J), strictly increasing within a row
  *   val      [nnz]  finite values (counts in the paper's use)
- *   days     [S]    visit day of each row (finite), read only when l > 0
+ *   days     [S]    visit day of each row (finite); with l > 0 and basis == NULL the library
+ *                   evaluates the cubic spline basis at these days (Section "Smoothness on U_k":
+ *                   clamped knots, l - 4 equally spaced interior knots on the subject's span)
+ *   basis    [S*l]  optional caller basis, FP64 row-major: row i holds M_k(i, :) of the subject
+ *                   that owns visit row i (for example a basis on knots the caller placed);
+ *                   when given, days is not read. Only span(M_k) enters the fit.
  * Limits: S and nnz below 2^31; J below 2^31.                                              */
 typedef struct copa_tensor {
   int64_t K, J, S, nnz;
@@ -72,7 +77,16 @@ typedef struct copa_tensor {
   const float *val;
   const double *days;
   int32_t l; /* spline basis functions per subject; 0 = no smoothing; this build: 0 or 1..8 */
+  const double *basis;
 } copa_tensor;
+
+/* Arithmetic of the streaming passes (copa_options.precision).
+ *   FP32   every product and sum of the passes in FP32, the Procrustes eigenproblems, Grams and
+ *          ADMM systems in FP64
+ *   MIXED  the factor rows the passes gather (V in pass 1, the u rows in pass 2) stored as
+ *          bfloat16 pairs hi + lo (hi = bf16(x), lo = bf16(x - hi)), FP32 accumulation; the
+ *          products with lo are the FP32 residual refinement of the products with hi           */
+typedef enum { COPA_PREC_FP32 = 0, COPA_PREC_MIXED = 1 } copa_precision;
 
 /* Fit options. R: target rank (this build: 1..64 from the list copa_rank_supported accepts).
  * inner_iters: ADMM steps per factor per outer iteration (>= 1). rank_rtol: Procrustes
@@ -91,16 +105,30 @@ typedef struct copa_options {
    * early once its largest block value is below stop_tol. 0 = fixed iteration count.          */
   double stop_tol;
   int32_t check_every;
+  int32_t precision;     /* copa_precision; 0 = FP32                                          */
+  /* 1: every reduction in a fixed order (no floating-point atomics), so that two runs on the
+   * same inputs give bitwise equal results. Needs the chunked pass 2 (J <= 65536 and a F_V tile
+   * that fits LDS); the plan is refused with COPA_EUNSUPPORTED otherwise.                     */
+  int32_t deterministic;
+  /* 1: the workspace also holds the buffers of copa_loss_grad and copa_stationarity (2 S R +
+   * J R floats and S R floats more). Implied by stop_tol > 0.                                 */
+  int32_t adjoint;
 } copa_options;
 
 /* Fit state, device memory owned by the caller, FP32 row-major. In: the starting point
  * (auxiliary variables Hbar = H, Wbar = W, Vbar = V and duals D_*; D_* = 0 for a fresh start).
  * Out: the state after the last iteration (Algorithm 1 output H = Hbar_1, W = Hbar_2,
- * V = Hbar_3); passing it back continues the fit exactly where it stopped.
- *   H, D_H: R x R;  W, D_W: K x R;  V, D_V: J x R                                           */
+ * V = Hbar_3).
+ *   H, D_H: R x R;  W, D_W: K x R;  V, D_V: J x R
+ * iter (host field): outer iterations this state has been through; 0 marks a fresh start.
+ * copa_fit adds the iterations it ran. When a call continues the state that the plan's previous
+ * copa_fit returned (same buffers, iter unchanged since), it also continues the Procrustes warm
+ * start, so that n + m iterations in two calls give the same numbers as n + m in one call (bitwise
+ * with deterministic = 1). Any other state starts the warm start afresh.                     */
 typedef struct copa_state {
   float *H, *W, *V;
   float *D_H, *D_W, *D_V;
+  int32_t iter;
 } copa_state;
 
 /* Fit report (host memory). fit_history / objective_history are optional host arrays of
@@ -124,21 +152,32 @@ typedef struct copa_report {
 
 typedef struct copa_plan copa_plan;
 
-/* Validates the tensor (shapes on the host, CSR content on the device), packs it into the
- * plan's device memory, builds the per-subject smoothing bases (l > 0) and allocates every
- * buffer the fit needs. Allocates device memory (hipMalloc) and synchronises `stream`; copa_fit
- * allocates nothing (copa_loss_grad allocates its own buffers once, see below). Returns COPA_EINVAL for bad shapes or content,
- * COPA_EUNSUPPORTED for R or l outside this build, COPA_ENOMEM when memory runs out.       */
-copa_status copa_plan_create(const copa_tensor *X, const copa_options *opt, void *stream,
-                             copa_plan **out);
+/* Device memory of a plan: every buffer the plan uses (packed tensor, smoothing basis, iteration
+ * row spaces, pass-2 layout, Gram partials, and with opt->adjoint the adjoint's buffers) lives in
+ * one workspace of *bytes bytes, sized here from the shapes and options alone (a bound where the
+ * layout depends on the data). Reads no device memory.                                       */
+copa_status copa_workspace_bytes(const copa_tensor *X, const copa_options *opt, size_t *bytes);
 
-/* Runs `iters` outer iterations of Algorithm 1 from `state` (updated in place). Qtilde
- * (device, S x R, may be NULL) receives C_k Q_k of the last iteration (Q_k without smoothing),
- * so that U_k = Qtilde_k H. `rep` (host, may be NULL) receives the report. Synchronises
- * `stream` once at the end to read the per-iteration scalars. Returns COPA_ENUMERIC (and sets
- * rep->fail_iter) when a non-finite value or a Cholesky failure occurred; the state then holds
- * the values of the last iteration. iters = 0 is valid and only refreshes Qtilde/rep if any. */
-copa_status copa_fit(copa_plan *plan, const copa_state *state, int32_t iters, float *Qtilde,
+/* Validates the tensor (shapes on the host, CSR content on the device), packs it into the
+ * workspace, builds the per-subject smoothing bases (l > 0) and lays out every buffer the fit
+ * needs. workspace: device memory of at least copa_workspace_bytes bytes, 256-byte aligned,
+ * owned by the caller and not touched by anyone else until copa_plan_destroy; or NULL, and the
+ * library allocates it (one hipMalloc) and frees it in copa_plan_destroy. No later call on the
+ * plan allocates device memory. Synchronises `stream`. Returns COPA_EINVAL for bad shapes or
+ * content or a workspace that is too small or misaligned, COPA_EUNSUPPORTED for R, l or options
+ * outside this build, COPA_ENOMEM when the library's own allocation fails.                   */
+copa_status copa_plan_create(const copa_tensor *X, const copa_options *opt, void *workspace,
+                             size_t workspace_bytes, void *stream, copa_plan **out);
+
+/* Runs `iters` outer iterations of Algorithm 1 from `state` (updated in place, state->iter
+ * advanced). Qtilde (device, S x R, may be NULL) receives C_k Q_k of the last iteration (Q_k
+ * without smoothing), so that U_k = Qtilde_k H. `rep` (host, may be NULL) receives the report.
+ * Synchronises `stream` at the end, and every check_every iterations when stop_tol > 0.
+ * Allocates nothing. Returns COPA_ENUMERIC (and sets rep->fail_iter) when a non-finite value or
+ * a non-positive pivot of an ADMM system occurred; iterations are then run in chunks of up to
+ * 1024 (the whole call when it is shorter), so the state holds the values at the end of the
+ * chunk in which the failure happened. iters = 0 is valid and only refreshes Qtilde/rep.     */
+copa_status copa_fit(copa_plan *plan, copa_state *state, int32_t iters, float *Qtilde,
                      copa_report *rep, void *stream);
 
 /* MTTKRPs of the last completed iteration (Algorithm 1, "F" of each mode): F_H (R x R),
@@ -153,8 +192,8 @@ copa_status copa_plan_basis(copa_plan *plan, float *C, int32_t *rank, void *stre
  *   L = 1/2 sum_k ||X_k - Qtilde_k H S_k V^T||_F^2,  S_k = diag(W(k,:)),
  * and its gradient: dH (R x R), dV (J x R), dW (K x R), optional dS (K x R x R, the full
  * dL/dS_k; may be NULL). Inputs and outputs are device FP32; *loss is written to host memory
- * (the call synchronises `stream`). The first call on a plan allocates its work buffers
- * (2 S R + J R floats), which the plan keeps until copa_plan_destroy.                       */
+ * (the call synchronises `stream`). Needs a plan created with opt->adjoint = 1 (or stop_tol >
+ * 0): COPA_EINVAL otherwise. Allocates nothing.                                              */
 copa_status copa_loss_grad(copa_plan *plan, const float *H, const float *V, const float *W,
                            const float *Qtilde, float *dH, float *dV, float *dW, float *dS,
                            double *loss, void *stream);
@@ -162,10 +201,10 @@ copa_status copa_loss_grad(copa_plan *plan, const float *H, const float *V, cons
 /* Frees every device buffer of the plan (synchronises its device first). NULL is a no-op.   */
 void copa_plan_destroy(copa_plan *plan);
 
-/* copa_fit replays each run of outer iterations from one hipGraph (captured on a stream of the
- * plan on first use and again when the iteration count per call or the state buffers change),
- * which removes the per-kernel launch cost. copa_set_graph(plan, 0) launches the kernels one by
- * one instead (as does per-kernel timing). Default: enabled.                                 */
+/* copa_fit replays each outer iteration from one hipGraph (captured on a stream of the plan on
+ * the first call and again when the state buffers change), which removes the per-kernel launch
+ * cost. copa_set_graph(plan, 0) launches the kernels one by one instead (as does per-kernel
+ * timing). Default: enabled.                                                                 */
 copa_status copa_set_graph(copa_plan *plan, int32_t enable);
 
 /* Stationarity residual of each factor block of the penalised reconstruction loss at (H, V, W)
@@ -174,8 +213,8 @@ copa_status copa_set_graph(copa_plan *plan, int32_t enable);
  * with each block's proximity operator and weight from the plan's options and rho_n =
  * trace(G_n) / R (G_H = W^TW * V^TV, G_W = H^TH * V^TV, G_V = H^TH * W^TW, the steps of
  * Algorithm 1). r_n = 0 exactly at a first-order stationary point of the block. Arguments as
- * for copa_loss_grad (device memory); res: 3 doubles (host) in the order H, W, V. Allocates its
- * buffers on first use and synchronises `stream`. Where Q_k^T Q_k != I (subjects with fewer
+ * for copa_loss_grad (device memory); res: 3 doubles (host) in the order H, W, V. Needs a plan
+ * created with opt->adjoint = 1 (or stop_tol > 0); synchronises `stream`. Where Q_k^T Q_k != I (subjects with fewer
  * rows than R, or a basis of rank below R) the ADMM blocks fit Q_k^T X_k rather than X_k, and
  * the residual of the reconstruction loss need not vanish at the fit's fixed point.          */
 copa_status copa_stationarity(copa_plan *plan, const float *H, const float *V, const float *W,

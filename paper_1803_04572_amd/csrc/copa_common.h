@@ -148,11 +148,24 @@ struct copa_plan {
   int ev_used = 0;
   double t_ms[copa::kNumKernels] = {};
   int64_t t_cnt[copa::kNumKernels] = {};
-  float *gradbuf = nullptr; // [2 x S x R] U and D rows of the adjoint (allocated on first use)
-  float *statbuf = nullptr; // dH, dV, dW and the stationarity partials (allocated on first use)
-  float *qtbuf = nullptr;   // [S x R] Qtilde for the stationarity stop (allocated on first use)
+  bool adjoint = false;      // the workspace holds the adjoint's buffers
+  float *gradbuf = nullptr; // [2 x S x R + J x R] U and D rows and F of the adjoint
+  float *statbuf = nullptr; // dH, dV, dW and the stationarity partials
+  float *qtbuf = nullptr;   // [S x R] Qtilde for the stationarity stop
   size_t statfloats = 0;
   double *lpart = nullptr;  // per-block loss partials of the adjoint
+  // every device buffer above lives in one workspace (the caller's, or one the plan allocated)
+  char *arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
+  bool arena_owned = false;
+  double *tmp = nullptr;     // plan-creation scratch (checks, partial sums)
+  int nchunks_cap = 0;       // bound on the pass-2 chunks the workspace holds
+  int p2_blocks_cap = 0;     // bound on the pass-2 grid width
+  float *fvpart = nullptr;   // deterministic pass 2: each block's F_V tile [p2_blocks_cap x J x R]
+  // Procrustes warm start: the state (buffers and iteration count) the last copa_fit returned
+  copa_state last_state{};
+  bool warm_valid = false;
+  bool reset_warm = true;    // set by copa_fit: start the warm start from the identity
 };
 namespace copa {
 enum { kSlotFH = 0, kSlotWtW = 1, kSlotPsi = 2, kSlotVtV = 3, kSlotG = 4, kSlotG2 = 5 };

@@ -294,17 +294,9 @@ static copa_status loss_grad_r(copa_plan *p, const float *H, const float *V, con
 }
 
 static copa_status ensure_grad_buffers(copa_plan *p) {
-  if (!p->gradbuf) {
-    // first use: U and D rows (2 S R floats), F (J R) and the per-block loss partials
-    const size_t n = std::max<size_t>(1, (size_t)2 * p->S * p->R + (size_t)p->J * p->R);
-    hipError_t e = hipMalloc((void **)&p->gradbuf, n * sizeof(float));
-    if (e == hipSuccess)
-      e = hipMalloc((void **)&p->lpart,
-                    (size_t)2 * std::max(1, (p->n_waves + 3) / 4) * sizeof(double));
-    if (e != hipSuccess) {
-      set_error(std::string("hipMalloc for the gradient buffers: ") + hipGetErrorString(e));
-      return COPA_ENOMEM;
-    }
+  if (!p->adjoint) {
+    set_error("the plan was created without the adjoint's buffers (copa_options.adjoint = 0)");
+    return COPA_EINVAL;
   }
   return COPA_OK;
 }
@@ -420,16 +412,6 @@ copa_status launch_stationarity(copa_plan *p, const float *H, const float *V, co
                                 const float *Qt, double *res_host, hipStream_t s) {
   copa_status cg = ensure_grad_buffers(p);
   if (cg != COPA_OK) return cg;
-  if (!p->statbuf) {
-    p->statfloats = ((size_t)p->R * p->R + (size_t)(p->J + p->K) * p->R + 1) & ~(size_t)1;
-    const size_t bytes = p->statfloats * sizeof(float) + (6 * kStatBlocks + 3) * sizeof(double);
-    hipError_t e = hipMalloc((void **)&p->statbuf, bytes);
-    if (e != hipSuccess) {
-      p->statbuf = nullptr;
-      set_error(std::string("hipMalloc for the stationarity buffers: ") + hipGetErrorString(e));
-      return COPA_ENOMEM;
-    }
-  }
   copa_status cs;
   switch (p->R) {
 #define CASE(r) \

@@ -190,7 +190,7 @@ copa_status copa_set_graph(copa_plan *p, int32_t enable) {
   return COPA_OK;
 }
 
-copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Qtilde,
+copa_status copa_fit(copa_plan *p, copa_state *st, int32_t iters, float *Qtilde,
                      copa_report *rep, void *stream) {
   if (!p || !st || iters < 0) {
     set_error("plan/state is NULL or iters < 0");
@@ -202,6 +202,10 @@ copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Q
   }
   hipStream_t s = (hipStream_t)stream;
   COPA_HIP(hipSetDevice(p->device));
+  // the Procrustes warm start continues only for the state the previous call returned
+  p->reset_warm = !(p->warm_valid && st->iter > 0 && same_state(p->last_state, *st) &&
+                    p->last_state.iter == st->iter);
+  p->warm_valid = false;
   copa_status cs = launch_init_grams(p, st, s);
   if (cs != COPA_OK) return cs;
   std::vector<double> hf, ho;
@@ -236,7 +240,6 @@ copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Q
       break;
     }
     if (check) {
-      if (!p->qtbuf) COPA_HIP(hipMalloc((void **)&p->qtbuf, std::max<size_t>(1, (size_t)p->S * p->R) * sizeof(float)));
       cs = launch_qtilde(p, p->qtbuf, s);
       if (cs != COPA_OK) return cs;
       double r[3];
@@ -251,6 +254,11 @@ copa_status copa_fit(copa_plan *p, const copa_state *st, int32_t iters, float *Q
     if (cs != COPA_OK) return cs;
   }
   COPA_HIP(hipStreamSynchronize(s));
+  st->iter += done;
+  if (fail < 0) {
+    p->last_state = *st;
+    p->warm_valid = true;
+  }
   if (rep) {
     rep->iters_done = done;
     rep->fail_iter = fail;

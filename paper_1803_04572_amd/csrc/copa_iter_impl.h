@@ -1854,7 +1854,7 @@ template <int R>
 static void init_grams_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   constexpr int RR = R * R;
   k_reset_scalars<<<1, 64, 0, s>>>(p->scal);
-  if (p->Ew && p->K > 0)
+  if (p->reset_warm && p->Ew && p->K > 0)
     k_eye8<<<(unsigned)std::min<int64_t>(4096, (p->K * kNMax * kNMax + 255) / 256), 256, 0, s>>>(
         p->Ew, p->K);
   if (p->J > 0)

@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(512)
              const int32_t *__restrict__ wsplit, const uint2 *__restrict__ pkv,
              const int32_t *__restrict__ rowsubj,
              const float *__restrict__ C, const float *__restrict__ M, int64_t J, int R, int l,
-             float *__restrict__ FV) {
+             float *__restrict__ FV, float *__restrict__ part) {
   // F_V tile and u rows with rows padded to RTP floats (16-byte LDS accesses; the pad stays 0)
   constexpr int RTP = row4(RT);
   extern __shared__ float4 smem4[];
@@ -434,6 +434,16 @@ __global__ void __launch_bounds__(512)
     }
   }
   __syncthreads();
+  if (part) {
+    // fixed-order mode: the block's tile goes to its own slice, summed in block order later
+    float *dst = part + (int64_t)blockIdx.x * J * R;
+    for (int64_t e = t; e < J * RTP; e += nt) {
+      const int64_t j = e / RTP;
+      const int r = (int)(e - j * RTP);
+      if (r < RT && c0 + r < R) dst[j * R + c0 + r] = sF[e];
+    }
+    return;
+  }
   for (int64_t e = t; e < J * RTP; e += nt) {
     const int64_t j = e / RTP;
     const int r = (int)(e - j * RTP);
@@ -442,16 +452,36 @@ __global__ void __launch_bounds__(512)
   }
 }
 
+// F[e] += sum over blocks b = 0, 1, ... of part[b][e], in that order (fixed-order mode).
+static __global__ void __launch_bounds__(256)
+    k_fv_sum(const float *__restrict__ part, int nb, int64_t n, float *__restrict__ F) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    float acc = F[e];
+    for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * n + e];
+    F[e] = acc;
+  }
+}
+
 // Unchunked fallback (features >= 2^16): global atomics per nonzero.
 // Launches k_pass2c on the plan's chunks: SMOOTH forms u rows from the basis and the M rows of
 // each chunk's subjects; otherwise u_i is row i of Mrows (R wide).
+// In fixed-order mode (deterministic) every block writes its F_V tile to its slice of fvpart and
+// one more launch adds the slices to F in block order.
 template <int RT, bool SMOOTH>
 inline void launch_pass2c(const copa_plan *p, const float *Mrows, float *F, hipStream_t s) {
-  const dim3 grid((unsigned)std::min(p->nchunks, 2 * std::max(1, p->n_cu)), (unsigned)p->tiles2.nt);
+  const int gx = std::min(p->nchunks, p->p2_blocks_cap);
+  const dim3 grid((unsigned)gx, (unsigned)p->tiles2.nt);
   const size_t lds = ((size_t)p->J * row4(RT) + (size_t)kChunkRows * row4(RT) + 4) * sizeof(float);
+  float *part = p->opt.deterministic ? p->fvpart : nullptr;
   k_pass2c<RT, SMOOTH><<<grid, 512, lds, s>>>(p->nchunks, p->crow, p->cinfo, p->wsplit, p->pkv,
                                              p->rowsubj, p->C, Mrows, p->J, p->R,
-                                             SMOOTH ? p->l : 0, F);
+                                             SMOOTH ? p->l : 0, F, part);
+  if (part) {
+    const int64_t n = p->J * p->R;
+    k_fv_sum<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256)), 256, 0,
+               s>>>(part, gx, n, F);
+  }
 }
 
 template <int RT, bool SMOOTH>

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <numeric>
 #include <thread>
+#include <type_traits>
 
 #include "copa_common.h"
 
@@ -15,7 +16,8 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 
 // ------------------------------------------------------------------------------------ checks
 enum : int32_t {
-  kBadSubjPtr = 1, kBadRowPtr = 2, kBadCol = 4, kUnsortedCol = 8, kBadVal = 16, kBadDays = 32
+  kBadSubjPtr = 1, kBadRowPtr = 2, kBadCol = 4, kUnsortedCol = 8, kBadVal = 16, kBadDays = 32,
+  kBadBasis = 64
 };
 
 __global__ void k_check_offsets(const int64_t *subj_ptr, const int64_t *row_ptr, int64_t K,
@@ -33,10 +35,11 @@ __global__ void k_check_offsets(const int64_t *subj_ptr, const int64_t *row_ptr,
   }
 }
 
-// Thread per visit row: columns in range and strictly increasing, values finite, days finite.
-// Only launched once the offsets are known to be monotone and in range.
+// Thread per visit row: columns in range and strictly increasing, values finite, days (or the
+// caller's basis row) finite. Only launched once the offsets are known to be monotone and in range.
 __global__ void k_check_rows(const int64_t *row_ptr, const int32_t *col, const float *val,
-                             const double *days, int64_t S, int64_t J, int32_t *flags) {
+                             const double *days, const double *basis, int l, int64_t S, int64_t J,
+                             int32_t *flags) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S) return;
   int64_t a = row_ptr[i], b = row_ptr[i + 1];
@@ -50,6 +53,9 @@ __global__ void k_check_rows(const int64_t *row_ptr, const int32_t *col, const f
     if (!isfinite(val[e])) f |= kBadVal;
   }
   if (days && !isfinite(days[i])) f |= kBadDays;
+  if (basis)
+    for (int a = 0; a < l; ++a)
+      if (!isfinite(basis[i * l + a])) f |= kBadBasis;
   if (f) atomicOr(flags, f);
 }
 
@@ -134,8 +140,9 @@ __device__ __forceinline__ void spline_row(double t, const double (&beta)[L + 4]
 // the singular values, keeps sigma > rtol * sigma_1 and writes C_k = M_k V_r Sigma_r^{-1}, an
 // orthonormal basis of span(M_k), as FP32 rows of width kLMax.
 template <int L>
-__global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double *days, float *C,
-                                              int32_t *rk, int64_t K, double rtol) {
+__global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double *days,
+                                              const double *basis, float *C, int32_t *rk,
+                                              int64_t K, double rtol) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   const int r0 = subj[k], r1 = subj[k + 1];
@@ -143,6 +150,17 @@ __global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double 
     rk[k] = 0;
     return;
   }
+  // row i of M_k: the caller's basis row, or the spline basis evaluated at the visit day
+  double beta[L + 4];
+  auto basis_row = [&](int i, double (&m)[L]) {
+    if (basis) {
+#pragma unroll
+      for (int a = 0; a < L; ++a) m[a] = basis[(int64_t)i * L + a];
+    } else {
+      spline_row<L>(days[i], beta, m);
+    }
+  };
+  if (!basis) {
   double t1 = days[r0], tn = days[r0];
   for (int i = r0 + 1; i < r1; ++i) {
     t1 = fmin(t1, days[i]);
@@ -159,13 +177,13 @@ __global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double 
   }
   constexpr int d = L - 1 < 3 ? L - 1 : 3;
   constexpr int ninner = L - d - 1;
-  double beta[L + 4];
 #pragma unroll
   for (int i = 0; i < L + 4; ++i) beta[i] = tn;
 #pragma unroll
   for (int i = 0; i <= d; ++i) beta[i] = t1;
 #pragma unroll
   for (int j = 1; j <= ninner; ++j) beta[d + j] = t1 + (tn - t1) * j / (ninner + 1);
+  }
 
   double R[L][L];
 #pragma unroll
@@ -174,7 +192,7 @@ __global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double 
     for (int b = 0; b < L; ++b) R[a][b] = 0.0;
   for (int i = r0; i < r1; ++i) {
     double m[L];
-    spline_row<L>(days[i], beta, m);
+    basis_row(i, m);
 #pragma unroll
     for (int j = 0; j < L; ++j) {
       if (m[j] != 0.0) {
@@ -264,7 +282,7 @@ __global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double 
   }
   for (int i = r0; i < r1; ++i) {
     double m[L];
-    spline_row<L>(days[i], beta, m);
+    basis_row(i, m);
 #pragma unroll
     for (int j = 0; j < kLMax; ++j) {
       double c = 0.0;
@@ -278,12 +296,13 @@ __global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double 
   rk[k] = r;
 }
 
-static copa_status launch_basis(int l, const int32_t *subj, const double *days, float *C,
-                                int32_t *rk, int64_t K, double rtol, hipStream_t s) {
+static copa_status launch_basis(int l, const int32_t *subj, const double *days,
+                                const double *basis, float *C, int32_t *rk, int64_t K,
+                                double rtol, hipStream_t s) {
   dim3 g((unsigned)((K + 63) / 64)), b(64);
   switch (l) {
 #define CASE(Lv) \
-  case Lv: k_basis<Lv><<<g, b, 0, s>>>(subj, days, C, rk, K, rtol); break;
+  case Lv: k_basis<Lv><<<g, b, 0, s>>>(subj, days, basis, C, rk, K, rtol); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: set_error("l outside 0..8"); return COPA_EUNSUPPORTED;
@@ -298,16 +317,138 @@ static copa_status launch_basis(int l, const int32_t *subj, const double *days, 
     if (st_ != COPA_OK) return st_;   \
   } while (0)
 
+// Every device buffer of a plan is carved, 256-byte aligned, from one workspace.
 template <typename T>
-static copa_status dalloc(T **ptr, size_t count) {
+static copa_status dalloc(copa_plan *p, T **ptr, size_t count) {
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void **)ptr, count * sizeof(T));
-  if (e != hipSuccess) {
+  const size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+  if (p->arena_used + bytes > p->arena_bytes) {
     *ptr = nullptr;
-    set_error(std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes: " +
-              hipGetErrorString(e));
-    return COPA_ENOMEM;
+    set_error("workspace layout exceeds its computed size (internal error)");
+    return COPA_EDEVICE;
   }
+  *ptr = reinterpret_cast<T *>(p->arena + p->arena_used);
+  p->arena_used += bytes;
+  return COPA_OK;
+}
+
+// Sizes of a plan that follow from the shapes and options alone (host only).
+static copa_status plan_dims(const copa_tensor *X, const copa_options *opt, copa_plan *p) {
+  p->K = X->K;
+  p->J = X->J;
+  p->S = X->S;
+  p->nnz = X->nnz;
+  p->l = X->l;
+  p->R = opt->R;
+  p->opt = *opt;
+  if (p->opt.rank_rtol <= 0.0) p->opt.rank_rtol = 1e-6;
+  if (p->opt.basis_rtol <= 0.0) p->opt.basis_rtol = 1e-10;
+  p->adjoint = opt->adjoint != 0 || opt->stop_tol > 0.0;
+  COPA_HIP(hipGetDevice(&p->device));
+  int lds = 0;
+  COPA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+  p->lds_limit = lds;  // 160 KB per workgroup on gfx950
+  COPA_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
+  const int R = p->R;
+  const int64_t K = p->K;
+  p->tiles = choose_tiles(R, p->J, p->lds_limit);
+  if ((int64_t)p->J * (row4(p->tiles.rt)) * 4 + 16 > p->lds_limit) {
+    set_error("J too large for the LDS-staged factor tile of this build");
+    return COPA_EUNSUPPORTED;
+  }
+  p->tiles2 = choose_tiles2(R, p->J, p->lds_limit);
+  p->p2c = p->J <= 65536 && p->nnz > 0 && p->tiles2.nt > 0;
+  if (p->opt.deterministic && !p->p2c && p->nnz > 0) {
+    set_error("deterministic mode needs the chunked pass 2 (J <= 65536 and an F_V tile that "
+              "fits LDS)");
+    return COPA_EUNSUPPORTED;
+  }
+  p->slot_rows = p->l > 0 ? p->l : 0;
+  p->rows_total = p->l > 0 ? K * p->l : p->S;
+  p->gmaxnb = 2 * std::max(1, p->n_cu);
+  {
+    // V update: 4 wavefronts per block, 64 / R rows per wavefront (R lanes per row)
+    const int64_t rb = 4 * (kWave / R);
+    p->n_vblocks =
+        (int)std::max<int64_t>(1, std::min<int64_t>((p->J + rb - 1) / rb, 4 * std::max(1, p->n_cu)));
+  }
+  p->gcap = std::max(p->gmaxnb, p->n_vblocks);
+  p->gstride = ((int64_t)p->gcap + 1) * R * R;
+  {
+    const int64_t per_block = 4 * (kWave / R);
+    p->n_wblocks = (int)std::max<int64_t>(1, (K + per_block - 1) / per_block);
+  }
+  // pass-2 chunks: at most kChunkRows rows and kChunkRows / l subjects each
+  const int64_t msub = p->l > 0 ? kChunkRows / p->l : INT64_MAX;
+  p->nchunks_cap = (int)std::min<int64_t>(INT32_MAX - 1, (p->S + kChunkRows - 1) / kChunkRows +
+                                                          (p->l > 0 ? K / msub : 0) + 1);
+  p->p2_blocks_cap = 2 * std::max(1, p->n_cu);
+  return COPA_OK;
+}
+
+// Carves every buffer of the plan in a fixed order, with bounds for the counts that depend on
+// the data (wave lists, chunks, large eigenproblems). Run on an empty arena of size 0 it only
+// adds up the bytes (the arena pointer stays null and nothing is written).
+static copa_status carve_all(copa_plan *p, bool dry) {
+  const int64_t K = p->K, S = p->S, nnz = p->nnz, J = p->J;
+  const int R = p->R;
+  size_t total = 0;
+  auto take = [&](auto **ptr, size_t count) -> copa_status {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(*ptr)>>;
+    if (count == 0) count = 1;
+    const size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    total += bytes;
+    if (dry) return COPA_OK;
+    return dalloc(p, ptr, count);
+  };
+  COPA_TRY(take(&p->tmp, 1024));
+  COPA_TRY(take(&p->subj, K + 1));
+  COPA_TRY(take(&p->row, S + 1));
+  COPA_TRY(take(&p->col, nnz));
+  COPA_TRY(take(&p->val, nnz));
+  COPA_TRY(take(&p->xc, p->J <= 65536 ? nnz : 0));
+  COPA_TRY(take(&p->order, K));
+  COPA_TRY(take(&p->waves, K));
+  COPA_TRY(take(&p->waves1, K));
+  COPA_TRY(take(&p->rowsubj, S));
+  if (p->l > 0) {
+    COPA_TRY(take(&p->C, S * kLMax));
+    COPA_TRY(take(&p->rk, K));
+    COPA_TRY(take(&p->Ew, (size_t)K * kNMax * kNMax));
+  } else {
+    COPA_TRY(take(&p->big_list, K));
+  }
+  COPA_TRY(take(&p->T, p->rows_total * R));
+  COPA_TRY(take(&p->Q, p->rows_total * R));
+  COPA_TRY(take(&p->M, p->rows_total * R));
+  COPA_TRY(take(&p->FW, K * R));
+  COPA_TRY(take(&p->FV, J * R));
+  COPA_TRY(take(&p->Vp, (size_t)p->tiles.nt * J * row4(p->tiles.rt)));
+  COPA_TRY(take(&p->gpart, (size_t)kGramSlots * p->gstride));
+  COPA_TRY(take(&p->gcount, 8));
+  if (p->p2c) {
+    const size_t nch = (size_t)p->nchunks_cap;
+    COPA_TRY(take(&p->wsplit, nch * 9));
+    COPA_TRY(take(&p->cptr, nch + 1));
+    COPA_TRY(take(&p->crow, nch + 1));
+    COPA_TRY(take(&p->cinfo, 2 * nch));
+    COPA_TRY(take(&p->pkv, nnz));
+    if (p->opt.deterministic) COPA_TRY(take(&p->fvpart, (size_t)p->p2_blocks_cap * J * R));
+  }
+  COPA_TRY(take(&p->vpart, (size_t)p->n_vblocks * 4));
+  COPA_TRY(take(&p->wpart, (size_t)p->n_wblocks));
+  COPA_TRY(take(&p->small, 8 * R * R));
+  COPA_TRY(take(&p->modes, 3));
+  COPA_TRY(take(&p->scal, 1));
+  COPA_TRY(take(&p->dloss, 64));
+  if (p->adjoint) {
+    COPA_TRY(take(&p->gradbuf, (size_t)2 * S * R + (size_t)J * R));
+    COPA_TRY(take(&p->lpart, (size_t)2 * ((K + 3) / 4 + 1)));
+    p->statfloats = ((size_t)R * R + (size_t)(J + K) * R + 1) & ~(size_t)1;
+    COPA_TRY(take(&p->statbuf, p->statfloats + 2 * (6 * kStatBlocks + 3)));
+    COPA_TRY(take(&p->qtbuf, (size_t)S * R));
+  }
+  if (dry) p->arena_bytes = total;
   return COPA_OK;
 }
 
@@ -390,15 +531,14 @@ static copa_status build_sorted_chunks(const copa_tensor *X, copa_plan *p, hipSt
     }
     ws[c * 9 + 8] = e1;
   }
+  if (nch > p->nchunks_cap) {
+    set_error("pass-2 chunk count above its bound (internal error)");
+    return COPA_EDEVICE;
+  }
   p->nchunks = nch;
-  COPA_TRY(dalloc(&p->wsplit, (size_t)nch * 9));
   COPA_HIP(hipMemcpyAsync(p->wsplit, ws.data(), ws.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  COPA_TRY(dalloc(&p->cptr, nch + 1));
-  COPA_TRY(dalloc(&p->crow, nch + 1));
-  COPA_TRY(dalloc(&p->cinfo, (size_t)2 * nch));
   COPA_HIP(hipMemcpyAsync(p->crow, crow.data(), (nch + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
   COPA_HIP(hipMemcpyAsync(p->cinfo, cinf.data(), 2 * nch * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  COPA_TRY(dalloc(&p->pkv, nnz));
   COPA_HIP(hipMemcpyAsync(p->cptr, cp.data(), (nch + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
   {
     std::vector<uint2> kv(nnz);
@@ -414,26 +554,40 @@ static copa_status build_sorted_chunks(const copa_tensor *X, copa_plan *p, hipSt
   return COPA_OK;
 }
 
-static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hipStream_t s,
-                              copa_plan *p) {
-  p->K = X->K;
-  p->J = X->J;
-  p->S = X->S;
-  p->nnz = X->nnz;
-  p->l = X->l;
-  p->R = opt->R;
-  p->opt = *opt;
-  if (p->opt.rank_rtol <= 0.0) p->opt.rank_rtol = 1e-6;
-  if (p->opt.basis_rtol <= 0.0) p->opt.basis_rtol = 1e-10;
-  COPA_HIP(hipGetDevice(&p->device));
-  int lds = 0;
-  COPA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
-  p->lds_limit = lds;  // 160 KB per workgroup on gfx950
+static copa_status build_plan(const copa_tensor *X, const copa_options *opt, void *workspace,
+                              size_t ws_bytes, hipStream_t s, copa_plan *p) {
+  COPA_TRY(plan_dims(X, opt, p));
+  COPA_TRY(carve_all(p, true));
+  const size_t need = p->arena_bytes;
+  if (workspace) {
+    if (ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0) {
+      set_error("workspace of " + std::to_string(ws_bytes) + " bytes at a " +
+                (((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) ? "misaligned"
+                                                                         : "256-byte aligned") +
+                " address; the plan needs " + std::to_string(need) + " bytes, 256-byte aligned");
+      return COPA_EINVAL;
+    }
+    p->arena = static_cast<char *>(workspace);
+    p->arena_owned = false;
+  } else {
+    hipError_t e = hipMalloc((void **)&p->arena, need);
+    if (e != hipSuccess) {
+      p->arena = nullptr;
+      set_error("hipMalloc of the " + std::to_string(need) + "-byte workspace: " +
+                hipGetErrorString(e));
+      return COPA_ENOMEM;
+    }
+    p->arena_owned = true;
+  }
+  p->arena_bytes = need;
+  p->arena_used = 0;
+  COPA_TRY(carve_all(p, false));
 
   const int64_t K = p->K, S = p->S, nnz = p->nnz;
+  const int R = p->R;
+  const bool caller_basis = p->l > 0 && X->basis != nullptr;
   // ---- content checks on the device
-  int32_t *flags = nullptr;
-  COPA_TRY(dalloc(&flags, 1));
+  int32_t *flags = reinterpret_cast<int32_t *>(p->tmp);
   COPA_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), s));
   {
     int64_t n = std::max(K, S) + 1;
@@ -445,14 +599,13 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   COPA_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   COPA_HIP(hipStreamSynchronize(s));
   if (hflags == 0 && S > 0) {
-    k_check_rows<<<(unsigned)((S + 255) / 256), 256, 0, s>>>(X->row_ptr, X->col, X->val,
-                                                              p->l > 0 ? X->days : nullptr, S,
-                                                              p->J, flags);
+    k_check_rows<<<(unsigned)((S + 255) / 256), 256, 0, s>>>(
+        X->row_ptr, X->col, X->val, p->l > 0 && !caller_basis ? X->days : nullptr,
+        caller_basis ? X->basis : nullptr, p->l, S, p->J, flags);
     COPA_HIP(hipGetLastError());
     COPA_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     COPA_HIP(hipStreamSynchronize(s));
   }
-  (void)hipFree(flags);
   if (hflags) {
     std::string m = "invalid tensor:";
     if (hflags & kBadSubjPtr) m += " subj_ptr not 0..S non-decreasing;";
@@ -461,15 +614,12 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
     if (hflags & kUnsortedCol) m += " columns not strictly increasing within a row;";
     if (hflags & kBadVal) m += " non-finite value;";
     if (hflags & kBadDays) m += " non-finite visit day;";
+    if (hflags & kBadBasis) m += " non-finite basis value;";
     set_error(m);
     return COPA_EINVAL;
   }
 
   // ---- packing
-  COPA_TRY(dalloc(&p->subj, K + 1));
-  COPA_TRY(dalloc(&p->row, S + 1));
-  COPA_TRY(dalloc(&p->col, nnz));
-  COPA_TRY(dalloc(&p->val, nnz));
   k_pack_offsets<<<(unsigned)((K + 1 + 255) / 256), 256, 0, s>>>(X->subj_ptr, p->subj, K + 1);
   k_pack_offsets<<<(unsigned)((S + 1 + 255) / 256), 256, 0, s>>>(X->row_ptr, p->row, S + 1);
   COPA_HIP(hipGetLastError());
@@ -483,14 +633,12 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   }
   {
     constexpr int nb = 512;
-    double *part = nullptr;
-    COPA_TRY(dalloc(&part, nb));
+    double *part = p->tmp + 8;
     k_sumsq<<<nb, 256, 0, s>>>(p->val, nnz, part);
     COPA_HIP(hipGetLastError());
     std::vector<double> h(nb);
     COPA_HIP(hipMemcpyAsync(h.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, s));
     COPA_HIP(hipStreamSynchronize(s));
-    (void)hipFree(part);
     p->normX2 = 0.0;
     for (double v : h) p->normX2 += v;
   }
@@ -498,24 +646,21 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   // a bfloat16 (count data); half the bytes and one load per nonzero
   p->compact = false;
   if (nnz > 0 && p->J <= 65536) {
-    int *flag = nullptr;
-    COPA_TRY(dalloc(&flag, 1));
+    int *flag = reinterpret_cast<int *>(p->tmp + 4);
     COPA_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
     k_check_bf16<<<1024, 256, 0, s>>>(p->val, nnz, flag);
     COPA_HIP(hipGetLastError());
     int hf = 1;
     COPA_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     COPA_HIP(hipStreamSynchronize(s));
-    (void)hipFree(flag);
     if (hf == 0) {
-      COPA_TRY(dalloc(&p->xc, nnz));
       k_pack_compact<<<2048, 256, 0, s>>>(p->col, p->val, nnz, p->xc);
       COPA_HIP(hipGetLastError());
       p->compact = true;
     }
   }
 
-  // ---- subject order and wave work list (host): subjects by decreasing visit count; a wave
+  // ---- subject order and wave work lists (host): subjects by decreasing visit count; a wave
   // gives G = 2^lg lanes to each subject with G ~ I_max / 4 rows per lane
   std::vector<int64_t> hs(K + 1);
   COPA_HIP(hipMemcpyAsync(hs.data(), X->subj_ptr, (K + 1) * sizeof(int64_t),
@@ -526,13 +671,6 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
   std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
     return hs[a + 1] - hs[a] > hs[b + 1] - hs[b];
   });
-  // pass-1 tiling first: its lane groups set the lanes a pass-1 wave gives its subjects
-  const int R = p->R;
-  p->tiles = choose_tiles(R, p->J, p->lds_limit);
-  if ((int64_t)p->J * (row4(p->tiles.rt)) * 4 + 16 > p->lds_limit) {
-    set_error("J too large for the LDS-staged factor tile of this build");
-    return COPA_EUNSUPPORTED;
-  }
   auto wave_list = [&](int lanes) {
     std::vector<WaveEntry> w;
     for (int64_t i = 0; i < K;) {
@@ -545,90 +683,44 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, hip
     }
     return w;
   };
-  std::vector<WaveEntry> waves = wave_list(kWave);
+  const std::vector<WaveEntry> waves = wave_list(kWave);
+  const std::vector<WaveEntry> waves1 = wave_list(kWave / p->tiles.cg);
   p->n_waves = (int32_t)waves.size();
-  COPA_TRY(dalloc(&p->order, K));
-  COPA_TRY(dalloc(&p->waves, waves.size()));
-  if (K > 0)
+  p->n_waves1 = (int32_t)waves1.size();
+  if (K > 0) {
     COPA_HIP(hipMemcpyAsync(p->order, ord.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  if (!waves.empty())
     COPA_HIP(hipMemcpyAsync(p->waves, waves.data(), waves.size() * sizeof(WaveEntry),
                             hipMemcpyHostToDevice, s));
-  {
-    std::vector<WaveEntry> w1 = wave_list(kWave / p->tiles.cg);
-    p->n_waves1 = (int32_t)w1.size();
-    COPA_TRY(dalloc(&p->waves1, w1.size()));
-    if (!w1.empty())
-      COPA_HIP(hipMemcpyAsync(p->waves1, w1.data(), w1.size() * sizeof(WaveEntry),
-                              hipMemcpyHostToDevice, s));
-    COPA_HIP(hipStreamSynchronize(s));  // w1 leaves scope
+    COPA_HIP(hipMemcpyAsync(p->waves1, waves1.data(), waves1.size() * sizeof(WaveEntry),
+                            hipMemcpyHostToDevice, s));
   }
-
-  COPA_TRY(dalloc(&p->rowsubj, S));
   if (K > 0) {
     k_row_subject<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(p->subj, p->rowsubj, K);
     COPA_HIP(hipGetLastError());
   }
   // ---- smoothing basis
+  std::vector<int32_t> big;
   if (p->l > 0) {
-    p->slot_rows = p->l;
-    p->rows_total = K * p->l;
-    COPA_TRY(dalloc(&p->C, S * kLMax));
-    COPA_TRY(dalloc(&p->rk, K));
-    COPA_TRY(dalloc(&p->Ew, (size_t)K * kNMax * kNMax));
-    if (K > 0) COPA_TRY(launch_basis(p->l, p->subj, X->days, p->C, p->rk, K, p->opt.basis_rtol, s));
+    if (K > 0)
+      COPA_TRY(launch_basis(p->l, p->subj, caller_basis ? nullptr : X->days,
+                            caller_basis ? X->basis : nullptr, p->C, p->rk, K,
+                            p->opt.basis_rtol, s));
   } else {
-    p->slot_rows = 0;
-    p->rows_total = S;
     // subjects whose eigenproblem min(I_k, R) is larger than a lane can hold
-    std::vector<int32_t> big;
     for (int64_t k = 0; k < K; ++k)
       if (std::min<int64_t>(hs[k + 1] - hs[k], p->R) > kNMax) big.push_back((int32_t)k);
     p->n_big = (int32_t)big.size();
-    COPA_TRY(dalloc(&p->big_list, big.size()));
     if (!big.empty())
       COPA_HIP(hipMemcpyAsync(p->big_list, big.data(), big.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, s));
   }
-
-  // ---- iteration buffers
-  COPA_TRY(dalloc(&p->T, p->rows_total * R));
-  COPA_TRY(dalloc(&p->Q, p->rows_total * R));
-  COPA_TRY(dalloc(&p->M, p->rows_total * R));
-  COPA_TRY(dalloc(&p->FW, K * R));
-  COPA_TRY(dalloc(&p->FV, p->J * R));
   {
     const int rtp = row4(p->tiles.rt);
-    COPA_TRY(dalloc(&p->Vp, (size_t)p->tiles.nt * p->J * rtp));
     COPA_HIP(hipMemsetAsync(p->Vp, 0, (size_t)p->tiles.nt * p->J * rtp * sizeof(float), s));
   }
-  COPA_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
-  p->gmaxnb = 2 * std::max(1, p->n_cu);
-  {
-    // V update: 4 wavefronts per block, 64 / R rows per wavefront (R lanes per row)
-    const int64_t rb = 4 * (kWave / R);
-    p->n_vblocks = (int)std::max<int64_t>(1, std::min<int64_t>((p->J + rb - 1) / rb, 4 * std::max(1, p->n_cu)));
-  }
-  p->gcap = std::max(p->gmaxnb, p->n_vblocks);
-  p->gstride = ((int64_t)p->gcap + 1) * R * R;
-  COPA_TRY(dalloc(&p->gpart, (size_t)kGramSlots * p->gstride));
-  COPA_TRY(dalloc(&p->gcount, 8));
   COPA_HIP(hipMemsetAsync(p->gcount, 0, 8 * sizeof(int32_t), s));
-  // ---- feature-sorted chunks for pass 2 (features < 2^16 and the F_V tile plus one chunk of
-  // u rows fit in LDS)
-  p->tiles2 = choose_tiles2(R, p->J, p->lds_limit);
-  p->p2c = p->J <= 65536 && nnz > 0 && p->tiles2.nt > 0;
+  // ---- feature-sorted chunks for pass 2
   if (p->p2c) COPA_TRY(build_sorted_chunks(X, p, s));
-  COPA_TRY(dalloc(&p->vpart, (size_t)p->n_vblocks * 4));
-  {
-    const int64_t per_block = 4 * (kWave / R);
-    p->n_wblocks = (int)std::max<int64_t>(1, (K + per_block - 1) / per_block);
-  }
-  COPA_TRY(dalloc(&p->wpart, (size_t)p->n_wblocks));
-  COPA_TRY(dalloc(&p->small, 8 * R * R));
-  COPA_TRY(dalloc(&p->modes, 3));
-  COPA_TRY(dalloc(&p->scal, 1));
-  COPA_TRY(dalloc(&p->dloss, 64));
   COPA_HIP(hipMemsetAsync(p->T, 0, p->rows_total * R * sizeof(float), s));
   COPA_HIP(hipMemsetAsync(p->Q, 0, p->rows_total * R * sizeof(float), s));
   COPA_HIP(hipMemsetAsync(p->M, 0, p->rows_total * R * sizeof(float), s));
@@ -647,13 +739,7 @@ static void free_plan(copa_plan *p) {
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-  void *bufs[] = {p->subj, p->row, p->col, p->val, p->rowsubj, p->xc, p->C, p->rk, p->Ew, p->order, p->waves, p->waves1,
-                  p->big_list, p->T, p->Q, p->M, p->FW, p->FV, p->cptr, p->crow, p->cinfo, p->wsplit, p->pkv, p->Vp,
-                  p->gpart, p->gcount,
-                  p->vpart, p->wpart, p->small, p->modes, p->scal, p->dloss, p->gradbuf, p->statbuf, p->qtbuf,
-                  p->lpart};
-  for (void *b : bufs)
-    if (b) (void)hipFree(b);
+  if (p->arena_owned && p->arena) (void)hipFree(p->arena);
   delete p;
 }
 
@@ -675,13 +761,8 @@ const char *copa_status_string(copa_status st) {
 
 int32_t copa_rank_supported(int32_t R) { return rank_supported(R) ? 1 : 0; }
 
-copa_status copa_plan_create(const copa_tensor *X, const copa_options *opt, void *stream,
-                             copa_plan **out) {
-  if (!out) {
-    set_error("out is NULL");
-    return COPA_EINVAL;
-  }
-  *out = nullptr;
+// Host-side checks of the shapes and options shared by the size query and plan creation.
+static copa_status check_args(const copa_tensor *X, const copa_options *opt, bool arrays) {
   if (!X || !opt) {
     set_error("tensor or options is NULL");
     return COPA_EINVAL;
@@ -691,7 +772,7 @@ copa_status copa_plan_create(const copa_tensor *X, const copa_options *opt, void
     set_error("sizes must satisfy K >= 0, J >= 1, S >= 0, nnz >= 0, all below 2^31");
     return COPA_EINVAL;
   }
-  if (!X->subj_ptr || !X->row_ptr || (X->nnz > 0 && (!X->col || !X->val))) {
+  if (arrays && (!X->subj_ptr || !X->row_ptr || (X->nnz > 0 && (!X->col || !X->val)))) {
     set_error("tensor array is NULL");
     return COPA_EINVAL;
   }
@@ -703,8 +784,8 @@ copa_status copa_plan_create(const copa_tensor *X, const copa_options *opt, void
     set_error("l > 8 spline basis functions is not supported by this build");
     return COPA_EUNSUPPORTED;
   }
-  if (X->l > 0 && X->S > 0 && !X->days) {
-    set_error("days is NULL with l > 0");
+  if (arrays && X->l > 0 && X->S > 0 && !X->days && !X->basis) {
+    set_error("days and basis are NULL with l > 0");
     return COPA_EINVAL;
   }
   if (opt->R < 1 || opt->inner_iters < 1) {
@@ -724,8 +805,40 @@ copa_status copa_plan_create(const copa_tensor *X, const copa_options *opt, void
     set_error("rank R=" + std::to_string(opt->R) + " has no kernels in this build");
     return COPA_EUNSUPPORTED;
   }
+  if (opt->precision != COPA_PREC_FP32 && opt->precision != COPA_PREC_MIXED) {
+    set_error("unknown precision");
+    return COPA_EINVAL;
+  }
+  if (opt->precision == COPA_PREC_MIXED) {
+    set_error("mixed precision is not available in this build");
+    return COPA_EUNSUPPORTED;
+  }
+  return COPA_OK;
+}
+
+copa_status copa_workspace_bytes(const copa_tensor *X, const copa_options *opt, size_t *bytes) {
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return COPA_EINVAL;
+  }
+  COPA_TRY(check_args(X, opt, false));
+  copa_plan tmp;
+  COPA_TRY(plan_dims(X, opt, &tmp));
+  COPA_TRY(carve_all(&tmp, true));
+  *bytes = tmp.arena_bytes;
+  return COPA_OK;
+}
+
+copa_status copa_plan_create(const copa_tensor *X, const copa_options *opt, void *workspace,
+                             size_t workspace_bytes, void *stream, copa_plan **out) {
+  if (!out) {
+    set_error("out is NULL");
+    return COPA_EINVAL;
+  }
+  *out = nullptr;
+  COPA_TRY(check_args(X, opt, true));
   copa_plan *p = new copa_plan();
-  copa_status st = build_plan(X, opt, (hipStream_t)stream, p);
+  copa_status st = build_plan(X, opt, workspace, workspace_bytes, (hipStream_t)stream, p);
   if (st != COPA_OK) {
     (void)hipDeviceSynchronize();
     free_plan(p);

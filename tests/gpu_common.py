@@ -29,15 +29,16 @@ def stacked_U(Qts, H):
 
 
 def run_gpu(coh, R, l, iters, seed=0, inner=5, prox=(co.PROX_NONE, co.PROX_NONNEG, co.PROX_L1),
-            lam=(0.0, 0.0, 0.1), init=None):
+            lam=(0.0, 0.0, 0.1), init=None, **plan_kw):
     import torch
     from paper_1803_04572_amd import copa
-    plan = copa.Plan.from_cohort(coh, R=R, l=l, inner_iters=inner, prox=prox, lam=lam)
+    plan_kw.setdefault("adjoint", True)
+    plan = copa.Plan.from_cohort(coh, R=R, l=l, inner_iters=inner, prox=prox, lam=lam, **plan_kw)
     H0, W0, V0 = init if init is not None else synth.init_factors(coh.K, coh.J, R, seed)
     st = plan.new_state(H0, W0, V0)
     rep, Qt = plan.fit(st, iters)
     torch.cuda.synchronize()
-    out = {k: v.double().cpu().numpy() for k, v in st.items()}
+    out = {k: v.double().cpu().numpy() for k, v in st.items() if k != "iter"}
     out["Qt"] = Qt.double().cpu().numpy()
     out["rep"] = rep
     out["plan"] = plan

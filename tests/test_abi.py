@@ -45,7 +45,8 @@ def test_status_strings_and_rank_table(lib):
 def _create(lib, t, o):
     h = ctypes.c_void_p()
     st = lib.copa_plan_create(ctypes.byref(t) if t is not None else None,
-                              ctypes.byref(o) if o is not None else None, None, ctypes.byref(h))
+                              ctypes.byref(o) if o is not None else None, None, 0, None,
+                              ctypes.byref(h))
     return st, h
 
 

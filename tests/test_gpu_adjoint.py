@@ -43,7 +43,7 @@ def _point(coh, R, seed):
 def _gpu(coh, R, Qts, H, V, W, want_dS=False, l=0):
     import torch
     from paper_1803_04572_amd import copa
-    plan = copa.Plan.from_cohort(coh, R=R, l=l)
+    plan = copa.Plan.from_cohort(coh, R=R, l=l, adjoint=True)
     d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).cuda()  # noqa
     Qt = d(np.concatenate(Qts, axis=0))
     out = plan.loss_grad(d(H), d(V), d(W), Qt, want_dS=want_dS)
@@ -126,7 +126,7 @@ def test_autograd_function_returns_the_adjoint():
     coh, _ = synth.make_config("c5", K=200)
     R = 10
     Qts, H, V, W = _point(coh, R, seed=11)
-    plan = copa.Plan.from_cohort(coh, R=R, l=0)
+    plan = copa.Plan.from_cohort(coh, R=R, l=0, adjoint=True)
     d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).cuda()  # noqa
     Qt = d(np.concatenate(Qts, axis=0))
     Ht, Vt, Wt = (d(a).requires_grad_(True) for a in (H, V, W))
@@ -170,7 +170,7 @@ def test_stationarity_stop_rule():
         assert rep["iters_done"] == expect, (tol, rep["iters_done"])
         assert 0.0 <= rep["stationarity"] < 10.0
         assert len(rep["fit_history"]) == expect
-    plan = copa.Plan.from_cohort(coh, R=R, l=0)
+    plan = copa.Plan.from_cohort(coh, R=R, l=0, adjoint=True)
     st = plan.new_state(*synth.init_factors(coh.K, coh.J, R, 0))
     rep, _ = plan.fit(st, 3)
     assert rep["stationarity"] == -1.0

@@ -150,8 +150,10 @@ def test_graph_replay_matches_kernel_by_kernel_launches():
     st2 = None
     for rep in range(3):
         if rep == 1:  # the same buffers again, reset to the initial point
-            for k, v in plan.new_state(*init).items():
-                st2[k].copy_(v)
+            fresh = plan.new_state(*init)
+            for k in ("H", "W", "V", "D_H", "D_W", "D_V"):
+                st2[k].copy_(fresh[k])
+            st2["iter"] = 0
         else:  # new buffers (a new capture)
             st2 = plan.new_state(*init)
         got, _ = plan.fit(st2, 6)
