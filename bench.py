@@ -116,6 +116,27 @@ def cpu_baseline(cfg_name, R, l, K_full, n_subjects, iters=3):
                       f"split over {workers} worker processes with one BLAS thread each"}
 
 
+def load_or_make(workload, cache, progress):
+    """The workload's cohort, generated (or read back from `cache` when an earlier run saved it
+    there: the same seeded arrays)."""
+    from paper_1803_04572_amd import synth
+    path = os.path.join(cache, f"cohort_{workload}.npz") if cache else None
+    cfg = dict(synth.CONFIGS[workload])
+    if path and os.path.exists(path):
+        progress(f"reading {path}")
+        z = np.load(path)
+        coh = synth.Cohort(K=int(z["K"]), J=int(z["J"]), subj_ptr=z["subj_ptr"],
+                           row_ptr=z["row_ptr"], col=z["col"], val=z["val"], days=z["days"])
+        return coh, cfg
+    progress(f"generating {workload}")
+    coh, cfg = synth.make_config(workload)
+    if path:
+        os.makedirs(cache, exist_ok=True)
+        np.savez(path, K=coh.K, J=coh.J, subj_ptr=coh.subj_ptr, row_ptr=coh.row_ptr, col=coh.col,
+                 val=coh.val, days=coh.days)
+    return coh, cfg
+
+
 def golden_check(workload, R, coh, fit_history, H, V, tol):
     """Compares a fit started from the seeded initial point with the FP64 oracle's trajectory on
     the same inputs, stored by tests/golden/make_fullsize_golden.py. None when no trajectory is
@@ -159,6 +180,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (HBM counter scaling)")
+    ap.add_argument("--cache", default=None,
+                    help="directory for the generated cohort (reused by later runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not supported "
@@ -175,8 +198,7 @@ def main():
     def progress(msg):
         print(f"bench.py: {msg}", file=sys.stderr, flush=True)
 
-    progress(f"generating {args.workload}")
-    coh, cfg = synth.make_config(args.workload)
+    coh, cfg = load_or_make(args.workload, args.cache, progress)
     R, l = args.R or cfg["R"], cfg["l"]
     progress(f"K={coh.K} S={coh.S} nnz={coh.nnz} R={R}; creating the plan")
     plan = copa.Plan.from_cohort(coh, R=R, l=l, inner_iters=cfg["inner"])
@@ -236,11 +258,13 @@ def main():
     ach = per_kernel[dom]["GBps"]
     traffic = measured_traffic(dom, args.workload if args.R is None else f"{args.workload}_R{R}")
     if args.copy_probe:
+        # a plain elementwise kernel of known size for the HBM counters' scale: reads and writes
+        # 256 MiB once per launch
         n = 64 << 20
         a = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
     del plan, state, init
     torch.cuda.empty_cache()
