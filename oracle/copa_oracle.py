@@ -287,6 +287,7 @@ class FitResult:
     rho: list          # (rho_H, rho_W, rho_V) per outer iteration
     F: dict            # last iteration's MTTKRPs {"H", "W", "V"}
     ranks: list        # Procrustes ranks of the last iteration
+    sigmas: list       # singular values of each A_k in the last iteration
 
 
 def copa_fit(prob, H0, W0, V0, opt: Options, D0=None):
@@ -297,15 +298,16 @@ def copa_fit(prob, H0, W0, V0, opt: Options, D0=None):
     else:
         D_H, D_W, D_V = (np.array(a, dtype=np.float64) for a in D0)
     fits, objs, spars, rhos = [], [], [], []
-    Qs, ranks, F = [], [], {}
+    Qs, ranks, sigmas, F = [], [], [], {}
     for _ in range(opt.outer_iters):
         # Procrustes: Q_k from the truncated SVD of X'_k V S_k H^T, then Y_k = Q_k^T X'_k
-        Qs, ranks = [], []
+        Qs, ranks, sigmas = [], [], []
         for k, Xh in enumerate(prob.Xh):
             A = Xh @ V @ np.diag(W[k]) @ H.T
-            Q, r, _ = procrustes(A, opt.rank_rtol)
+            Q, r, sv = procrustes(A, opt.rank_rtol)
             Qs.append(Q)
             ranks.append(r)
+            sigmas.append(sv)
         Ys = slices_Y(prob, Qs)
         # mode 1: H
         G = (W.T @ W) * (V.T @ V)
@@ -327,7 +329,7 @@ def copa_fit(prob, H0, W0, V0, opt: Options, D0=None):
         rhos.append((rH, rW, rV))
     Qt = [Q if prob.C[k] is None else prob.C[k] @ Q for k, Q in enumerate(Qs)]
     return FitResult(H=H, W=W, V=V, D_H=D_H, D_W=D_W, D_V=D_V, Q=Qs, Qtilde=Qt, fit=fits,
-                     objective=objs, sparsity=spars, rho=rhos, F=F, ranks=ranks)
+                     objective=objs, sparsity=spars, rho=rhos, F=F, ranks=ranks, sigmas=sigmas)
 
 
 def penalty(Z, kind, lam):

@@ -72,3 +72,47 @@ def procrustes_condition(coh, R, l, H, W, V, rtol=1e-6):
         kept = s[s > rtol * s[0]]
         out.append(kept[0] / kept[-1])
     return np.array(out)
+
+
+def ambiguous_band(sigmas, lo=1e-7, hi=1e-5):
+    """Subjects with a singular value of A_k within [lo, hi] of the largest: there the truncation
+    at rank_rtol = 1e-6 depends on the last bits of A_k."""
+    n = 0
+    for s in sigmas:
+        if s.size and s[0] > 0:
+            rel = s / s[0]
+            n += int(np.any((rel >= lo) & (rel <= hi)))
+    return n
+
+
+def rank_deficient(o, prob, R):
+    """Oracle's count of subjects whose Procrustes rank is below min(rows, R)."""
+    return sum(int(r < min(x.shape[0], R)) for r, x in zip(o.ranks, prob.Xh))
+
+
+def check_fit(tag, coh, g, o, prob, R, fit_rtol=None, cong_min=None, spars_entries=2):
+    """FIT history, objective history, V sparsity, rank counts and factor congruence of a GPU
+    fit against the oracle's on the same inputs."""
+    fit_rtol = FIT_RTOL if fit_rtol is None else fit_rtol
+    cong_min = CONGRUENCE_MIN if cong_min is None else cong_min
+    rep = g["rep"]
+    hist = np.abs(np.array(rep["fit_history"]) - np.array(o.fit)) / np.abs(o.fit)
+    obj = np.abs(np.array(rep["objective_history"]) - np.array(o.objective)) / np.abs(o.objective)
+    cong = dict(H=congruence(g["H"], o.H), V=congruence(g["V"], o.V), W=congruence(g["W"], o.W),
+                U=congruence(stacked_U(split_rows(coh, g["Qt"]), g["H"]),
+                             stacked_U(o.Qtilde, o.H)))
+    J = g["V"].shape[0]
+    dz = abs(rep["sparsity_V"] - o.sparsity[-1]) * J * R
+    band = ambiguous_band(o.sigmas)
+    rd_o = rank_deficient(o, prob, R)
+    print(tag, f"fit_gpu={rep['fit']:.9f} fit_oracle={o.fit[-1]:.9f} fit_rel={hist[-1]:.2e} "
+          f"hist_max={hist.max():.2e} obj_max={obj.max():.2e} spars={rep['sparsity_V']:.4f}/"
+          f"{o.sparsity[-1]:.4f} rank_def={rep['rank_deficient']}/{rd_o} band={band} "
+          + " ".join(f"cong_{k}={v:.7f}" for k, v in cong.items()), flush=True)
+    assert hist[-1] <= fit_rtol and hist.max() <= 10 * fit_rtol
+    assert obj.max() <= 10 * fit_rtol
+    assert dz <= spars_entries + 1e-9
+    assert abs(rep["rank_deficient"] - rd_o) <= band
+    assert min(cong.values()) >= cong_min
+    assert np.isclose(rep["sparsity_V"], float(np.mean(g["V"] == 0.0)))
+    return cong

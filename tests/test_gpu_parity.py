@@ -4,8 +4,8 @@ import pytest
 
 from oracle import copa_oracle as co
 from paper_1803_04572_amd import synth
-from gpu_common import (CONGRUENCE_MIN, FIT_RTOL, congruence, procrustes_condition, run_gpu,
-                        run_oracle, split_rows, stacked_U)
+from gpu_common import (CONGRUENCE_MIN, FIT_RTOL, ambiguous_band, check_fit, congruence,
+                        procrustes_condition, run_gpu, run_oracle, split_rows, stacked_U)
 
 pytestmark = pytest.mark.gpu
 
@@ -49,14 +49,31 @@ def test_one_iteration_step_parity(cfg_name, K, R, l):
     g = run_gpu(coh, R, l, 1)
     o, prob = run_oracle(coh, R, l, 1)
     FH, FW, FV = (t.double().cpu().numpy() for t in g["plan"].mttkrp_last())
-    # Q_k: a relative FP32 perturbation of A_k moves the polar factor by up to ~ eps * kappa_k
+    # Q_k: a relative perturbation eps of A_k moves its polar factor by up to about eps * kappa_k
+    # (kappa_k = sigma_1 / sigma_r over the kept singular values); the bound is asserted where
+    # kappa_k <= 1e4 and capped at 1e-3. Subjects past that, or with a singular value near the
+    # truncation threshold (the ambiguous band), are checked for structure instead: Qtilde_k^T
+    # Qtilde_k is a projector of the oracle's rank.
     H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
     kappa = procrustes_condition(coh, R, l, H0, W0, V0)
     Qg = split_rows(coh, g["Qt"])
-    qerr = max((np.abs(a - b).max(initial=0.0) / (1e-5 + 1e-6 * kap)
-                for a, b, kap in zip(Qg, o.Qtilde, kappa)), default=0.0)
+    band = [bool(sv.size and sv[0] > 0 and np.any((sv / sv[0] >= 1e-7) & (sv / sv[0] <= 1e-5)))
+            for sv in o.sigmas]
+    worst_scaled, worst_abs, n_struct = 0.0, 0.0, 0
+    for a, b, kap, amb, r in zip(Qg, o.Qtilde, kappa, band, o.ranks):
+        d = np.abs(a - b).max(initial=0.0)
+        worst_abs = max(worst_abs, d)
+        if kap <= 1e4 and not amb:
+            worst_scaled = max(worst_scaled, d / min(1e-5 + 1e-6 * kap, 1e-3))
+        else:
+            n_struct += 1
+            P = a.T @ a
+            assert np.abs(P @ P - P).max() < 1e-4 and abs(np.trace(P) - r) < 1e-3
+        if a.size:  # ranks agree wherever the truncation is not ambiguous
+            if not amb:
+                assert abs(np.trace(a.T @ a) - r) < 1e-3
     errs = dict(
-        Qt_scaled=qerr * 2e-4,
+        Qt_scaled=worst_scaled * 2e-4,
         FH=np.abs(FH - o.F["H"]).max() / np.abs(o.F["H"]).max(),
         FW=np.abs(FW - o.F["W"]).max() / np.abs(o.F["W"]).max(),
         FV=np.abs(FV - o.F["V"]).max() / np.abs(o.F["V"]).max(),
@@ -64,6 +81,8 @@ def test_one_iteration_step_parity(cfg_name, K, R, l):
         W=np.abs(g["W"] - o.W).max() / np.abs(o.W).max(),
         V=np.abs(g["V"] - o.V).max() / np.abs(o.V).max(),
         fit=abs(g["rep"]["fit"] - o.fit[-1]) / abs(o.fit[-1]))
+    print(f"step {cfg_name}: max |dQ| {worst_abs:.2e}, structure-checked subjects {n_struct}, "
+          f"ambiguous band {sum(band)}", flush=True)
     _report(f"step {cfg_name}", **errs)
     for k, v in errs.items():
         assert v < 2e-4, (k, v)
@@ -76,17 +95,81 @@ def test_fit_parity(cfg_name, K, R, l, iters):
     coh, cfg = synth.make_config(cfg_name, K=K)
     g = run_gpu(coh, R, l, iters)
     o, prob = run_oracle(coh, R, l, iters)
-    fit_rel = abs(g["rep"]["fit"] - o.fit[-1]) / abs(o.fit[-1])
-    hist = np.abs(np.array(g["rep"]["fit_history"]) - np.array(o.fit)) / np.abs(o.fit)
-    cong = dict(H=congruence(g["H"], o.H), V=congruence(g["V"], o.V), W=congruence(g["W"], o.W),
-                U=congruence(stacked_U(split_rows(coh, g["Qt"]), g["H"]),
-                             stacked_U(o.Qtilde, o.H)))
-    _report(f"fit {cfg_name}", fit_gpu=g["rep"]["fit"], fit_oracle=o.fit[-1], fit_rel=fit_rel,
-            hist_rel_max=float(hist.max()), spars_gpu=g["rep"]["sparsity_V"],
-            spars_oracle=o.sparsity[-1], rank_def=g["rep"]["rank_deficient"],
-            **{f"cong_{k}": v for k, v in cong.items()})
-    assert fit_rel <= FIT_RTOL
-    assert min(cong.values()) >= CONGRUENCE_MIN
+    check_fit(f"fit {cfg_name} K={coh.K} R={R} l={l}", coh, g, o, prob, R)
+
+
+# Constraint variants of Section "Examples of useful constraints": l0 (hard threshold, mu passed
+# as the weight), non-negativity on every factor ("Non-neg COPA"), nonnegative l1, and l1 on W.
+PX = co
+@pytest.mark.parametrize("name,prox,lam", [
+    ("l0_V", (PX.PROX_NONE, PX.PROX_NONNEG, PX.PROX_L0), (0.0, 0.0, 0.01)),
+    ("nonneg_all", (PX.PROX_NONNEG, PX.PROX_NONNEG, PX.PROX_NONNEG), (0.0, 0.0, 0.0)),
+    ("nonneg_l1_V", (PX.PROX_NONE, PX.PROX_NONNEG, PX.PROX_NONNEG_L1), (0.0, 0.0, 2.0)),
+    ("l1_W_l1_V", (PX.PROX_NONE, PX.PROX_L1, PX.PROX_L1), (0.0, 0.5, 2.0)),
+])
+@pytest.mark.parametrize("cfg_name,K,R,l", [("c2", 400, 10, 7), ("c5", 300, 10, 0)])
+def test_constraint_variants_parity(name, prox, lam, cfg_name, K, R, l):
+    coh, cfg = synth.make_config(cfg_name, K=K)
+    init = synth.init_factors(coh.K, coh.J, R, 0)
+    if prox[0] == PX.PROX_NONNEG:
+        # from H = I the non-negative H block collapses to zero on this data (then G_W = 0 and
+        # the W system is singular, in the oracle as well): start from a seeded non-negative H
+        H1 = np.random.default_rng(3).random((R, R)).astype(np.float32).astype(np.float64)
+        init = (H1, init[1], init[2])
+    g = run_gpu(coh, R, l, 10, prox=prox, lam=lam, init=init)
+    o, prob = run_oracle(coh, R, l, 10, prox=prox, lam=lam, init=init)
+    check_fit(f"constraints {name} {cfg_name}", coh, g, o, prob, R, spars_entries=3)
+    if prox[2] in (PX.PROX_L0, PX.PROX_NONNEG_L1):
+        assert o.sparsity[-1] > 0.05  # the variant really zeroes entries of V
+    if prox[2] in (PX.PROX_NONNEG, PX.PROX_NONNEG_L1):
+        assert (g["V"] >= 0).all()
+    if prox[0] == PX.PROX_NONNEG:
+        assert (g["H"] >= 0).all()
+
+
+@pytest.mark.parametrize("R,l", [(10, 4), (10, 8), (20, 8), (5, 3)])
+def test_basis_sizes_parity(R, l):
+    """Spline bases of 3, 4 and 8 functions per subject (the general-l Procrustes kernels)."""
+    coh, cfg = synth.make_config("c2", K=300)
+    g = run_gpu(coh, R, l, 8)
+    o, prob = run_oracle(coh, R, l, 8)
+    check_fit(f"basis l={l} R={R}", coh, g, o, prob, R)
+
+
+@pytest.mark.parametrize("l", [7, 0])
+def test_subjects_without_visits(l):
+    """Subjects with no visit rows (I_k = 0) among the others: they contribute nothing to any
+    MTTKRP and their W rows follow the ADMM steps with F_W = 0, as in the oracle."""
+    base, _ = synth.make_config("c2", K=200)
+    ik = np.diff(base.subj_ptr)
+    ik2 = np.insert(ik, [0, 5, 5, 77, 200], 0)  # empty subjects first, in a run, inside, last
+    subj_ptr = np.concatenate([[0], np.cumsum(ik2)]).astype(np.int64)
+    coh = synth.Cohort(K=ik2.size, J=base.J, subj_ptr=subj_ptr, row_ptr=base.row_ptr,
+                       col=base.col, val=base.val, days=base.days)
+    R = 10
+    g = run_gpu(coh, R, l, 8)
+    o, prob = run_oracle(coh, R, l, 8)
+    check_fit(f"empty subjects l={l}", coh, g, o, prob, R)
+    np.testing.assert_allclose(g["W"][ik2 == 0], o.W[ik2 == 0], rtol=1e-4, atol=1e-6)
+
+
+def test_numeric_failure_is_reported():
+    """A weight large enough to zero V leaves the next iteration's Gram of the H block at zero
+    (rho = 0, a singular ADMM system): the fit stops with COPA_ENUMERIC at that iteration. The
+    oracle's Cholesky of the same system fails the same way."""
+    from paper_1803_04572_amd import copa
+    coh, _ = synth.make_config("c5", K=100)
+    R = 5
+    prox, lam = (co.PROX_NONE, co.PROX_NONNEG, co.PROX_L1), (0.0, 0.0, 1e12)
+    with pytest.raises(np.linalg.LinAlgError):
+        run_oracle(coh, R, 0, 3, prox=prox, lam=lam)
+    plan = copa.Plan.from_cohort(coh, R=R, l=0, prox=prox, lam=lam)
+    st = plan.new_state(*synth.init_factors(coh.K, coh.J, R, 0))
+    with pytest.raises(copa.CopaError) as e:
+        plan.fit(st, 3)
+    assert e.value.status == copa.ENUMERIC
+    assert e.value.report["fail_iter"] == 1
+    assert float(np.abs(st["V"].cpu().numpy()).max()) == 0.0
 
 
 @pytest.mark.parametrize("J,chunked", [(8000, True), (9800, False)])
