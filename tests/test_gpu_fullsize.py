@@ -1,6 +1,10 @@
-"""The benchmark workload at full size (50,000 subjects, 11.5M nonzeros), through the same launch
-path bench.py times (graph replay): outputs the oracle can compute one subject at a time, and
+"""The 50,000-subject workload (11.5M nonzeros) at full size, through the launch path bench.py
+times (graph replay): the oracle's stored trajectory on the same inputs (written by
+tests/golden/make_fullsize_golden.py), outputs the oracle can compute one subject at a time, and
 properties that hold at any size."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -92,3 +96,29 @@ def test_full_size_fit_equals_dense_reconstruction(full_c2):
         r0, r1 = int(coh.subj_ptr[k]), int(coh.subj_ptr[k + 1])
         P = Qt[r0:r1].T @ Qt[r0:r1]
         assert np.abs(P @ P - P).max() < 1e-5
+
+
+def test_full_size_trajectory_matches_oracle(full_c2):
+    """20 outer iterations from the seeded start: FIT and objective history within 1e-5 of the
+    FP64 oracle's trajectory, H and V congruent to the oracle's final factors."""
+    import torch
+    from gpu_common import congruence
+    coh, cfg, plan = full_c2
+    R = cfg["R"]
+    golden = os.path.join(os.path.dirname(__file__), "golden", f"fullsize_c2_R{R}")
+    with open(golden + ".json") as fh:
+        ref = json.load(fh)
+    z = np.load(golden + ".npz")
+    assert (ref["K"], ref["S"], ref["nnz"]) == (coh.K, coh.S, coh.nnz)
+    st = plan.new_state(*synth.init_factors(coh.K, coh.J, R, 0))
+    rep, _ = plan.fit(st, ref["iters"], qtilde=False)
+    torch.cuda.synchronize()
+    fit = np.abs(np.array(rep["fit_history"]) - np.array(ref["fit"])) / np.abs(ref["fit"])
+    obj = np.abs(np.array(rep["objective_history"]) - np.array(ref["objective"])) / \
+        np.abs(ref["objective"])
+    cH = congruence(st["H"].double().cpu().numpy(), z["H"])
+    cV = congruence(st["V"].double().cpu().numpy(), z["V"])
+    print(f"full-size trajectory: fit_rel={fit[-1]:.2e} hist_max={fit.max():.2e} "
+          f"obj_max={obj.max():.2e} cong_H={cH:.9f} cong_V={cV:.9f}", flush=True)
+    assert fit.max() <= 1e-5 and obj.max() <= 1e-5
+    assert min(cH, cV) >= 0.999
