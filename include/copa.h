@@ -235,11 +235,15 @@ const char *copa_kernel_name(int32_t id);
  *   COPA_QUERY_COMPACT  1 if pass 1 streams the compact nonzeros (feature id below 2^16 and every
  *                       value exactly representable as bfloat16, so the 4-byte form is lossless),
  *   COPA_QUERY_CHUNKS   number of pass-2 chunks (0 if pass 2 uses its unchunked form),
- *   COPA_QUERY_WAVES    number of pass-1 wave entries.
+ *   COPA_QUERY_WAVES    number of pass-1 wave entries,
+ *   COPA_QUERY_PAIRS    number of (subject, feature) pairs of the projected data C_k^T X_k that
+ *                       the passes stream (smoothed plans with at most two nonzeros per visit
+ *                       row on average), or 0 when they stream the nonzeros and basis rows.
  * *out (host) receives the value. COPA_EINVAL for a NULL argument or an unknown `what`.       */
 #define COPA_QUERY_COMPACT 0
 #define COPA_QUERY_CHUNKS 1
 #define COPA_QUERY_WAVES 2
+#define COPA_QUERY_PAIRS 3
 copa_status copa_plan_query(const copa_plan *plan, int32_t what, int64_t *out);
 
 /* 1 if this build has kernels for rank R, else 0.                                           */

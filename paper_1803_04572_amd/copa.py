@@ -282,8 +282,9 @@ class Plan:
 
     def query(self, what):
         """Plan layout facts: 'compact' (pass 1 reads the lossless 4-byte nonzeros), 'chunks'
-        (pass-2 chunks), 'waves' (pass-1 wave entries)."""
-        code = {"compact": 0, "chunks": 1, "waves": 2}[what]
+        (pass-2 chunks), 'waves' (pass-1 wave entries), 'pairs' (projected (subject, feature)
+        pairs the passes stream; 0 when they stream nonzeros and basis rows)."""
+        code = {"compact": 0, "chunks": 1, "waves": 2, "pairs": 3}[what]
         out = c_int64(0)
         _check(lib().copa_plan_query(self._h, code, ctypes.byref(out)), "copa_plan_query")
         return int(out.value)

@@ -95,6 +95,7 @@ struct copa_plan {
   int32_t *rk = nullptr;     // [K] basis ranks (l > 0)
   float *Ew = nullptr;       // [64 x K] Procrustes eigenvectors of the last outer iteration (l > 0)
   int32_t *order = nullptr;  // [K] subjects by decreasing visit count
+  int32_t *order1 = nullptr; // [K] pass-1 subject order (by pair count for projected plans)
   copa::WaveEntry *waves = nullptr;
   int32_t n_waves = 0;
   copa::WaveEntry *waves1 = nullptr;  // pass-1 wave list for lane groups of 64 / tiles.cg lanes
@@ -110,6 +111,25 @@ struct copa_plan {
   float *FW = nullptr;  // [K x R]
   float *Vp = nullptr;  // [nt x J x RTP] V in padded column tiles (pass-1 LDS image)
   float *FV = nullptr;  // [J x R]
+  // projected pairs (smoothed plans with at most 2 nonzeros per visit row on average): one record
+  // of pw floats per (subject, feature) pair: the feature's column of C_k^T X_k and a key
+  bool proj = false;
+  int pw = 0;
+  int64_t npairs = 0;
+  int32_t *pp = nullptr;      // [K+1] pair offsets per subject
+  float *pairs1 = nullptr;    // [npairs x pw] by subject; key = feature id
+  float *pairs2 = nullptr;    // [npairs x pw] by pass-2 chunk and feature; key = feature << 16 | s
+  int32_t *pj = nullptr;      // [npairs] feature of each pair          (plan-creation input)
+  int32_t *pn = nullptr;      // [npairs+1] offsets into nzr / nzx      (plan-creation input)
+  int32_t *nzr = nullptr;     // [nnz] visit row of each nonzero, by (subject, feature, row)
+  float *nzx = nullptr;       // [nnz] its value
+  int32_t *perm2 = nullptr;   // [npairs] pairs1 index of each pairs2 record
+  int32_t *key2 = nullptr;    // [npairs] pairs2 keys
+  int pnchunks = 0;
+  int pchunks_cap = 0;
+  int32_t *pcq = nullptr;     // [pnchunks+1] pair offsets of the chunks
+  int32_t *pcinfo = nullptr;  // [pnchunks x 2] first subject and subject count
+  int32_t *pwsplit = nullptr; // [pnchunks x 9] wave slices on feature boundaries
   // pass-2 layout: per chunk of kChunkRows visit rows, nonzeros sorted by feature
   bool p2c = false;
   int nchunks = 0;

@@ -317,7 +317,8 @@ copa_status copa_plan_query(const copa_plan *p, int32_t what, int64_t *out) {
   }
   switch (what) {
     case COPA_QUERY_COMPACT: *out = p->compact ? 1 : 0; return COPA_OK;
-    case COPA_QUERY_CHUNKS: *out = p->p2c ? p->nchunks : 0; return COPA_OK;
+    case COPA_QUERY_CHUNKS: *out = p->proj ? p->pnchunks : (p->p2c ? p->nchunks : 0); return COPA_OK;
+    case COPA_QUERY_PAIRS: *out = p->proj ? p->npairs : 0; return COPA_OK;
     case COPA_QUERY_WAVES: *out = p->n_waves; return COPA_OK;
     default: set_error("unknown query"); return COPA_EINVAL;
   }

@@ -230,6 +230,105 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Pass 1 on the projected pairs (smoothed plans with few nonzeros per visit row): the T rows of
+// subject k are sum over its pairs (j, x'_j) of x'_j V(j, :)^T, with x'_j the l entries of column j
+// of C_k^T X_k. Same persistent blocks, LDS-staged tiles, lane groups and reduce-scatter as
+// k_pass1; a lane streams every G-th pair of its subject, four records in flight, with no
+// dependent loads (a pair carries its feature id).
+template <int RT, int PW>
+__global__ void __launch_bounds__(256)
+    k_pass1p(const WaveEntry *__restrict__ waves, int n_waves, const int32_t *__restrict__ order,
+             const int32_t *__restrict__ pp, const float *__restrict__ recs,
+             const float *__restrict__ Vp, int64_t J, int R, int l, int cg,
+             float *__restrict__ T, float *__restrict__ FV, FitScalars *sc) {
+  constexpr int RTP = row4(RT);
+  extern __shared__ float4 smem4[];
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) sc->cur += 1;
+  if (blockIdx.y == 0)
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < J * R;
+         e += (int64_t)gridDim.x * blockDim.x)
+      FV[e] = 0.0f;
+  {
+    const float4 *src = reinterpret_cast<const float4 *>(Vp + (int64_t)blockIdx.y * cg * J * RTP);
+    const int64_t n4 = cg * J * RTP / 4;
+    for (int64_t e0 = 0; e0 < n4; e0 += 8 * (int64_t)blockDim.x) {
+      float4 tmp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t e = e0 + u * blockDim.x + threadIdx.x;
+        tmp[u] = src[e < n4 ? e : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t e = e0 + u * blockDim.x + threadIdx.x;
+        smem4[e < n4 ? e : n4] = tmp[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int lpg = 64 / cg, cgi = lane / lpg, lgl = lane - cgi * lpg;
+  const float *sV = reinterpret_cast<const float *>(smem4) + (int64_t)cgi * J * RTP;
+  const int c0 = (blockIdx.y * cg + cgi) * RT;
+  for (int wv = blockIdx.x * 4 + (threadIdx.x >> 6); wv < n_waves; wv += gridDim.x * 4) {
+    const WaveEntry we = waves[wv];
+    const int lg = we.lg_count & 255, cnt = we.lg_count >> 8;
+    const int G = 1 << lg, sidx = lgl >> lg, sub = lgl & (G - 1);
+    const bool active = sidx < cnt;
+    const int k = active ? order[we.first + sidx] : 0;
+    const int p0 = active ? pp[k] : 0, p1 = active ? pp[k + 1] : 0;
+    float acc[kLMax][RT];
+#pragma unroll
+    for (int a = 0; a < kLMax; ++a)
+#pragma unroll
+      for (int r = 0; r < RT; ++r) acc[a][r] = 0.0f;
+    auto take = [&](const float (&f)[PW]) {
+      const int j = (int)__float_as_uint(f[PW - 1]);
+      float v[RT];
+      lds_row<RT>(sV + j * RTP, v);
+#pragma unroll
+      for (int a = 0; a < kLMax; ++a)
+        if (a < l)
+#pragma unroll
+          for (int r = 0; r < RT; ++r) acc[a][r] += f[a] * v[r];
+    };
+    for (int q = p0 + sub; q < p1; q += 4 * G) {
+      float f[4][PW];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) load_rec<PW>(recs, q + u * G < p1 ? q + u * G : q, f[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q + u * G < p1) take(f[u]);
+    }
+    constexpr int E = kLMax * RT;
+    float *dst = T + (int64_t)k * l * R + c0;
+    auto scatter_store = [&](auto gc) {
+      constexpr int Gc = decltype(gc)::value;
+      constexpr int Ep = (E + Gc - 1) / Gc * Gc;
+      float v[Ep];
+#pragma unroll
+      for (int e = 0; e < Ep; ++e) v[e] = e < E ? acc[e / RT][e % RT] : 0.0f;
+      reduce_scatter<Ep, Gc>(v, sub);
+      if (active) {
+#pragma unroll
+        for (int m = 0; m < Ep / Gc; ++m) {
+          const int e = m * Gc + sub, a = e / RT, r = e - a * RT;
+          if (e < E && a < l && c0 + r < R) dst[a * R + r] = v[m];
+        }
+      }
+    };
+    switch (lg) {
+      case 0: scatter_store(std::integral_constant<int, 1>{}); break;
+      case 1: scatter_store(std::integral_constant<int, 2>{}); break;
+      case 2: scatter_store(std::integral_constant<int, 4>{}); break;
+      case 3: scatter_store(std::integral_constant<int, 8>{}); break;
+      case 4: scatter_store(std::integral_constant<int, 16>{}); break;
+      case 5: scatter_store(std::integral_constant<int, 32>{}); break;
+      default: scatter_store(std::integral_constant<int, 64>{}); break;
+    }
+  }
+}
+
 // V (J x R) -> padded column tiles Vp[tile][j][0..RTP) (padding stays zero)
 template <int R>
 __global__ void k_pad_V(const float *__restrict__ V, float *__restrict__ Vp, int64_t J, int rt,
@@ -1687,10 +1786,19 @@ static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
   const int nb = std::max(1, std::min((p->n_waves1 + 3) / 4, p->n_cu * per_cu));
   dim3 grid((unsigned)nb, (unsigned)(p->tiles.nt / cg)), block(256);
 #define P1(SM, CP)                                                                              \
-  k_pass1<RT, SM, CP><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order, p->subj,       \
+  k_pass1<RT, SM, CP><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1, p->subj,       \
                                               p->row, p->col, p->val, p->xc, p->C, p->Vp, p->J, \
                                               p->R, p->l, cg, p->T, p->FV, p->scal)
-  if (p->l > 0) {
+  if (p->proj) {
+    if (p->pw == 8)
+      k_pass1p<RT, 8><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1, p->pp,
+                                                p->pairs1, p->Vp, p->J, p->R, p->l, cg, p->T,
+                                                p->FV, p->scal);
+    else
+      k_pass1p<RT, 12><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1, p->pp,
+                                                 p->pairs1, p->Vp, p->J, p->R, p->l, cg, p->T,
+                                                 p->FV, p->scal);
+  } else if (p->l > 0) {
     if (p->compact) P1(true, true); else P1(true, false);
   } else {
     if (p->compact) P1(false, true); else P1(false, false);
@@ -1700,7 +1808,9 @@ static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
 
 template <int RT>
 static void launch_pass2c_rt(copa_plan *p, hipStream_t s) {
-  if (p->l > 0)
+  if (p->proj)
+    launch_pass2p<RT>(p, p->FV, s);
+  else if (p->l > 0)
     launch_pass2c<RT, true>(p, p->M, p->FV, s);
   else
     launch_pass2c<RT, false>(p, p->M, p->FV, s);
@@ -1836,7 +1946,7 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
     gram<R>(p, st->W, st->W, K, nullptr, 0, kSlotWtW, p->M, p->rows_total, kSlotPsi, s);
   });
   timed(p, s, kidPass2, [&] {
-    if (p->p2c) {
+    if (p->p2c || p->proj) {
       RT2_SWITCH(R, p->tiles2.rt, launch_pass2c_rt, p, s);
     } else {
       RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s);

@@ -463,6 +463,204 @@ static __global__ void __launch_bounds__(256)
   }
 }
 
+// ------------------------------------------------------------------ projected pairs
+// A smoothed plan with few nonzeros per visit row streams the projected data X'_k = C_k^T X_k
+// instead of X and the basis rows: one record of PW floats per (subject, feature) pair that
+// occurs, holding the l entries of that column of X'_k (FP32, formed in FP64 at plan creation),
+// zeros, and a key in the last float.
+template <int PW>
+__device__ __forceinline__ void load_rec(const float *__restrict__ recs, int64_t q,
+                                         float (&f)[PW]) {
+  const float4 *r4 = reinterpret_cast<const float4 *>(recs + q * PW);
+#pragma unroll
+  for (int u = 0; u < PW / 4; ++u) {
+    const float4 v = r4[u];
+    f[4 * u] = v.x;
+    f[4 * u + 1] = v.y;
+    f[4 * u + 2] = v.z;
+    f[4 * u + 3] = v.w;
+  }
+}
+
+// Pass 2 on the projected pairs: F_V(j, :) += x'_j M_k for every pair (k, j), with the M rows of
+// a chunk's subjects staged in LDS. A chunk is a run of at most kChunkRows / l subjects whose
+// pairs are sorted by feature (key = feature << 16 | subject within the chunk) and cut into
+// eight wave slices on feature boundaries; each lane sums a contiguous run of its wave's slice
+// feature by feature, and the segmented scan over lanes of k_pass2c joins runs that share a
+// feature, so each feature is added to the block's LDS copy of F_V by one lane.
+template <int RT, int PW>
+__global__ void __launch_bounds__(512)
+    k_pass2p(int nchunks, const int32_t *__restrict__ cq, const int32_t *__restrict__ cinfo,
+             const int32_t *__restrict__ wsplit, const float *__restrict__ recs,
+             const float *__restrict__ M, int64_t J, int R, int l, float *__restrict__ FV,
+             float *__restrict__ part) {
+  constexpr int RTP = row4(RT);
+  constexpr int PF = 4;  // records per lane loaded ahead of the chunk's M staging
+  extern __shared__ float4 smem4[];
+  float *sF = reinterpret_cast<float *>(smem4);
+  float *sM = sF + J * RTP;  // the chunk's M rows, RTP apart
+  const int c0 = blockIdx.y * RT;
+  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wave = t >> 6;
+  for (int64_t e = t; e < J * RTP; e += nt) sF[e] = 0.0f;
+  int nk0 = 0, nns = 0, ns0 = 0, ns1 = 0;
+  auto fetch = [&](int cc) {
+    if (cc < nchunks) {
+      nk0 = cinfo[2 * cc];
+      nns = cinfo[2 * cc + 1];
+      ns0 = wsplit[cc * 9 + wave];
+      ns1 = wsplit[cc * 9 + wave + 1];
+    }
+  };
+  fetch(blockIdx.x);
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int k0 = nk0, nsub = nns, s0 = ns0, s1 = ns1;
+    __syncthreads();  // the previous chunk is done with sM
+    const int per = (s1 - s0 + 63) >> 6;
+    const int a = s0 + lane * per;
+    const int b = a + per < s1 ? a + per : s1;
+    float pre[PF][PW];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) load_rec<PW>(recs, a + u < b ? a + u : 0, pre[u]);
+    {
+      // the chunk's M block (nsub l rows of RT floats), 4 loads in flight per thread
+      const int nm = nsub * l * RT;
+      const float *Mb = M + (int64_t)k0 * l * R + c0;
+      for (int e0 = 0; e0 < nm; e0 += 4 * nt) {
+        float mv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * nt + t;
+          const int ec = e < nm ? e : nm - 1;
+          const int q = ec / RT, r = ec - q * RT;
+          mv[u] = Mb[(int64_t)q * R + (c0 + r < R ? r : R - 1 - c0)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * nt + t;
+          const int q = e / RT;
+          sM[e < nm ? q * RTP + (e - q * RT) : kChunkRows * RTP] = mv[u];
+        }
+      }
+    }
+    fetch(c + gridDim.x);
+    __syncthreads();
+    auto add_row = [&](int j, const float *v) { lds_row_add<RT>(sF + j * RTP, v); };
+    float acc[RTP], head[RTP];
+#pragma unroll
+    for (int r = 0; r < RTP; ++r) {
+      acc[r] = 0.0f;
+      head[r] = 0.0f;
+    }
+    int cur = -1, hkey = -1, nseg = 0;
+    auto take = [&](const float (&f)[PW]) {
+      const uint32_t key = __float_as_uint(f[PW - 1]);
+      const int j = (int)(key >> 16);
+      const float *mr = sM + (int)(key & 0xffffu) * l * RTP;
+      if (j != cur) {
+        if (nseg == 1) {
+          hkey = cur;
+#pragma unroll
+          for (int r = 0; r < RTP; ++r) head[r] = acc[r];
+        } else if (nseg > 1) {
+          add_row(cur, acc);  // a segment inside this lane's run: no other lane has it
+        }
+        cur = j;
+        ++nseg;
+#pragma unroll
+        for (int r = 0; r < RTP; ++r) acc[r] = 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < PW - 1; ++q) {
+        if (q < l) {
+          float mv[RT];
+          lds_row<RT>(mr + q * RTP, mv);
+#pragma unroll
+          for (int r = 0; r < RT; ++r) acc[r] += f[q] * mv[r];
+        }
+      }
+    };
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+      if (a + u < b) take(pre[u]);
+    for (int e = a + PF; e < b; e += PF) {
+      float f[PF][PW];
+#pragma unroll
+      for (int u = 0; u < PF; ++u) load_rec<PW>(recs, e + u < b ? e + u : e, f[u]);
+#pragma unroll
+      for (int u = 0; u < PF; ++u)
+        if (e + u < b) take(f[u]);
+    }
+    const int first = nseg > 1 ? hkey : cur;
+    auto seg_step = [&](auto ctrl, auto mask) {
+      constexpr int CT = decltype(ctrl)::value, MK = decltype(mask)::value;
+      const int kp = dpp_i<CT, MK>(-1, cur);
+      float vp[RT];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) vp[r] = dpp_f<CT, MK>(0.0f, acc[r]);
+      if (cur >= 0 && kp == cur) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[r] += vp[r];
+      }
+    };
+    seg_step(std::integral_constant<int, 0x111>{}, std::integral_constant<int, 0xF>{});
+    seg_step(std::integral_constant<int, 0x112>{}, std::integral_constant<int, 0xF>{});
+    seg_step(std::integral_constant<int, 0x114>{}, std::integral_constant<int, 0xF>{});
+    seg_step(std::integral_constant<int, 0x118>{}, std::integral_constant<int, 0xF>{});
+    seg_step(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
+    seg_step(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
+    const int knext = dpp_i<0x130>(-1, first);
+    const int kprev1 = dpp_i<0x138>(-1, cur);
+    float carry[RTP];
+#pragma unroll
+    for (int r = 0; r < RTP; ++r) carry[r] = r < RT ? dpp_f<0x138>(0.0f, acc[r]) : 0.0f;
+    if (nseg > 1) {
+      const bool join = lane > 0 && kprev1 == hkey;
+#pragma unroll
+      for (int r = 0; r < RTP; ++r) head[r] += join ? carry[r] : 0.0f;
+      add_row(hkey, head);
+    }
+    if (cur >= 0) {
+      const bool cont = lane < 63 && knext == cur;
+      if (!cont) add_row(cur, acc);
+    }
+  }
+  __syncthreads();
+  if (part) {
+    float *dst = part + (int64_t)blockIdx.x * J * R;
+    for (int64_t e = t; e < J * RTP; e += nt) {
+      const int64_t j = e / RTP;
+      const int r = (int)(e - j * RTP);
+      if (r < RT && c0 + r < R) dst[j * R + c0 + r] = sF[e];
+    }
+    return;
+  }
+  for (int64_t e = t; e < J * RTP; e += nt) {
+    const int64_t j = e / RTP;
+    const int r = (int)(e - j * RTP);
+    const float v = sF[e];
+    if (r < RT && c0 + r < R && v != 0.0f) unsafeAtomicAdd(&FV[j * R + c0 + r], v);
+  }
+}
+
+template <int RT>
+inline void launch_pass2p(const copa_plan *p, float *F, hipStream_t s) {
+  const int gx = std::min(p->pnchunks, p->p2_blocks_cap);
+  const dim3 grid((unsigned)gx, (unsigned)p->tiles2.nt);
+  const size_t lds = ((size_t)p->J * row4(RT) + (size_t)kChunkRows * row4(RT) + 4) * sizeof(float);
+  float *part = p->opt.deterministic ? p->fvpart : nullptr;
+  if (p->pw == 8)
+    k_pass2p<RT, 8><<<grid, 512, lds, s>>>(p->pnchunks, p->pcq, p->pcinfo, p->pwsplit, p->pairs2,
+                                            p->M, p->J, p->R, p->l, F, part);
+  else
+    k_pass2p<RT, 12><<<grid, 512, lds, s>>>(p->pnchunks, p->pcq, p->pcinfo, p->pwsplit,
+                                             p->pairs2, p->M, p->J, p->R, p->l, F, part);
+  if (part) {
+    const int64_t n = p->J * p->R;
+    k_fv_sum<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256)), 256, 0,
+               s>>>(part, gx, n, F);
+  }
+}
+
 // Unchunked fallback (features >= 2^16): global atomics per nonzero.
 // Launches k_pass2c on the plan's chunks: SMOOTH forms u rows from the basis and the M rows of
 // each chunk's subjects; otherwise u_i is row i of Mrows (R wide).

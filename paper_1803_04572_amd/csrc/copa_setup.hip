@@ -139,10 +139,17 @@ __device__ __forceinline__ void spline_row(double t, const double (&beta)[L + 4]
 // triangle R (M_k = Q_M R), takes the SVD of R by one-sided Jacobi (columns orthogonalised), sorts
 // the singular values, keeps sigma > rtol * sigma_1 and writes C_k = M_k V_r Sigma_r^{-1}, an
 // orthonormal basis of span(M_k), as FP32 rows of width kLMax.
+// With `pp` set it also forms the projected data X'_k = C_k^T X_k in FP64, one record of `pw`
+// floats per (subject, feature) pair: the column (entries 0..L-1), zeros, and the feature id in
+// the last float (the subject's nonzeros come grouped by feature in nzr / nzx, pair q owning
+// [pn[q], pn[q+1])).
 template <int L>
 __global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double *days,
                                               const double *basis, float *C, int32_t *rk,
-                                              int64_t K, double rtol) {
+                                              int64_t K, double rtol, const int32_t *pp,
+                                              const int32_t *pj, const int32_t *pn,
+                                              const int32_t *nzr, const float *nzx,
+                                              float *recs, int pw) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   const int r0 = subj[k], r1 = subj[k + 1];
@@ -167,12 +174,22 @@ __global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double 
     tn = fmax(tn, days[i]);
   }
   if (t1 == tn) {  // no time span: the basis is the constant function
-    const float c0 = (float)(1.0 / sqrt((double)(r1 - r0)));
+    const double cd = 1.0 / sqrt((double)(r1 - r0));
+    const float c0 = (float)cd;
     for (int i = r0; i < r1; ++i) {
 #pragma unroll
       for (int a = 0; a < kLMax; ++a) C[(int64_t)i * kLMax + a] = a == 0 ? c0 : 0.0f;
     }
     rk[k] = 1;
+    if (pp) {
+      for (int q = pp[k]; q < pp[k + 1]; ++q) {
+        double x = 0.0;
+        for (int n = pn[q]; n < pn[q + 1]; ++n) x += cd * (double)nzx[n];
+        float *rec = recs + (int64_t)q * pw;
+        for (int a = 0; a < pw - 1; ++a) rec[a] = a == 0 ? (float)x : 0.0f;
+        rec[pw - 1] = __int_as_float(pj[q]);
+      }
+    }
     return;
   }
   constexpr int d = L - 1 < 3 ? L - 1 : 3;
@@ -294,15 +311,57 @@ __global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double 
     }
   }
   rk[k] = r;
+  if (pp) {
+    for (int q = pp[k]; q < pp[k + 1]; ++q) {
+      double x[L];
+#pragma unroll
+      for (int j = 0; j < L; ++j) x[j] = 0.0;
+      for (int n = pn[q]; n < pn[q + 1]; ++n) {
+        double m[L];
+        basis_row(nzr[n], m);
+        const double v = (double)nzx[n];
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+          double c = 0.0;
+#pragma unroll
+          for (int a = 0; a < L; ++a) c += m[a] * Vr[a][j];
+          x[j] += c * v;
+        }
+      }
+      float *rec = recs + (int64_t)q * pw;
+#pragma unroll
+      for (int j = 0; j < L; ++j) rec[j] = (float)x[j];
+      for (int a = L; a < pw - 1; ++a) rec[a] = 0.0f;
+      rec[pw - 1] = __int_as_float(pj[q]);
+    }
+  }
+}
+
+// pairs2[q] = pairs1[perm[q]] with the key replaced by key2[q]
+__global__ void k_permute_pairs(const float *__restrict__ recs1, const int32_t *__restrict__ perm,
+                                const int32_t *__restrict__ key2, int64_t n, int pw,
+                                float *__restrict__ recs2) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * pw;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = e / pw;
+    const int a = (int)(e - q * pw);
+    recs2[e] = a == pw - 1 ? __int_as_float(key2[q]) : recs1[(int64_t)perm[q] * pw + a];
+  }
 }
 
 static copa_status launch_basis(int l, const int32_t *subj, const double *days,
                                 const double *basis, float *C, int32_t *rk, int64_t K,
-                                double rtol, hipStream_t s) {
+                                double rtol, const copa_plan *p, hipStream_t s) {
+  const bool pr = p->proj;
   dim3 g((unsigned)((K + 63) / 64)), b(64);
   switch (l) {
 #define CASE(Lv) \
-  case Lv: k_basis<Lv><<<g, b, 0, s>>>(subj, days, basis, C, rk, K, rtol); break;
+  case Lv:                                                                                      \
+    k_basis<Lv><<<g, b, 0, s>>>(subj, days, basis, C, rk, K, rtol, pr ? p->pp : nullptr,       \
+                                pr ? p->pj : nullptr, pr ? p->pn : nullptr,                    \
+                                pr ? p->nzr : nullptr, pr ? p->nzx : nullptr,                  \
+                                pr ? p->pairs1 : nullptr, p->pw);                              \
+    break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: set_error("l outside 0..8"); return COPA_EUNSUPPORTED;
@@ -357,8 +416,13 @@ static copa_status plan_dims(const copa_tensor *X, const copa_options *opt, copa
     return COPA_EUNSUPPORTED;
   }
   p->tiles2 = choose_tiles2(R, p->J, p->lds_limit);
-  p->p2c = p->J <= 65536 && p->nnz > 0 && p->tiles2.nt > 0;
-  if (p->opt.deterministic && !p->p2c && p->nnz > 0) {
+  // smoothed data with at most two nonzeros per visit row on average are streamed as projected
+  // (subject, feature) pairs: fewer bytes than the nonzeros plus a basis row per visit row
+  p->proj = p->l > 0 && p->J <= 65536 && p->nnz > 0 && p->nnz <= 2 * p->S && p->tiles2.nt > 0;
+  p->pw = p->l <= 7 ? 8 : 12;
+  // row chunks: pass 2 of plans without projected pairs, and the adjoint's scatter
+  p->p2c = p->J <= 65536 && p->nnz > 0 && p->tiles2.nt > 0 && (!p->proj || p->adjoint);
+  if (p->opt.deterministic && p->nnz > 0 && !(p->p2c || p->proj)) {
     set_error("deterministic mode needs the chunked pass 2 (J <= 65536 and an F_V tile that "
               "fits LDS)");
     return COPA_EUNSUPPORTED;
@@ -383,6 +447,7 @@ static copa_status plan_dims(const copa_tensor *X, const copa_options *opt, copa
   p->nchunks_cap = (int)std::min<int64_t>(INT32_MAX - 1, (p->S + kChunkRows - 1) / kChunkRows +
                                                           (p->l > 0 ? K / msub : 0) + 1);
   p->p2_blocks_cap = 2 * std::max(1, p->n_cu);
+  p->pchunks_cap = p->proj ? (int)std::min<int64_t>(INT32_MAX - 1, K / msub + 2) : 0;
   return COPA_OK;
 }
 
@@ -408,6 +473,7 @@ static copa_status carve_all(copa_plan *p, bool dry) {
   COPA_TRY(take(&p->val, nnz));
   COPA_TRY(take(&p->xc, p->J <= 65536 ? nnz : 0));
   COPA_TRY(take(&p->order, K));
+  COPA_TRY(take(&p->order1, K));
   COPA_TRY(take(&p->waves, K));
   COPA_TRY(take(&p->waves1, K));
   COPA_TRY(take(&p->rowsubj, S));
@@ -433,8 +499,25 @@ static copa_status carve_all(copa_plan *p, bool dry) {
     COPA_TRY(take(&p->crow, nch + 1));
     COPA_TRY(take(&p->cinfo, 2 * nch));
     COPA_TRY(take(&p->pkv, nnz));
-    if (p->opt.deterministic) COPA_TRY(take(&p->fvpart, (size_t)p->p2_blocks_cap * J * R));
   }
+  if (p->proj) {
+    const size_t pcap = (size_t)nnz;  // pairs never outnumber nonzeros
+    COPA_TRY(take(&p->pp, K + 1));
+    COPA_TRY(take(&p->pairs1, pcap * p->pw));
+    COPA_TRY(take(&p->pairs2, pcap * p->pw));
+    COPA_TRY(take(&p->pj, pcap));
+    COPA_TRY(take(&p->pn, pcap + 1));
+    COPA_TRY(take(&p->nzr, nnz));
+    COPA_TRY(take(&p->nzx, nnz));
+    COPA_TRY(take(&p->perm2, pcap));
+    COPA_TRY(take(&p->key2, pcap));
+    const size_t nch = (size_t)p->pchunks_cap;
+    COPA_TRY(take(&p->pcq, nch + 1));
+    COPA_TRY(take(&p->pcinfo, 2 * nch));
+    COPA_TRY(take(&p->pwsplit, nch * 9));
+  }
+  if ((p->p2c || p->proj) && p->opt.deterministic)
+    COPA_TRY(take(&p->fvpart, (size_t)p->p2_blocks_cap * J * R));
   COPA_TRY(take(&p->vpart, (size_t)p->n_vblocks * 4));
   COPA_TRY(take(&p->wpart, (size_t)p->n_wblocks));
   COPA_TRY(take(&p->small, 8 * R * R));
@@ -549,6 +632,161 @@ static copa_status build_sorted_chunks(const copa_tensor *X, copa_plan *p, hipSt
     }
     COPA_HIP(hipMemcpyAsync(p->pkv, kv.data(), nnz * sizeof(uint2), hipMemcpyHostToDevice, s));
     COPA_HIP(hipStreamSynchronize(s));
+  }
+  COPA_HIP(hipStreamSynchronize(s));
+  return COPA_OK;
+}
+
+// Host-side lists of the projected pairs: per subject, its nonzeros grouped by feature (rows in
+// order within a feature); pair q of the subject's feature pj[q] owns nonzeros [pn[q], pn[q+1])
+// of nzr (visit row) / nzx (value). The device basis kernel then forms the records.
+static copa_status build_pair_lists(const copa_tensor *X, copa_plan *p,
+                                    const std::vector<int64_t> &hs, std::vector<int32_t> &hpp,
+                                    std::vector<int32_t> &hpj, hipStream_t s) {
+  const int64_t K = p->K, S = p->S, nnz = p->nnz;
+  std::vector<int64_t> rp(S + 1);
+  std::vector<int32_t> cl(nnz);
+  std::vector<float> vl(nnz);
+  COPA_HIP(hipMemcpyAsync(rp.data(), X->row_ptr, (S + 1) * sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipMemcpyAsync(cl.data(), X->col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipMemcpyAsync(vl.data(), X->val, nnz * sizeof(float), hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> nzr(nnz), cnt(K + 1, 0);
+  std::vector<float> nzx(nnz);
+  std::vector<int32_t> feat(nnz);  // feature of each nonzero in the grouped order
+  const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  auto run = [&](auto &&body) {
+    std::vector<std::thread> pool;
+    for (unsigned w = 0; w < nthreads; ++w)
+      pool.emplace_back([&, w]() {
+        const int64_t a = K * w / nthreads, b = K * (w + 1) / nthreads;
+        body(a, b);
+      });
+    for (auto &t : pool) t.join();
+  };
+  run([&](int64_t ka, int64_t kb) {
+    std::vector<uint64_t> tmp;
+    for (int64_t k = ka; k < kb; ++k) {
+      const int64_t e0 = rp[hs[k]], e1 = rp[hs[k + 1]];
+      tmp.clear();
+      for (int64_t i = hs[k]; i < hs[k + 1]; ++i)
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+          tmp.push_back(((uint64_t)(uint32_t)cl[e] << 32) | (uint64_t)(e - e0));
+      std::sort(tmp.begin(), tmp.end());  // by feature, then by position (row order)
+      int32_t distinct = 0;
+      for (size_t q = 0; q < tmp.size(); ++q) {
+        const int64_t e = e0 + (int64_t)(tmp[q] & 0xffffffffu);
+        const int32_t j = (int32_t)(tmp[q] >> 32);
+        if (q == 0 || j != feat[e0 + q - 1]) ++distinct;
+        feat[e0 + q] = j;
+        nzx[e0 + q] = vl[e];
+        // visit row of nonzero e: the last row of the subject starting at or before e
+        int64_t lo = hs[k], hi = hs[k + 1] - 1;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi + 1) / 2;
+          if (rp[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        nzr[e0 + q] = (int32_t)lo;
+      }
+      (void)e1;
+      cnt[k] = distinct;
+    }
+  });
+  hpp.assign(K + 1, 0);
+  for (int64_t k = 0; k < K; ++k) hpp[k + 1] = hpp[k] + cnt[k];
+  const int64_t P = hpp[K];
+  p->npairs = P;
+  hpj.assign(P, 0);
+  std::vector<int32_t> hpn(P + 1);
+  run([&](int64_t ka, int64_t kb) {
+    for (int64_t k = ka; k < kb; ++k) {
+      const int64_t e0 = rp[hs[k]], e1 = rp[hs[k + 1]];
+      int64_t q = hpp[k];
+      for (int64_t e = e0; e < e1; ++e)
+        if (e == e0 || feat[e] != feat[e - 1]) {
+          hpj[q] = feat[e];
+          hpn[q] = (int32_t)e;
+          ++q;
+        }
+    }
+  });
+  hpn[P] = (int32_t)nnz;
+  COPA_HIP(hipMemcpyAsync(p->pp, hpp.data(), (K + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (P > 0) {
+    COPA_HIP(hipMemcpyAsync(p->pj, hpj.data(), P * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  }
+  COPA_HIP(hipMemcpyAsync(p->pn, hpn.data(), (P + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  COPA_HIP(hipMemcpyAsync(p->nzr, nzr.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  COPA_HIP(hipMemcpyAsync(p->nzx, nzx.data(), nnz * sizeof(float), hipMemcpyHostToDevice, s));
+  COPA_HIP(hipStreamSynchronize(s));
+  return COPA_OK;
+}
+
+// Pass-2 chunks of the projected pairs: runs of at most kChunkRows / l consecutive subjects,
+// each chunk's pairs ordered by (feature, subject) into pairs2 and cut into eight wave slices on
+// feature boundaries.
+static copa_status build_pair_chunks(copa_plan *p, const std::vector<int32_t> &hpp,
+                                     const std::vector<int32_t> &hpj, hipStream_t s) {
+  const int64_t K = p->K, P = p->npairs;
+  const int64_t msub = kChunkRows / p->l;
+  std::vector<int32_t> cq, cinf;
+  for (int64_t k = 0; k < K; k += msub) {
+    const int64_t n = std::min<int64_t>(msub, K - k);
+    cq.push_back(hpp[k]);
+    cinf.push_back((int32_t)k);
+    cinf.push_back((int32_t)n);
+  }
+  cq.push_back((int32_t)P);
+  const int nch = (int)cinf.size() / 2;
+  if (nch > p->pchunks_cap) {
+    set_error("pass-2 chunk count above its bound (internal error)");
+    return COPA_EDEVICE;
+  }
+  std::vector<int32_t> perm(P), key(P), ws((size_t)nch * 9);
+  const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (unsigned w = 0; w < nthreads; ++w) {
+    pool.emplace_back([&, w]() {
+      std::vector<uint64_t> tmp;
+      for (int c = (int)w; c < nch; c += (int)nthreads) {
+        const int64_t k0 = cinf[2 * c], n = cinf[2 * c + 1];
+        tmp.clear();
+        for (int64_t k = k0; k < k0 + n; ++k)
+          for (int64_t q = hpp[k]; q < hpp[k + 1]; ++q)
+            tmp.push_back(((uint64_t)(uint32_t)hpj[q] << 48) | ((uint64_t)(k - k0) << 32) |
+                          (uint64_t)q);
+        std::sort(tmp.begin(), tmp.end());
+        const int64_t q0 = cq[c];
+        for (size_t i = 0; i < tmp.size(); ++i) {
+          perm[q0 + i] = (int32_t)(tmp[i] & 0xffffffffu);
+          key[q0 + i] = (int32_t)((tmp[i] >> 48) << 16 | ((tmp[i] >> 32) & 0xffffu));
+        }
+        const int32_t e0 = cq[c], e1 = cq[c + 1];
+        ws[c * 9] = e0;
+        int32_t pos = e0;
+        for (int wv = 1; wv < 8; ++wv) {
+          int32_t target = e0 + (int32_t)(((int64_t)(e1 - e0) * wv) / 8);
+          if (target < pos) target = pos;
+          while (target > e0 && target < e1 && (key[target] >> 16) == (key[target - 1] >> 16))
+            ++target;
+          pos = target;
+          ws[c * 9 + wv] = pos;
+        }
+        ws[c * 9 + 8] = e1;
+      }
+    });
+  }
+  for (auto &t : pool) t.join();
+  p->pnchunks = nch;
+  COPA_HIP(hipMemcpyAsync(p->pcq, cq.data(), (nch + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  COPA_HIP(hipMemcpyAsync(p->pcinfo, cinf.data(), 2 * nch * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  COPA_HIP(hipMemcpyAsync(p->pwsplit, ws.data(), ws.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (P > 0) {
+    COPA_HIP(hipMemcpyAsync(p->perm2, perm.data(), P * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    COPA_HIP(hipMemcpyAsync(p->key2, key.data(), P * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    k_permute_pairs<<<2048, 256, 0, s>>>(p->pairs1, p->perm2, p->key2, P, p->pw, p->pairs2);
+    COPA_HIP(hipGetLastError());
   }
   COPA_HIP(hipStreamSynchronize(s));
   return COPA_OK;
@@ -671,24 +909,43 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, voi
   std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
     return hs[a + 1] - hs[a] > hs[b + 1] - hs[b];
   });
-  auto wave_list = [&](int lanes) {
+  // wave list over subjects in the order `o`: G = 2^lg lanes per subject with about `per` units
+  // of work (visit rows, or projected pairs) per lane
+  auto wave_list = [&](int lanes, const std::vector<int32_t> &o, auto work, int64_t per) {
     std::vector<WaveEntry> w;
     for (int64_t i = 0; i < K;) {
-      int64_t ik = hs[ord[i] + 1] - hs[ord[i]];
+      const int64_t ik = work(o[i]);
       int lg = 0;
-      while ((1 << lg) < lanes && (int64_t)(1 << lg) * 4 < ik) ++lg;
+      while ((1 << lg) < lanes && (int64_t)(1 << lg) * per < ik) ++lg;
       int cnt = (int)std::min<int64_t>(lanes >> lg, K - i);
       w.push_back(WaveEntry{(int32_t)i, lg | (cnt << 8)});
       i += cnt;
     }
     return w;
   };
-  const std::vector<WaveEntry> waves = wave_list(kWave);
-  const std::vector<WaveEntry> waves1 = wave_list(kWave / p->tiles.cg);
+  auto visits = [&](int32_t k) { return hs[k + 1] - hs[k]; };
+  const std::vector<WaveEntry> waves = wave_list(kWave, ord, visits, 4);
+  // pass 1: projected plans stream pairs, so their subjects are ordered and split by pair count
+  std::vector<int32_t> hpp, hpj;
+  std::vector<int32_t> ord1;
+  std::vector<WaveEntry> waves1;
+  if (p->proj) {
+    COPA_TRY(build_pair_lists(X, p, hs, hpp, hpj, s));
+    ord1.resize(K);
+    std::iota(ord1.begin(), ord1.end(), 0);
+    auto pairs = [&](int32_t k) { return (int64_t)(hpp[k + 1] - hpp[k]); };
+    std::stable_sort(ord1.begin(), ord1.end(),
+                     [&](int32_t a, int32_t b) { return pairs(a) > pairs(b); });
+    waves1 = wave_list(kWave / p->tiles.cg, ord1, pairs, 8);
+  } else {
+    ord1 = ord;
+    waves1 = wave_list(kWave / p->tiles.cg, ord, visits, 4);
+  }
   p->n_waves = (int32_t)waves.size();
   p->n_waves1 = (int32_t)waves1.size();
   if (K > 0) {
     COPA_HIP(hipMemcpyAsync(p->order, ord.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    COPA_HIP(hipMemcpyAsync(p->order1, ord1.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
     COPA_HIP(hipMemcpyAsync(p->waves, waves.data(), waves.size() * sizeof(WaveEntry),
                             hipMemcpyHostToDevice, s));
     COPA_HIP(hipMemcpyAsync(p->waves1, waves1.data(), waves1.size() * sizeof(WaveEntry),
@@ -698,13 +955,13 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, voi
     k_row_subject<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(p->subj, p->rowsubj, K);
     COPA_HIP(hipGetLastError());
   }
-  // ---- smoothing basis
+  // ---- smoothing basis (and, for projected plans, the pairs' records)
   std::vector<int32_t> big;
   if (p->l > 0) {
     if (K > 0)
       COPA_TRY(launch_basis(p->l, p->subj, caller_basis ? nullptr : X->days,
                             caller_basis ? X->basis : nullptr, p->C, p->rk, K,
-                            p->opt.basis_rtol, s));
+                            p->opt.basis_rtol, p, s));
   } else {
     // subjects whose eigenproblem min(I_k, R) is larger than a lane can hold
     for (int64_t k = 0; k < K; ++k)
@@ -720,6 +977,7 @@ static copa_status build_plan(const copa_tensor *X, const copa_options *opt, voi
   }
   COPA_HIP(hipMemsetAsync(p->gcount, 0, 8 * sizeof(int32_t), s));
   // ---- feature-sorted chunks for pass 2
+  if (p->proj) COPA_TRY(build_pair_chunks(p, hpp, hpj, s));
   if (p->p2c) COPA_TRY(build_sorted_chunks(X, p, s));
   COPA_HIP(hipMemsetAsync(p->T, 0, p->rows_total * R * sizeof(float), s));
   COPA_HIP(hipMemsetAsync(p->Q, 0, p->rows_total * R * sizeof(float), s));
