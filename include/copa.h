@@ -198,6 +198,17 @@ copa_status copa_loss_grad(copa_plan *plan, const float *H, const float *V, cons
                            const float *Qtilde, float *dH, float *dV, float *dW, float *dS,
                            double *loss, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc), also on plans created without opt->adjoint: the same
+ * loss and gradient as copa_loss_grad, with the adjoint's work memory (2 S R + J R floats plus 4
+ * per 256 subjects' rows block) taken from a static device array of 64 MiB (16 Mi floats) that
+ * the library holds on each GPU it runs on until the process ends. Larger problems return
+ * COPA_EINVAL. Allocates nothing. Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU race (issue them on one stream, or serialise them). Synchronises `stream`. */
+copa_status copa_loss_grad_static(copa_plan *plan, const float *H, const float *V, const float *W,
+                                  const float *Qt, float *dH, float *dV, float *dW, float *dS,
+                                  double *loss, void *stream);
+
 /* Frees every device buffer of the plan (synchronises its device first). NULL is a no-op.   */
 void copa_plan_destroy(copa_plan *plan);
 

@@ -25,7 +25,7 @@ SYMBOLS = ("copa_workspace_bytes", "copa_plan_create", "copa_fit", "copa_mttkrp_
            "copa_plan_basis",
            "copa_loss_grad", "copa_plan_destroy", "copa_rank_supported", "copa_status_string",
            "copa_last_error", "copa_set_timing", "copa_read_timing", "copa_kernel_name",
-           "copa_plan_query", "copa_set_graph", "copa_stationarity")
+           "copa_plan_query", "copa_set_graph", "copa_stationarity", "copa_loss_grad_static")
 NUM_KERNELS = 8
 
 
@@ -84,6 +84,9 @@ def lib():
                                      c_void_p, c_void_p, c_void_p, POINTER(c_double), c_void_p]
         L.copa_stationarity.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                         POINTER(c_double), c_void_p]
+        L.copa_loss_grad_static.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                            c_void_p, c_void_p, c_void_p, c_void_p,
+                                            POINTER(c_double), c_void_p]
         L.copa_plan_destroy.argtypes = [c_void_p]
         L.copa_plan_destroy.restype = None
         L.copa_rank_supported.argtypes = [c_int32]
@@ -96,7 +99,7 @@ def lib():
         L.copa_kernel_name.argtypes = [c_int32]
         L.copa_plan_query.argtypes = [c_void_p, c_int32, POINTER(c_int64)]
         L.copa_kernel_name.restype = ctypes.c_char_p
-        for name in ("copa_workspace_bytes", "copa_plan_create", "copa_fit", "copa_mttkrp_last", "copa_plan_basis",
+        for name in ("copa_loss_grad_static", "copa_workspace_bytes", "copa_plan_create", "copa_fit", "copa_mttkrp_last", "copa_plan_basis",
                      "copa_loss_grad", "copa_rank_supported", "copa_set_timing",
                      "copa_read_timing"):
             getattr(L, name).restype = c_int32
@@ -271,6 +274,20 @@ class Plan:
         _check(lib().copa_loss_grad(self._h, _ptr(H), _ptr(V), _ptr(W), _ptr(Qt), _ptr(dH),
                                     _ptr(dV), _ptr(dW), _ptr(dS), ctypes.byref(loss), _stream()),
                "copa_loss_grad")
+        return loss.value, dH, dV, dW, dS
+
+    def loss_grad_static(self, H, V, W, Qt, want_dS=False):
+        """copa_loss_grad_static: copa_loss_grad without any device allocation (the library's
+        static 64 MiB work array); same return values as loss_grad."""
+        import torch
+        dH, dV, dW = torch.empty_like(H), torch.empty_like(V), torch.empty_like(W)
+        dS = torch.empty((self.K, self.R, self.R), dtype=torch.float32, device=self.device) \
+            if want_dS else None
+        loss = c_double()
+        _check(lib().copa_loss_grad_static(self._h, _ptr(H), _ptr(V), _ptr(W), _ptr(Qt),
+                                           _ptr(dH), _ptr(dV), _ptr(dW), _ptr(dS),
+                                           ctypes.byref(loss), _stream()),
+               "copa_loss_grad_static")
         return loss.value, dH, dV, dW, dS
 
     def stationarity(self, H, V, W, Qt):

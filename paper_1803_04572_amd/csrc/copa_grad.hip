@@ -11,6 +11,7 @@
 //   dL/dS_k  = sum_{i in k} a_i^T (z_i - t_i)                       (-H^T P_k + H^T Pi_k H S_k G)
 //   dL/dW(k,r) = [dL/dS_k]_rr.
 #include <climits>
+#include <mutex>
 
 #include "copa_common.h"
 #include "copa_kernels.h"
@@ -262,26 +263,51 @@ static void launch_scatter_rows(copa_plan *p, const float *U, float *F, hipStrea
   }
 }
 
+// Work buffers of the adjoint: U and D rows (S x R each), F = X^T U (J x R), the per-block loss
+// partials (2 doubles per block of the rows pass).
+struct GradBufs {
+  float *U, *D, *F;
+  double *lpart;
+};
+
+static int grad_blocks(const copa_plan *p) { return std::max(1, (p->n_waves + 3) / 4); }
+
+// floats of one contiguous GradBufs area (the partials 8-byte aligned at its end)
+static size_t grad_floats(const copa_plan *p) {
+  const size_t f = (((size_t)2 * p->S * p->R + (size_t)p->J * p->R) + 1) & ~(size_t)1;
+  return f + (size_t)4 * grad_blocks(p);
+}
+
+static GradBufs grad_bufs_at(const copa_plan *p, float *base) {
+  const size_t f = (((size_t)2 * p->S * p->R + (size_t)p->J * p->R) + 1) & ~(size_t)1;
+  GradBufs b;
+  b.U = base;
+  b.D = base + (size_t)p->S * p->R;
+  b.F = base + (size_t)2 * p->S * p->R;
+  b.lpart = reinterpret_cast<double *>(base + f);
+  return b;
+}
+
 template <int R>
 static copa_status loss_grad_r(copa_plan *p, const float *H, const float *V, const float *W,
                                const float *Qt, float *dH, float *dV, float *dW, float *dS,
-                               hipStream_t s) {
+                               const GradBufs &bf, hipStream_t s) {
   // G = V^T V
   gram<R>(p, V, V, p->J, nullptr, 0, kSlotG, nullptr, 0, 0, s);
   const double *Gm = gram_total(p, kSlotG);
-  float *U = p->gradbuf;
-  float *D = p->gradbuf + (size_t)p->S * R;
-  const int nb = std::max(1, (p->n_waves + 3) / 4);
+  float *U = bf.U;
+  float *D = bf.D;
+  const int nb = grad_blocks(p);
   k_grad_rows<R><<<nb, 256, 0, s>>>(p->waves, p->n_waves, p->order, p->subj, p->row, p->col,
-                                    p->val, V, H, W, Qt, Gm, U, D, dW, p->lpart);
+                                    p->val, V, H, W, Qt, Gm, U, D, dW, bf.lpart);
   // dL/dH = Qt^T D and Psi' = U^T U in one launch
   gram<R>(p, Qt, D, p->S, nullptr, 0, kSlotFH, U, p->S, kSlotG2, s);
   // F = X^T U through the feature-sorted scatter
-  float *F = p->gradbuf + (size_t)2 * p->S * R;
+  float *F = bf.F;
   k_zero_f<<<(unsigned)std::min<int64_t>(1024, (p->J * R + 255) / 256), 256, 0, s>>>(F, p->J * R);
   launch_scatter_rows<R>(p, U, F, s);
   k_grad_finish<R><<<(unsigned)std::max<int64_t>(1, (p->J + 255) / 256), 256, 0, s>>>(
-      p->J, F, V, gram_total(p, kSlotFH), gram_total(p, kSlotG2), 1, p->lpart, nb, p->normX2,
+      p->J, F, V, gram_total(p, kSlotFH), gram_total(p, kSlotG2), 1, bf.lpart, nb, p->normX2,
       dV, dH, p->dloss);
   if (dS && p->K > 0) {
     constexpr int AR = R <= 12 ? R : (128 / R > 0 ? 128 / R : 1);
@@ -301,19 +327,34 @@ static copa_status ensure_grad_buffers(copa_plan *p) {
   return COPA_OK;
 }
 
-copa_status launch_loss_grad(copa_plan *p, const float *H, const float *V, const float *W,
-                             const float *Qt, float *dH, float *dV, float *dW, float *dS,
-                             hipStream_t s) {
-  const copa_status cs = ensure_grad_buffers(p);
-  if (cs != COPA_OK) return cs;
+static copa_status loss_grad_with(copa_plan *p, const float *H, const float *V, const float *W,
+                                  const float *Qt, float *dH, float *dV, float *dW, float *dS,
+                                  const GradBufs &bf, hipStream_t s) {
   switch (p->R) {
 #define CASE(r) \
-  case r: return loss_grad_r<r>(p, H, V, W, Qt, dH, dV, dW, dS, s);
+  case r: return loss_grad_r<r>(p, H, V, W, Qt, dH, dV, dW, dS, bf, s);
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(10) CASE(12) CASE(15)
     CASE(16) CASE(20) CASE(24) CASE(32) CASE(40)
 #undef CASE
     default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
   }
+}
+
+static GradBufs plan_grad_bufs(const copa_plan *p) {
+  GradBufs b;
+  b.U = p->gradbuf;
+  b.D = p->gradbuf + (size_t)p->S * p->R;
+  b.F = p->gradbuf + (size_t)2 * p->S * p->R;
+  b.lpart = p->lpart;
+  return b;
+}
+
+copa_status launch_loss_grad(copa_plan *p, const float *H, const float *V, const float *W,
+                             const float *Qt, float *dH, float *dV, float *dW, float *dS,
+                             hipStream_t s) {
+  const copa_status cs = ensure_grad_buffers(p);
+  if (cs != COPA_OK) return cs;
+  return loss_grad_with(p, H, V, W, Qt, dH, dV, dW, dS, plan_grad_bufs(p), s);
 }
 
 // ======================================================================= stationarity residual
@@ -395,7 +436,7 @@ static copa_status stationarity_r(copa_plan *p, const float *H, const float *V, 
                                   const float *Qt, hipStream_t s) {
   float *dH = p->statbuf, *dV = dH + R * R, *dW = dV + p->J * R;
   double *part = reinterpret_cast<double *>(p->statbuf + p->statfloats);
-  copa_status cs = loss_grad_r<R>(p, H, V, W, Qt, dH, dV, dW, nullptr, s);
+  copa_status cs = loss_grad_r<R>(p, H, V, W, Qt, dH, dV, dW, nullptr, plan_grad_bufs(p), s);
   if (cs != COPA_OK) return cs;
   // W^T W into a slot the adjoint no longer needs (its V^T V stays in kSlotG)
   gram<R>(p, W, W, p->K, nullptr, 0, kSlotFH, nullptr, 0, 0, s);
@@ -458,4 +499,62 @@ extern "C" copa_status copa_stationarity(copa_plan *p, const float *H, const flo
   hipStream_t s = (hipStream_t)stream;
   COPA_HIP(hipSetDevice(p->device));
   return launch_stationarity(p, H, V, W, Qt, res, s);
+}
+
+// ======================================================================= no-allocation adjoint
+// Work memory of copa_loss_grad_static: a file-scope device array, one copy per GPU, that every
+// call on that GPU reuses (it keeps the last call's contents; calls that overlap on one GPU race
+// on it). Host code never passes the array's name to a kernel: the device address of each GPU's
+// copy comes from hipGetSymbolAddress on that call's first use of the device.
+namespace copa {
+constexpr size_t kStaticScratchFloats = (size_t)16 << 20;  // 64 MiB
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
+static std::mutex g_scratch_mutex;
+static float *g_scratch_ptr[64] = {};
+
+static copa_status scratch_address(int device, float **out) {
+  if (device < 0 || device >= 64) {
+    set_error("device index outside 0..63");
+    return COPA_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return COPA_EDEVICE;
+    }
+    g_scratch_ptr[device] = static_cast<float *>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return COPA_OK;
+}
+}  // namespace copa
+
+extern "C" copa_status copa_loss_grad_static(copa_plan *p, const float *H, const float *V,
+                                             const float *W, const float *Qt, float *dH,
+                                             float *dV, float *dW, float *dS, double *loss,
+                                             void *stream) {
+  if (!p || !H || !V || !Qt || !dH || !dV || !loss || (p->K > 0 && (!W || !dW))) {
+    set_error("NULL argument");
+    return COPA_EINVAL;
+  }
+  const size_t need = grad_floats(p);
+  if (need > kStaticScratchFloats) {
+    set_error("copa_loss_grad_static needs " + std::to_string(need) +
+              " floats of work memory (2 S R + J R + 4 per rows-pass block); its static scratch "
+              "holds " + std::to_string(kStaticScratchFloats) + " (64 MiB)");
+    return COPA_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  COPA_HIP(hipSetDevice(p->device));
+  float *base = nullptr;
+  copa_status st = scratch_address(p->device, &base);
+  if (st != COPA_OK) return st;
+  st = loss_grad_with(p, H, V, W, Qt, dH, dV, dW, dS, grad_bufs_at(p, base), s);
+  if (st != COPA_OK) return st;
+  COPA_HIP(hipMemcpyAsync(loss, p->dloss, sizeof(double), hipMemcpyDeviceToHost, s));
+  COPA_HIP(hipStreamSynchronize(s));
+  return COPA_OK;
 }
