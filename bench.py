@@ -177,6 +177,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c4")
     ap.add_argument("--R", type=int, default=None, help="rank (default: the workload's)")
+    ap.add_argument("--precision", choices=("fp32", "mixed"), default="fp32",
+                    help="mixed: bfloat16 records of the projected data, FP32 accumulation, one "
+                         "FP32 refinement iteration per fit call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (HBM counter scaling)")
@@ -201,7 +204,10 @@ def main():
     coh, cfg = load_or_make(args.workload, args.cache, progress)
     R, l = args.R or cfg["R"], cfg["l"]
     progress(f"K={coh.K} S={coh.S} nnz={coh.nnz} R={R}; creating the plan")
-    plan = copa.Plan.from_cohort(coh, R=R, l=l, inner_iters=cfg["inner"])
+    mixed = args.precision == "mixed"
+    plan = copa.Plan.from_cohort(coh, R=R, l=l, inner_iters=cfg["inner"],
+                                 precision=copa.PREC_MIXED if mixed else copa.PREC_FP32,
+                                 mixed_refine=1)
     progress("plan ready")
     H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
     init = plan.new_state(H0, W0, V0)
@@ -234,7 +240,7 @@ def main():
         hist = rc["fit_history"]
         Hf, Vf = chk["H"].double().cpu().numpy(), chk["V"].double().cpu().numpy()
         del chk
-    gate = golden_check(args.workload, R, coh, hist, Hf, Vf, tol=1e-5)
+    gate = golden_check(args.workload, R, coh, hist, Hf, Vf, tol=1e-4 if mixed else 1e-5)
     progress(f"gate: {gate}")
 
     # the same number of steps again with HIP events around every kernel launch
@@ -247,6 +253,7 @@ def main():
     plan.set_timing(False)
 
     compact = plan.query("compact")
+    npairs = plan.query("pairs")
     abytes = algorithmic_bytes(coh, R, l, compact)
     per_kernel = {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in timing.items()
                   if n > 0}
@@ -256,7 +263,8 @@ def main():
             v["GBps"] = abytes[k] / (v["avg_us"] * 1e-6) / 1e9
     dom = max((k for k in per_kernel if k in abytes), key=lambda k: per_kernel[k]["avg_us"])
     ach = per_kernel[dom]["GBps"]
-    traffic = measured_traffic(dom, args.workload if args.R is None else f"{args.workload}_R{R}")
+    traffic = measured_traffic(dom, args.workload + ("" if args.R is None else f"_R{R}")
+                               + ("_mixed" if mixed else ""))
     if args.copy_probe:
         # a plain elementwise kernel of known size for the HBM counters' scale: reads and writes
         # 256 MiB once per launch
@@ -289,13 +297,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16-in/f32-acc" if mixed else "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['name'].replace(' R=' + str(cfg['R']), '')} R={R}",
                    "K": coh.K, "J": coh.J, "R": R, "l": l, "S": coh.S, "nnz": coh.nnz,
                    "outer_iters": gold_iters, "inner_iters": cfg["inner"],
                    "constraints": "H free, W nonneg, V l1 (lambda 0.1), cubic spline smoothing",
-                   "nonzeros": "compact 4-byte (lossless)" if compact else "fp32 8-byte"},
+                   "nonzeros": "compact 4-byte (lossless)" if compact else "fp32 8-byte",
+                   "streamed": (f"projected pairs C_k^T X_k ({npairs} records, "
+                                + ("16-byte bfloat16" if mixed else "32-byte FP32") + ")")
+                   if npairs else "nonzeros and basis rows",
+                   "precision": args.precision},
         "gate": gate,
         "value_if_ungated": value,
         "fit": rep["fit"],

@@ -81,11 +81,14 @@ typedef struct copa_tensor {
 } copa_tensor;
 
 /* Arithmetic of the streaming passes (copa_options.precision).
- *   FP32   every product and sum of the passes in FP32, the Procrustes eigenproblems, Grams and
+ *   FP32   the MTTKRP and SpMM inputs (nonzeros, basis rows or the projected data C_k^T X_k, and
+ *          the factor rows) in FP32, FP32 accumulation; the Procrustes eigenproblems, Grams and
  *          ADMM systems in FP64
- *   MIXED  the factor rows the passes gather (V in pass 1, the u rows in pass 2) stored as
- *          bfloat16 pairs hi + lo (hi = bf16(x), lo = bf16(x - hi)), FP32 accumulation; the
- *          products with lo are the FP32 residual refinement of the products with hi           */
+ *   MIXED  the projected data C_k^T X_k held a second time as bfloat16 (16-byte records, half
+ *          the bytes each pass streams) with FP32 accumulation; the last mixed_refine iterations
+ *          of each copa_fit call stream the FP32 records again (refinement), so that the returned
+ *          factors, MTTKRPs and FIT come from FP32 inputs. Needs smoothing with l <= 7, J <= 65536
+ *          and at most two nonzeros per visit row on average (COPA_EUNSUPPORTED otherwise).   */
 typedef enum { COPA_PREC_FP32 = 0, COPA_PREC_MIXED = 1 } copa_precision;
 
 /* Fit options. R: target rank (this build: 1..64 from the list copa_rank_supported accepts).
@@ -106,6 +109,7 @@ typedef struct copa_options {
   double stop_tol;
   int32_t check_every;
   int32_t precision;     /* copa_precision; 0 = FP32                                          */
+  int32_t mixed_refine;  /* MIXED: final iterations per copa_fit call on FP32 records (>= 0)  */
   /* 1: every reduction in a fixed order (no floating-point atomics), so that two runs on the
    * same inputs give bitwise equal results. Needs the chunked pass 2 (J <= 65536 and a F_V tile
    * that fits LDS); the plan is refused with COPA_EUNSUPPORTED otherwise.                     */

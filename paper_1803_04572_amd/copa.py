@@ -40,7 +40,8 @@ class CopaOptions(ctypes.Structure):
                 ("prox_W", c_int32), ("prox_V", c_int32), ("lambda_H", c_double),
                 ("lambda_W", c_double), ("lambda_V", c_double), ("rank_rtol", c_double),
                 ("basis_rtol", c_double), ("stop_tol", c_double), ("check_every", c_int32),
-                ("precision", c_int32), ("deterministic", c_int32), ("adjoint", c_int32)]
+                ("precision", c_int32), ("mixed_refine", c_int32), ("deterministic", c_int32),
+                ("adjoint", c_int32)]
 
 
 class CopaState(ctypes.Structure):
@@ -140,7 +141,8 @@ class Plan:
     def __init__(self, subj_ptr, row_ptr, col, val, days, J, l, R, inner_iters=5,
                  prox=(PROX_NONE, PROX_NONNEG, PROX_L1), lam=(0.0, 0.0, 0.1), rank_rtol=1e-6,
                  basis_rtol=1e-10, stop_tol=0.0, check_every=10, basis=None,
-                 precision=PREC_FP32, deterministic=False, adjoint=False, workspace="library"):
+                 precision=PREC_FP32, mixed_refine=1, deterministic=False, adjoint=False,
+                 workspace="library"):
         """workspace: "library" (the library allocates it once) or "caller" (a torch uint8
         tensor of copa_workspace_bytes bytes, kept by this object)."""
         import torch
@@ -157,8 +159,8 @@ class Plan:
                         lambda_W=float(lam[1]), lambda_V=float(lam[2]),
                         rank_rtol=float(rank_rtol), basis_rtol=float(basis_rtol),
                         stop_tol=float(stop_tol), check_every=int(check_every),
-                        precision=int(precision), deterministic=int(bool(deterministic)),
-                        adjoint=int(bool(adjoint)))
+                        precision=int(precision), mixed_refine=int(mixed_refine),
+                        deterministic=int(bool(deterministic)), adjoint=int(bool(adjoint)))
         self._ws = None
         ws_ptr, ws_bytes = None, 0
         if workspace == "caller":
@@ -180,6 +182,7 @@ class Plan:
         t = CopaTensor(K=K, J=J, S=S, nnz=nnz, l=l)
         o = CopaOptions(R=R, inner_iters=int(opts.get("inner_iters", 5)), prox_H=0, prox_W=1,
                         prox_V=2, lambda_V=0.1, precision=int(opts.get("precision", PREC_FP32)),
+                        mixed_refine=int(opts.get("mixed_refine", 1)),
                         deterministic=int(bool(opts.get("deterministic", False))),
                         adjoint=int(bool(opts.get("adjoint", False))),
                         stop_tol=float(opts.get("stop_tol", 0.0)))

@@ -125,6 +125,11 @@ struct copa_plan {
   float *nzx = nullptr;       // [nnz] its value
   int32_t *perm2 = nullptr;   // [npairs] pairs1 index of each pairs2 record
   int32_t *key2 = nullptr;    // [npairs] pairs2 keys
+  // mixed precision: the same records as 16-byte bfloat16 records (pass 2: the feature ids apart)
+  uint4 *pairs1h = nullptr;   // [npairs] by subject; tag = feature id
+  uint4 *pairs2h = nullptr;   // [npairs] pass-2 order; tag = subject within the chunk
+  uint16_t *feat2h = nullptr; // [npairs] feature id of each pass-2 record
+  bool use_bf = false;        // the launches being issued stream the bfloat16 records
   int pnchunks = 0;
   int pchunks_cap = 0;
   int32_t *pcq = nullptr;     // [pnchunks+1] pair offsets of the chunks
@@ -162,6 +167,8 @@ struct copa_plan {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
   copa_state gstate{};
+  hipGraphExec_t gexec_bf = nullptr;  // the same for the mixed-precision iteration
+  copa_state gstate_bf{};
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_kid;

@@ -157,10 +157,13 @@ static bool same_state(const copa_state &a, const copa_state &b) {
 // once per plan and state buffers on the plan's own stream (so that the caller's stream may be
 // the null stream) and launched on s. None of the captured launches is a memset or a copy.
 static copa_status run_chunk_graph(copa_plan *p, const copa_state *st, int chunk, hipStream_t s) {
-  if (!p->gexec || !same_state(p->gstate, *st)) {
-    if (p->gexec) {
-      COPA_HIP(hipGraphExecDestroy(p->gexec));
-      p->gexec = nullptr;
+  // one captured iteration per record precision (mixed-precision plans replay both)
+  hipGraphExec_t &gx = p->use_bf ? p->gexec_bf : p->gexec;
+  copa_state &gs = p->use_bf ? p->gstate_bf : p->gstate;
+  if (!gx || !same_state(gs, *st)) {
+    if (gx) {
+      COPA_HIP(hipGraphExecDestroy(gx));
+      gx = nullptr;
     }
     if (!p->cap_stream) COPA_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
@@ -172,12 +175,12 @@ static copa_status run_chunk_graph(copa_plan *p, const copa_state *st, int chunk
       return cs;
     }
     COPA_HIP(e);
-    const hipError_t ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+    const hipError_t ei = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     COPA_HIP(ei);
-    p->gstate = *st;
+    gs = *st;
   }
-  for (int t = 0; t < chunk; ++t) COPA_HIP(hipGraphLaunch(p->gexec, s));
+  for (int t = 0; t < chunk; ++t) COPA_HIP(hipGraphLaunch(gx, s));
   return launch_fit(p, st, s);
 }
 
@@ -214,9 +217,15 @@ copa_status copa_fit(copa_plan *p, copa_state *st, int32_t iters, float *Qtilde,
   const bool check = p->opt.stop_tol > 0.0;
   const int every = p->opt.check_every > 0 ? p->opt.check_every : 10;
   double stat = -1.0;
+  // mixed precision: the iterations stream the bfloat16 records, except the last mixed_refine of
+  // the call, which stream the FP32 records (refinement)
+  const bool mixed = p->opt.precision == COPA_PREC_MIXED && p->proj;
+  const int n_bf = mixed ? std::max(0, iters - p->opt.mixed_refine) : 0;
   while (done < iters) {
     int chunk = std::min(iters - done, p->timing ? kTimingChunk : kHistCap);
     if (check) chunk = std::min(chunk, every);
+    p->use_bf = done < n_bf;
+    if (p->use_bf) chunk = std::min(chunk, n_bf - done);
     if (done > 0) k_reset_scalars<<<1, 64, 0, s>>>(p->scal);
     if (p->use_graph && !p->timing) {
       cs = run_chunk_graph(p, st, chunk, s);
@@ -249,6 +258,7 @@ copa_status copa_fit(copa_plan *p, copa_state *st, int32_t iters, float *Qtilde,
       if (stat < p->opt.stop_tol) break;
     }
   }
+  p->use_bf = false;
   if (Qtilde) {
     cs = launch_qtilde(p, Qtilde, s);
     if (cs != COPA_OK) return cs;

@@ -235,10 +235,10 @@ __global__ void __launch_bounds__(256)
 // of C_k^T X_k. Same persistent blocks, LDS-staged tiles, lane groups and reduce-scatter as
 // k_pass1; a lane streams every G-th pair of its subject, four records in flight, with no
 // dependent loads (a pair carries its feature id).
-template <int RT, int PW>
+template <int RT, int PW, bool BF>
 __global__ void __launch_bounds__(256)
     k_pass1p(const WaveEntry *__restrict__ waves, int n_waves, const int32_t *__restrict__ order,
-             const int32_t *__restrict__ pp, const float *__restrict__ recs,
+             const int32_t *__restrict__ pp, const void *__restrict__ recs,
              const float *__restrict__ Vp, int64_t J, int R, int l, int cg,
              float *__restrict__ T, float *__restrict__ FV, FitScalars *sc) {
   constexpr int RTP = row4(RT);
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(256)
     for (int q = p0 + sub; q < p1; q += 4 * G) {
       float f[4][PW];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) load_rec<PW>(recs, q + u * G < p1 ? q + u * G : q, f[u]);
+      for (int u = 0; u < 4; ++u) fetch_rec<BF, PW>(recs, nullptr, q + u * G < p1 ? q + u * G : q, f[u]);
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         if (q + u * G < p1) take(f[u]);
@@ -1790,14 +1790,18 @@ static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
                                               p->row, p->col, p->val, p->xc, p->C, p->Vp, p->J, \
                                               p->R, p->l, cg, p->T, p->FV, p->scal)
   if (p->proj) {
-    if (p->pw == 8)
-      k_pass1p<RT, 8><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1, p->pp,
-                                                p->pairs1, p->Vp, p->J, p->R, p->l, cg, p->T,
-                                                p->FV, p->scal);
+    if (p->use_bf)
+      k_pass1p<RT, 8, true><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1, p->pp,
+                                                      p->pairs1h, p->Vp, p->J, p->R, p->l, cg,
+                                                      p->T, p->FV, p->scal);
+    else if (p->pw == 8)
+      k_pass1p<RT, 8, false><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1, p->pp,
+                                                       p->pairs1, p->Vp, p->J, p->R, p->l, cg,
+                                                       p->T, p->FV, p->scal);
     else
-      k_pass1p<RT, 12><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1, p->pp,
-                                                 p->pairs1, p->Vp, p->J, p->R, p->l, cg, p->T,
-                                                 p->FV, p->scal);
+      k_pass1p<RT, 12, false><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1, p->pp,
+                                                        p->pairs1, p->Vp, p->J, p->R, p->l, cg,
+                                                        p->T, p->FV, p->scal);
   } else if (p->l > 0) {
     if (p->compact) P1(true, true); else P1(true, false);
   } else {

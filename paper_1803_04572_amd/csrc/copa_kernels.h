@@ -482,18 +482,48 @@ __device__ __forceinline__ void load_rec(const float *__restrict__ recs, int64_t
   }
 }
 
+// Mixed precision: a 16-byte record of seven bfloat16 entries and a 16-bit tag (entry a in bits
+// 16 (a & 1) of word a / 2, the tag in the high half of the last word). Unpacked into the layout
+// of the FP32 records (PW = 8): f[0..6] the entries as FP32 (exact), f[7] the key bits, which are
+// the tag (pass 1: the feature id) or, with `hi` given, hi[q] << 16 | tag (pass 2: feature and
+// subject within the chunk).
+__device__ __forceinline__ void load_rec_bf(const uint4 *__restrict__ recs,
+                                            const uint16_t *__restrict__ hi, int64_t q,
+                                            float (&f)[8]) {
+  const uint4 w = recs[q];
+  const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int a = 0; a < 7; ++a)
+    f[a] = __uint_as_float((a & 1) ? (ws[a >> 1] & 0xffff0000u) : (ws[a >> 1] << 16));
+  const uint32_t tag = w.w >> 16;
+  f[7] = __uint_as_float(hi ? ((uint32_t)hi[q] << 16 | tag) : tag);
+}
+
+// the record of pair q as FP32 (BF: unpacked from the 16-byte mixed-precision form)
+template <bool BF, int PW>
+__device__ __forceinline__ void fetch_rec(const void *__restrict__ recs,
+                                          const uint16_t *__restrict__ hi, int64_t q,
+                                          float (&f)[PW]) {
+  if constexpr (BF) {
+    static_assert(PW == 8, "mixed-precision records hold seven entries");
+    load_rec_bf(static_cast<const uint4 *>(recs), hi, q, f);
+  } else {
+    load_rec<PW>(static_cast<const float *>(recs), q, f);
+  }
+}
+
 // Pass 2 on the projected pairs: F_V(j, :) += x'_j M_k for every pair (k, j), with the M rows of
 // a chunk's subjects staged in LDS. A chunk is a run of at most kChunkRows / l subjects whose
 // pairs are sorted by feature (key = feature << 16 | subject within the chunk) and cut into
 // eight wave slices on feature boundaries; each lane sums a contiguous run of its wave's slice
 // feature by feature, and the segmented scan over lanes of k_pass2c joins runs that share a
 // feature, so each feature is added to the block's LDS copy of F_V by one lane.
-template <int RT, int PW>
+template <int RT, int PW, bool BF>
 __global__ void __launch_bounds__(512)
     k_pass2p(int nchunks, const int32_t *__restrict__ cq, const int32_t *__restrict__ cinfo,
-             const int32_t *__restrict__ wsplit, const float *__restrict__ recs,
-             const float *__restrict__ M, int64_t J, int R, int l, float *__restrict__ FV,
-             float *__restrict__ part) {
+             const int32_t *__restrict__ wsplit, const void *__restrict__ recs,
+             const uint16_t *__restrict__ feat_hi, const float *__restrict__ M, int64_t J, int R,
+             int l, float *__restrict__ FV, float *__restrict__ part) {
   constexpr int RTP = row4(RT);
   constexpr int PF = 4;  // records per lane loaded ahead of the chunk's M staging
   extern __shared__ float4 smem4[];
@@ -520,7 +550,7 @@ __global__ void __launch_bounds__(512)
     const int b = a + per < s1 ? a + per : s1;
     float pre[PF][PW];
 #pragma unroll
-    for (int u = 0; u < PF; ++u) load_rec<PW>(recs, a + u < b ? a + u : 0, pre[u]);
+    for (int u = 0; u < PF; ++u) fetch_rec<BF, PW>(recs, feat_hi, a + u < b ? a + u : 0, pre[u]);
     {
       // the chunk's M block (nsub l rows of RT floats), 4 loads in flight per thread
       const int nm = nsub * l * RT;
@@ -585,7 +615,7 @@ __global__ void __launch_bounds__(512)
     for (int e = a + PF; e < b; e += PF) {
       float f[PF][PW];
 #pragma unroll
-      for (int u = 0; u < PF; ++u) load_rec<PW>(recs, e + u < b ? e + u : e, f[u]);
+      for (int u = 0; u < PF; ++u) fetch_rec<BF, PW>(recs, feat_hi, e + u < b ? e + u : e, f[u]);
 #pragma unroll
       for (int u = 0; u < PF; ++u)
         if (e + u < b) take(f[u]);
@@ -648,12 +678,18 @@ inline void launch_pass2p(const copa_plan *p, float *F, hipStream_t s) {
   const dim3 grid((unsigned)gx, (unsigned)p->tiles2.nt);
   const size_t lds = ((size_t)p->J * row4(RT) + (size_t)kChunkRows * row4(RT) + 4) * sizeof(float);
   float *part = p->opt.deterministic ? p->fvpart : nullptr;
-  if (p->pw == 8)
-    k_pass2p<RT, 8><<<grid, 512, lds, s>>>(p->pnchunks, p->pcq, p->pcinfo, p->pwsplit, p->pairs2,
-                                            p->M, p->J, p->R, p->l, F, part);
+  if (p->use_bf)
+    k_pass2p<RT, 8, true><<<grid, 512, lds, s>>>(p->pnchunks, p->pcq, p->pcinfo, p->pwsplit,
+                                                  p->pairs2h, p->feat2h, p->M, p->J, p->R, p->l,
+                                                  F, part);
+  else if (p->pw == 8)
+    k_pass2p<RT, 8, false><<<grid, 512, lds, s>>>(p->pnchunks, p->pcq, p->pcinfo, p->pwsplit,
+                                                   p->pairs2, nullptr, p->M, p->J, p->R, p->l, F,
+                                                   part);
   else
-    k_pass2p<RT, 12><<<grid, 512, lds, s>>>(p->pnchunks, p->pcq, p->pcinfo, p->pwsplit,
-                                             p->pairs2, p->M, p->J, p->R, p->l, F, part);
+    k_pass2p<RT, 12, false><<<grid, 512, lds, s>>>(p->pnchunks, p->pcq, p->pcinfo, p->pwsplit,
+                                                    p->pairs2, nullptr, p->M, p->J, p->R, p->l, F,
+                                                    part);
   if (part) {
     const int64_t n = p->J * p->R;
     k_fv_sum<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256)), 256, 0,

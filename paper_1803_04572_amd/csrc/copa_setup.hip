@@ -337,6 +337,33 @@ __global__ void __launch_bounds__(64) k_basis(const int32_t *subj, const double 
   }
 }
 
+// FP32 -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// 16-byte mixed-precision records of both pair orders (see load_rec_bf)
+__global__ void k_pack_bf16_pairs(const float *__restrict__ recs1, const float *__restrict__ recs2,
+                                  int64_t n, uint4 *__restrict__ h1, uint4 *__restrict__ h2,
+                                  uint16_t *__restrict__ feat2) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    for (int which = 0; which < 2; ++which) {
+      const float *r = (which ? recs2 : recs1) + q * 8;
+      const uint32_t key = __float_as_uint(r[7]);
+      const uint32_t tag = which ? (key & 0xffffu) : key;
+      uint4 w;
+      w.x = bf16_bits(r[0]) | bf16_bits(r[1]) << 16;
+      w.y = bf16_bits(r[2]) | bf16_bits(r[3]) << 16;
+      w.z = bf16_bits(r[4]) | bf16_bits(r[5]) << 16;
+      w.w = bf16_bits(r[6]) | tag << 16;
+      (which ? h2 : h1)[q] = w;
+      if (which) feat2[q] = (uint16_t)(key >> 16);
+    }
+  }
+}
+
 // pairs2[q] = pairs1[perm[q]] with the key replaced by key2[q]
 __global__ void k_permute_pairs(const float *__restrict__ recs1, const int32_t *__restrict__ perm,
                                 const int32_t *__restrict__ key2, int64_t n, int pw,
@@ -511,6 +538,11 @@ static copa_status carve_all(copa_plan *p, bool dry) {
     COPA_TRY(take(&p->nzx, nnz));
     COPA_TRY(take(&p->perm2, pcap));
     COPA_TRY(take(&p->key2, pcap));
+    if (p->opt.precision == COPA_PREC_MIXED) {
+      COPA_TRY(take(&p->pairs1h, pcap));
+      COPA_TRY(take(&p->pairs2h, pcap));
+      COPA_TRY(take(&p->feat2h, pcap));
+    }
     const size_t nch = (size_t)p->pchunks_cap;
     COPA_TRY(take(&p->pcq, nch + 1));
     COPA_TRY(take(&p->pcinfo, 2 * nch));
@@ -787,6 +819,11 @@ static copa_status build_pair_chunks(copa_plan *p, const std::vector<int32_t> &h
     COPA_HIP(hipMemcpyAsync(p->key2, key.data(), P * sizeof(int32_t), hipMemcpyHostToDevice, s));
     k_permute_pairs<<<2048, 256, 0, s>>>(p->pairs1, p->perm2, p->key2, P, p->pw, p->pairs2);
     COPA_HIP(hipGetLastError());
+    if (p->opt.precision == COPA_PREC_MIXED) {
+      k_pack_bf16_pairs<<<2048, 256, 0, s>>>(p->pairs1, p->pairs2, P, p->pairs1h, p->pairs2h,
+                                             p->feat2h);
+      COPA_HIP(hipGetLastError());
+    }
   }
   COPA_HIP(hipStreamSynchronize(s));
   return COPA_OK;
@@ -996,6 +1033,7 @@ using namespace copa;
 static void free_plan(copa_plan *p) {
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->gexec_bf) (void)hipGraphExecDestroy(p->gexec_bf);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->arena_owned && p->arena) (void)hipFree(p->arena);
   delete p;
@@ -1067,9 +1105,16 @@ static copa_status check_args(const copa_tensor *X, const copa_options *opt, boo
     set_error("unknown precision");
     return COPA_EINVAL;
   }
-  if (opt->precision == COPA_PREC_MIXED) {
-    set_error("mixed precision is not available in this build");
+  if (opt->precision == COPA_PREC_MIXED && (X->l < 1 || X->l > 7 || X->J > 65536 ||
+                                              X->nnz > 2 * X->S || X->nnz == 0)) {
+    set_error("mixed precision streams bfloat16 records of the projected data C_k^T X_k: it needs "
+              "smoothing with l <= 7, J <= 65536 and at most two nonzeros per visit row on "
+              "average");
     return COPA_EUNSUPPORTED;
+  }
+  if (opt->mixed_refine < 0) {
+    set_error("mixed_refine must be >= 0");
+    return COPA_EINVAL;
   }
   return COPA_OK;
 }
