@@ -254,6 +254,8 @@ def main():
 
     compact = plan.query("compact")
     npairs = plan.query("pairs")
+    shapes = {k: plan.query(k) for k in ("tuned", "pass1_blocks_per_cu", "procrustes_variant",
+                                         "gram_blocks", "pass2_blocks")}
     abytes = algorithmic_bytes(coh, R, l, compact)
     per_kernel = {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in timing.items()
                   if n > 0}
@@ -309,6 +311,7 @@ def main():
                    if npairs else "nonzeros and basis rows",
                    "precision": args.precision},
         "gate": gate,
+        "launch_shapes": shapes,
         "value_if_ungated": value,
         "fit": rep["fit"],
         "mttkrp_hbm": mttkrp,

@@ -117,6 +117,13 @@ typedef struct copa_options {
   /* 1: the workspace also holds the buffers of copa_loss_grad and copa_stationarity (2 S R +
    * J R floats and S R floats more). Implied by stop_tol > 0.                                 */
   int32_t adjoint;
+  /* 1: the first copa_fit on the plan picks the launch shapes (pass-1 blocks per compute unit,
+   * the Procrustes kernel variant for smoothed R > 16, row-Gram blocks, pass-2 grid width) by
+   * timing the candidates on the fit's starting point, or reads them from the file named by the
+   * environment variable COPA_TUNE_CACHE (lines "<J> <R> <l> <projected> <precision> <log2 K>
+   * <compute units> : <four shapes>"; tuned shapes are appended there). Not with deterministic
+   * = 1, whose fixed summation order needs fixed shapes. 0: fixed default shapes.            */
+  int32_t autotune;
 } copa_options;
 
 /* Fit state, device memory owned by the caller, FP32 row-major. In: the starting point
@@ -253,12 +260,21 @@ const char *copa_kernel_name(int32_t id);
  *   COPA_QUERY_WAVES    number of pass-1 wave entries,
  *   COPA_QUERY_PAIRS    number of (subject, feature) pairs of the projected data C_k^T X_k that
  *                       the passes stream (smoothed plans with at most two nonzeros per visit
- *                       row on average), or 0 when they stream the nonzeros and basis rows.
+ *                       row on average), or 0 when they stream the nonzeros and basis rows,
+ *   COPA_QUERY_TUNED    0 launch shapes not tuned (yet), 1 timed on this plan, 2 read from the
+ *                       tuning cache file,
+ *   COPA_QUERY_PASS1_BLOCKS_PER_CU, COPA_QUERY_PROCRUSTES_VARIANT, COPA_QUERY_GRAM_BLOCKS,
+ *   COPA_QUERY_PASS2_BLOCKS   the launch shapes in use (see copa_options.autotune).
  * *out (host) receives the value. COPA_EINVAL for a NULL argument or an unknown `what`.       */
 #define COPA_QUERY_COMPACT 0
 #define COPA_QUERY_CHUNKS 1
 #define COPA_QUERY_WAVES 2
 #define COPA_QUERY_PAIRS 3
+#define COPA_QUERY_TUNED 4
+#define COPA_QUERY_PASS1_BLOCKS_PER_CU 5
+#define COPA_QUERY_PROCRUSTES_VARIANT 6
+#define COPA_QUERY_GRAM_BLOCKS 7
+#define COPA_QUERY_PASS2_BLOCKS 8
 copa_status copa_plan_query(const copa_plan *plan, int32_t what, int64_t *out);
 
 /* 1 if this build has kernels for rank R, else 0.                                           */

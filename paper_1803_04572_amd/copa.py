@@ -41,7 +41,7 @@ class CopaOptions(ctypes.Structure):
                 ("lambda_W", c_double), ("lambda_V", c_double), ("rank_rtol", c_double),
                 ("basis_rtol", c_double), ("stop_tol", c_double), ("check_every", c_int32),
                 ("precision", c_int32), ("mixed_refine", c_int32), ("deterministic", c_int32),
-                ("adjoint", c_int32)]
+                ("adjoint", c_int32), ("autotune", c_int32)]
 
 
 class CopaState(ctypes.Structure):
@@ -142,7 +142,7 @@ class Plan:
                  prox=(PROX_NONE, PROX_NONNEG, PROX_L1), lam=(0.0, 0.0, 0.1), rank_rtol=1e-6,
                  basis_rtol=1e-10, stop_tol=0.0, check_every=10, basis=None,
                  precision=PREC_FP32, mixed_refine=1, deterministic=False, adjoint=False,
-                 workspace="library"):
+                 autotune=True, workspace="library"):
         """workspace: "library" (the library allocates it once) or "caller" (a torch uint8
         tensor of copa_workspace_bytes bytes, kept by this object)."""
         import torch
@@ -160,7 +160,8 @@ class Plan:
                         rank_rtol=float(rank_rtol), basis_rtol=float(basis_rtol),
                         stop_tol=float(stop_tol), check_every=int(check_every),
                         precision=int(precision), mixed_refine=int(mixed_refine),
-                        deterministic=int(bool(deterministic)), adjoint=int(bool(adjoint)))
+                        deterministic=int(bool(deterministic)), adjoint=int(bool(adjoint)),
+                        autotune=int(bool(autotune)))
         self._ws = None
         ws_ptr, ws_bytes = None, 0
         if workspace == "caller":
@@ -304,7 +305,9 @@ class Plan:
         """Plan layout facts: 'compact' (pass 1 reads the lossless 4-byte nonzeros), 'chunks'
         (pass-2 chunks), 'waves' (pass-1 wave entries), 'pairs' (projected (subject, feature)
         pairs the passes stream; 0 when they stream nonzeros and basis rows)."""
-        code = {"compact": 0, "chunks": 1, "waves": 2, "pairs": 3}[what]
+        code = {"compact": 0, "chunks": 1, "waves": 2, "pairs": 3, "tuned": 4,
+                "pass1_blocks_per_cu": 5, "procrustes_variant": 6, "gram_blocks": 7,
+                "pass2_blocks": 8}[what]
         out = c_int64(0)
         _check(lib().copa_plan_query(self._h, code, ctypes.byref(out)), "copa_plan_query")
         return int(out.value)

@@ -175,6 +175,13 @@ struct copa_plan {
   int ev_used = 0;
   double t_ms[copa::kNumKernels] = {};
   int64_t t_cnt[copa::kNumKernels] = {};
+  // launch shapes (set by the autotuner at the first copa_fit, else the defaults below)
+  int p1_per_cu = 4;         // pass-1 persistent blocks per compute unit (LDS permitting)
+  int proc_variant = 0;      // smoothed R > 16 Procrustes: 0 lane-per-subject blocks, 1 four-wavefront blocks
+  int p2_blocks = 0;         // pass-2 grid width (<= p2_blocks_cap)
+  int gram_blocks = 0;       // row-Gram blocks (<= gmaxnb)
+  int tuned = 0;             // 0 not yet, 1 timed on this plan, 2 read from the cache file
+  float tune_ms = 0.0f;      // time the tuner took
   bool adjoint = false;      // the workspace holds the adjoint's buffers
   float *gradbuf = nullptr; // [2 x S x R + J x R] U and D rows and F of the adjoint
   float *statbuf = nullptr; // dH, dV, dW and the stationarity partials
@@ -211,6 +218,7 @@ copa_status launch_iteration(copa_plan *p, const copa_state *st, hipStream_t s);
 copa_status launch_fit(copa_plan *p, const copa_state *st, hipStream_t s);
 copa_status launch_init_grams(copa_plan *p, const copa_state *st, hipStream_t s);
 copa_status launch_qtilde(copa_plan *p, float *Qt, hipStream_t s);
+copa_status launch_tune(copa_plan *p, const copa_state *st, hipStream_t s);
 copa_status harvest_timing(copa_plan *p);
 extern const char *const kernel_names[kNumKernels];
 bool rank_supported(int R);

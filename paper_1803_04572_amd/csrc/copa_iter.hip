@@ -17,6 +17,11 @@
 //   mode_V_prep G_V = H^TH * W^TW, rho, FP64 Cholesky
 //   v_admm      inner ADMM on V rows, FIT/penalty/sparsity partials
 //   gram(V), finalize  V^T V, FIT = 1 - (|X|^2 - 2<F_V,V> + <Psi, V^T V>) / |X|^2
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
 #include "copa_iter_impl.h"
 
 namespace copa {
@@ -119,6 +124,16 @@ copa_status launch_init_grams(copa_plan *p, const copa_state *st, hipStream_t s)
   return COPA_OK;
 }
 
+copa_status launch_tune(copa_plan *p, const copa_state *st, hipStream_t s) {
+  switch (p->R) {
+#define CASE(r) \
+  case r: return RankOps<r>::tune(p, st, s);
+    COPA_R_LIST(CASE)
+#undef CASE
+    default: set_error("unsupported R"); return COPA_EUNSUPPORTED;
+  }
+}
+
 copa_status launch_qtilde(copa_plan *p, float *Qt, hipStream_t s) {
   if (p->S == 0) return COPA_OK;
   switch (p->R) {
@@ -137,6 +152,52 @@ copa_status launch_qtilde(copa_plan *p, float *Qt, hipStream_t s) {
 using namespace copa;
 
 extern "C" {
+
+// Autotuner cache (optional): the file named by COPA_TUNE_CACHE holds one line per tuned shape,
+//   <J> <R> <l> <projected> <precision> <log2 K> <compute units> : <pass-1 blocks per CU>
+//   <Procrustes variant> <Gram blocks> <pass-2 blocks>
+static std::string tune_key(const copa_plan *p) {
+  int lk = 0;
+  while ((int64_t)1 << (lk + 1) <= std::max<int64_t>(1, p->K)) ++lk;
+  return std::to_string(p->J) + " " + std::to_string(p->R) + " " + std::to_string(p->l) + " " +
+         std::to_string(p->proj ? 1 : 0) + " " + std::to_string(p->opt.precision) + " " +
+         std::to_string(lk) + " " + std::to_string(p->n_cu);
+}
+
+static bool tune_from_cache(copa_plan *p) {
+  const char *path = std::getenv("COPA_TUNE_CACHE");
+  if (!path || !*path) return false;
+  std::FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  const std::string key = tune_key(p);
+  char line[512];
+  bool hit = false;
+  while (std::fgets(line, sizeof line, f)) {
+    const char *colon = std::strchr(line, ':');
+    if (!colon) continue;
+    std::string k(line, colon - line);
+    while (!k.empty() && k.back() == ' ') k.pop_back();
+    int a, b, c, d;
+    if (k == key && std::sscanf(colon + 1, "%d %d %d %d", &a, &b, &c, &d) == 4 && a >= 1 &&
+        a <= 4 && (b == 0 || b == 1) && c >= 1 && c <= p->gmaxnb && d >= 1 &&
+        d <= p->p2_blocks_cap) {
+      p->p1_per_cu = a, p->proc_variant = b, p->gram_blocks = c, p->p2_blocks = d;
+      hit = true;  // the last matching line wins
+    }
+  }
+  std::fclose(f);
+  return hit;
+}
+
+static void tune_to_cache(const copa_plan *p) {
+  const char *path = std::getenv("COPA_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s : %d %d %d %d\n", tune_key(p).c_str(), p->p1_per_cu, p->proc_variant,
+               p->gram_blocks, p->p2_blocks);
+  std::fclose(f);
+}
 
 // The launches of `chunk` outer iterations on stream s, and the FIT of the last one (the others
 // are taken by the next iteration's F_H launch).
@@ -209,7 +270,30 @@ copa_status copa_fit(copa_plan *p, copa_state *st, int32_t iters, float *Qtilde,
   p->reset_warm = !(p->warm_valid && st->iter > 0 && same_state(p->last_state, *st) &&
                     p->last_state.iter == st->iter);
   p->warm_valid = false;
-  copa_status cs = launch_init_grams(p, st, s);
+  copa_status cs;
+  if (!p->tuned && p->opt.autotune && !p->opt.deterministic && iters > 0) {
+    // launch shapes, once per plan: from the cache file, else timed on this fit's start
+    if (tune_from_cache(p)) {
+      p->tuned = 2;
+    } else {
+      const auto t0 = std::chrono::steady_clock::now();
+      cs = launch_tune(p, st, s);
+      if (cs != COPA_OK) return cs;
+      p->tune_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0)
+                       .count();
+      p->tuned = 1;
+      tune_to_cache(p);
+    }
+    if (p->gexec) {  // shapes captured before tuning are stale
+      COPA_HIP(hipGraphExecDestroy(p->gexec));
+      p->gexec = nullptr;
+    }
+    if (p->gexec_bf) {
+      COPA_HIP(hipGraphExecDestroy(p->gexec_bf));
+      p->gexec_bf = nullptr;
+    }
+  }
+  cs = launch_init_grams(p, st, s);
   if (cs != COPA_OK) return cs;
   std::vector<double> hf, ho;
   FitScalars hs;
@@ -329,6 +413,11 @@ copa_status copa_plan_query(const copa_plan *p, int32_t what, int64_t *out) {
     case COPA_QUERY_COMPACT: *out = p->compact ? 1 : 0; return COPA_OK;
     case COPA_QUERY_CHUNKS: *out = p->proj ? p->pnchunks : (p->p2c ? p->nchunks : 0); return COPA_OK;
     case COPA_QUERY_PAIRS: *out = p->proj ? p->npairs : 0; return COPA_OK;
+    case COPA_QUERY_TUNED: *out = p->tuned; return COPA_OK;
+    case COPA_QUERY_PASS1_BLOCKS_PER_CU: *out = p->p1_per_cu; return COPA_OK;
+    case COPA_QUERY_PROCRUSTES_VARIANT: *out = p->proc_variant; return COPA_OK;
+    case COPA_QUERY_GRAM_BLOCKS: *out = p->gram_blocks; return COPA_OK;
+    case COPA_QUERY_PASS2_BLOCKS: *out = p->p2_blocks; return COPA_OK;
     case COPA_QUERY_WAVES: *out = p->n_waves; return COPA_OK;
     default: set_error("unknown query"); return COPA_EINVAL;
   }

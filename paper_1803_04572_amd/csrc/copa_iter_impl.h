@@ -1245,6 +1245,249 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// Smoothed subjects with R > 16, four wavefronts per 64 subjects: the same steps as
+// k_procrustes_l, with the R-long products split by columns over the four wavefronts (each takes
+// a quarter of the columns of Y (H^T H), of P and of P H^T for all 64 subjects, the Gram partial
+// sums added in wavefront order) and the l x l eigenproblems split by subjects (16 per
+// wavefront). All four SIMDs of a compute unit work on a block.
+template <int R, int N>
+__global__ void __launch_bounds__(256)
+    k_procrustes_m(int64_t K, int l_arg, const int32_t *__restrict__ rk,
+                   const float *__restrict__ T, float *__restrict__ Q, const float *__restrict__ H,
+                   const float *__restrict__ W, float *__restrict__ Ew, double rtol,
+                   FitScalars *sc) {
+  constexpr int NT = N * (N + 1) / 2;
+  constexpr int RQ = (R + 3) / 4;  // columns per wavefront
+  const int l = l_arg;
+  extern __shared__ double smem_d[];
+  double *sHH = smem_d;                                   // H^T H
+  double *sG = sHH + R * R;                               // [NT x 64]: Gram, then B
+  float *sH = reinterpret_cast<float *>(sG + NT * 64);    // H
+  float *sX = sH + R * R;                                 // 64 per-subject blocks
+  const int lR = l * R, stride = lR + 1;
+  const float inv_lR = 1.0f / (float)lR;
+  auto at = [&](int f) {
+    int q = (int)((float)f * inv_lR);
+    const int r = f - q * lR;
+    q += (r >= lR) - (r < 0);
+    return f + q;
+  };
+  const int t = threadIdx.x, s = t & 63, w = t >> 6;
+  const int64_t k0 = (int64_t)blockIdx.x * 64;
+  const int nsub = (int)(K - k0 < 64 ? K - k0 : 64);
+  for (int e = t; e < R * R; e += 256) sH[e] = H[e];
+  {
+    const float *src = T + k0 * lR;
+    const int n = nsub * lR, total = 64 * lR;
+    for (int e0 = 0; e0 < total; e0 += 8 * 256) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        v[u] = e < n ? src[e] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        if (e < total) sX[at(e)] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < R * R; e += 256) {
+    const int a = e / R, b = e - a * R;
+    double acc = 0.0;
+    for (int r = 0; r < R; ++r) acc += (double)sH[r * R + a] * (double)sH[r * R + b];
+    sHH[e] = acc;
+  }
+  const bool live = s < nsub;
+  const int64_t k = k0 + (live ? s : 0);
+  float *x = sX + s * stride;
+  const int c_lo = w * RQ;
+  // Y = T_k S_k on this wavefront's columns
+#pragma unroll 1
+  for (int i = 0; i < l; ++i)
+#pragma unroll
+    for (int cc = 0; cc < RQ; ++cc)
+      if (c_lo + cc < R) x[i * R + c_lo + cc] *= W[k * R + c_lo + cc];
+  __syncthreads();
+  {
+    // partial Gram over this wavefront's columns: sum_c y_ic (Y (H^T H))_jc
+    double Gp[NT];
+#pragma unroll
+    for (int e = 0; e < NT; ++e) Gp[e] = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (j < l) {
+        double z[RQ];
+#pragma unroll
+        for (int cc = 0; cc < RQ; ++cc) z[cc] = 0.0;
+#pragma unroll 1
+        for (int r = 0; r < R; ++r) {
+          const double y = (double)x[j * R + r];
+          const double *hh = sHH + r * R + c_lo;
+#pragma unroll
+          for (int cc = 0; cc < RQ; ++cc)
+            if (c_lo + cc < R) z[cc] = fma(y, hh[cc], z[cc]);
+        }
+#pragma unroll
+        for (int i = 0; i <= j; ++i) {
+          double acc = 0.0;
+#pragma unroll
+          for (int cc = 0; cc < RQ; ++cc)
+            if (c_lo + cc < R) acc = fma((double)x[i * R + c_lo + cc], z[cc], acc);
+          Gp[triN<N>(i, j)] = acc;
+        }
+      }
+    }
+    // add the four partial sums in wavefront order
+#pragma unroll 1
+    for (int ww = 0; ww < 4; ++ww) {
+      if (w == ww) {
+#pragma unroll
+        for (int e = 0; e < NT; ++e) sG[e * 64 + s] = (ww == 0 ? 0.0 : sG[e * 64 + s]) + Gp[e];
+      }
+      __syncthreads();
+    }
+  }
+  if ((t & 63) < 16) {
+    // the eigenproblems: wavefront w takes subjects 16 w .. 16 w + 15
+    const int sj = 16 * w + (t & 63);
+    const bool lj = sj < nsub;
+    const int64_t kj = k0 + (lj ? sj : 0);
+    double G[NT];
+#pragma unroll
+    for (int e = 0; e < NT; ++e) G[e] = sG[e * 64 + sj];
+    double E[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) E[i][j] = (double)Ew[(int64_t)(i * kNMax + j) * K + kj];
+    orthonormalize<N>(E);
+    {
+      // G <- E^T G E, one column of G E at a time
+      double Gn[NT];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        double ge[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          double acc = 0.0;
+#pragma unroll
+          for (int pp = 0; pp < N; ++pp) acc = fma(G[triN<N>(i, pp)], E[pp][q], acc);
+          ge[i] = acc;
+        }
+#pragma unroll
+        for (int pp = 0; pp <= q; ++pp) {
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i < N; ++i) acc = fma(E[i][pp], ge[i], acc);
+          Gn[triN<N>(pp, q)] = acc;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < NT; ++e) G[e] = Gn[e];
+    }
+    jacobi_rr<N>(G, E);
+    if (lj) {
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) Ew[(int64_t)(i * kNMax + j) * K + kj] = (float)E[i][j];
+    }
+    double lmax = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) lmax = fmax(lmax, G[triN<N>(j, j)]);
+    double f[N];
+    int rank = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const double lv = G[triN<N>(j, j)];
+      const bool keep = lmax > 0.0 && lv > rtol * rtol * lmax;
+      f[j] = keep ? rsq_nr(lv) : 0.0;
+      rank += keep ? 1 : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) acc += E[i][q] * f[q] * E[j][q];
+        sG[triN<N>(i, j) * 64 + sj] = acc;
+      }
+    const int meff = rk[kj];
+    if (lj && rank < (meff < R ? meff : R)) atomicAdd(&sc->rank_def_slot[sc->cur & 1], 1);
+  }
+  __syncthreads();
+  {
+    // P = B Y on this wavefront's columns
+    double B[NT];
+#pragma unroll
+    for (int e = 0; e < NT; ++e) B[e] = sG[e * 64 + s];
+#pragma unroll 1
+    for (int cc = 0; cc < RQ; ++cc) {
+      const int c = c_lo + cc;
+      if (c < R) {
+        double v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = i < l ? (double)x[i * R + c] : 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+          if (i < l) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) acc = fma(B[triN<N>(i, j)], v[j], acc);
+            x[i * R + c] = (float)acc;
+          }
+      }
+    }
+  }
+  __syncthreads();
+  // Q rows = P H^T, row by row (every wavefront reads the whole row before any overwrites it)
+#pragma unroll 1
+  for (int i = 0; i < l; ++i) {
+    float pr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) pr[r] = x[i * R + r];
+    __syncthreads();
+#pragma unroll 1
+    for (int cc = 0; cc < RQ; ++cc) {
+      const int c = c_lo + cc;
+      if (c < R) {
+        const float *h = sH + c * R;
+        float acc = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc = fmaf(pr[r], h[r], acc);
+        x[i * R + c] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  {
+    float *dst = Q + k0 * lR;
+    const int n = nsub * lR;
+    for (int e0 = 0; e0 < n; e0 += 8 * 256) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        v[u] = e < n ? sX[at(e)] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        if (e < n) dst[e] = v[u];
+      }
+    }
+  }
+}
+
+inline size_t procrustes_m_lds(int R, int l, int N) {
+  return (size_t)R * R * 8 + (size_t)N * (N + 1) / 2 * 64 * 8 + (size_t)R * R * 4 +
+         (size_t)64 * (l * R + 1) * 4;
+}
+
 // Dynamic LDS of k_procrustes_l: H^T H (FP64), H (FP32) and 64 blocks of l R + 1 floats.
 inline size_t procrustes_l_lds(int R, int l) {
   return (size_t)R * R * 8 + (size_t)R * R * 4 + (size_t)64 * (l * R + 1) * 4;
@@ -1458,7 +1701,7 @@ static void gram_fit(copa_plan *p, const float *A, const float *B, int64_t rows,
                      const float *W, int wsel, int slot, const FitArgs &fa, const float *H,
                      hipStream_t s) {
   const int64_t units = (rows + 63) / 64;
-  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(p->gmaxnb, (units + 7) / 8));
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(p->gram_blocks, (units + 7) / 8));
   const unsigned grid = (unsigned)nb + 1u;
   double *p1 = gram_slot(p, slot);
   const int sr = p->slot_rows > 0 ? p->slot_rows : 1;
@@ -1782,7 +2025,8 @@ static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
   constexpr int RTP = row4(RT);
   const int cg = p->tiles.cg;
   size_t lds = (size_t)cg * p->J * RTP * sizeof(float) + sizeof(float4);  // + the spare slot
-  const int per_cu = std::max(1, std::min(4, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
+  const int per_cu =
+      std::max(1, std::min(p->p1_per_cu, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
   const int nb = std::max(1, std::min((p->n_waves1 + 3) / 4, p->n_cu * per_cu));
   dim3 grid((unsigned)nb, (unsigned)(p->tiles.nt / cg)), block(256);
 #define P1(SM, CP)                                                                              \
@@ -1894,6 +2138,52 @@ static FitArgs fit_args(const copa_plan *p) {
   return fa;
 }
 
+// The Procrustes step of one outer iteration (variant by l, R and the tuned proc_variant).
+template <int R>
+static void launch_procrustes_r(copa_plan *p, const copa_state *st, hipStream_t s) {
+  const copa_options &o = p->opt;
+  const int64_t K = p->K;
+  if constexpr (R > 16) {
+    if (p->l > 0 && p->proc_variant == 0) {
+      const size_t lds = procrustes_l_lds(R, p->l);
+      if (p->l == 7)
+        k_procrustes_l<R, 7><<<(unsigned)((K + 63) / 64), 64, lds, s>>>(
+            K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
+      else
+        k_procrustes_l<R, kLMax><<<(unsigned)((K + 63) / 64), 64, lds, s>>>(
+            K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
+      return;
+    }
+    if (p->l > 0) {
+      if (p->l == 7)
+        k_procrustes_m<R, 7><<<(unsigned)((K + 63) / 64), 256, procrustes_m_lds(R, 7, 7),
+                               s>>>(K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew,
+                                    o.rank_rtol, p->scal);
+      else
+        k_procrustes_m<R, kLMax><<<(unsigned)((K + 63) / 64), 256,
+                                   procrustes_m_lds(R, p->l, kLMax), s>>>(
+            K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
+      return;
+    }
+  }
+  if constexpr (R <= 16) {
+    if (p->l > 0) {
+      if (p->l == 7)
+        k_procrustes_s<R, 7><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
+            K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
+      else
+        k_procrustes_s<R, kLMax><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
+            K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
+      return;
+    }
+  }
+  k_procrustes<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
+      K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W, o.rank_rtol, p->scal);
+  if (p->n_big > 0)
+    k_procrustes_wave<R><<<(unsigned)p->n_big, 64, 0, s>>>(
+        p->big_list, p->n_big, p->subj, p->T, p->Q, st->H, st->W, o.rank_rtol, p->scal);
+    }
+
 // One outer iteration; pass 1 advances the device iteration index and the later kernels read it,
 // so the same launches serve every iteration (and one captured graph replays them).
 template <int R>
@@ -1901,37 +2191,7 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   const copa_options &o = p->opt;
   const int64_t K = p->K;
   timed(p, s, kidPass1, [&] { RT_SWITCH(p->tiles.rt, launch_pass1_rt, p, st->V, s); });
-  if (K > 0)
-    timed(p, s, kidProcrustes, [&] {
-      if constexpr (R > 16) {
-        if (p->l > 0) {
-          const size_t lds = procrustes_l_lds(R, p->l);
-          if (p->l == 7)
-            k_procrustes_l<R, 7><<<(unsigned)((K + 63) / 64), 64, lds, s>>>(
-                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
-          else
-            k_procrustes_l<R, kLMax><<<(unsigned)((K + 63) / 64), 64, lds, s>>>(
-                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
-          return;
-        }
-      }
-      if constexpr (R <= 16) {
-        if (p->l > 0) {
-          if (p->l == 7)
-            k_procrustes_s<R, 7><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
-          else
-            k_procrustes_s<R, kLMax><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-                K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
-          return;
-        }
-      }
-      k_procrustes<R><<<(unsigned)((K + 63) / 64), 64, 0, s>>>(
-          K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W, o.rank_rtol, p->scal);
-      if (p->n_big > 0)
-        k_procrustes_wave<R><<<(unsigned)p->n_big, 64, 0, s>>>(
-            p->big_list, p->n_big, p->subj, p->T, p->Q, st->H, st->W, o.rank_rtol, p->scal);
-    });
+  if (K > 0) timed(p, s, kidProcrustes, [&] { launch_procrustes_r<R>(p, st, s); });
   timed(p, s, kidGramFH, [&] {
     // one more block of the same launch takes the FIT of the previous outer iteration
     const FitArgs fa = fit_args(p);
@@ -1987,6 +2247,7 @@ struct RankOps {
   static void fit(copa_plan *p, const copa_state *st, hipStream_t s);
   static void init_grams(copa_plan *p, const copa_state *st, hipStream_t s);
   static void qtilde(copa_plan *p, float *Qt, hipStream_t s);
+  static copa_status tune(copa_plan *p, const copa_state *st, hipStream_t s);
 };
 // (defined out of the class so that they are not inline: the extern declarations below then
 // keep every other translation unit from instantiating the kernels)
@@ -2002,6 +2263,86 @@ template <int R>
 void RankOps<R>::init_grams(copa_plan *p, const copa_state *st, hipStream_t s) {
   init_grams_r<R>(p, st, s);
 }
+// Autotuner: times candidate launch shapes of the passes, the Procrustes step and the row Grams
+// on the plan's own data (the fit's starting point) and keeps the fastest of each. Every kernel
+// timed here writes only buffers the iteration writes again before reading them (T, Q, the
+// warm-start eigenvectors, which the fit then resets, F_V, the Gram slots), so the fit that
+// follows is unaffected apart from the launch shapes.
+template <int R>
+copa_status RankOps<R>::tune(copa_plan *p, const copa_state *st, hipStream_t s) {
+  hipEvent_t e0, e1;
+  COPA_HIP(hipEventCreate(&e0));
+  COPA_HIP(hipEventCreate(&e1));
+  auto time_it = [&](auto &&launch) -> float {
+    float best = 1e30f;
+    launch();  // warm (first-touch, code load)
+    for (int rep = 0; rep < 3; ++rep) {
+      (void)hipEventRecord(e0, s);
+      launch();
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      best = std::min(best, ms);
+    }
+    return best;
+  };
+  k_reset_scalars<<<1, 64, 0, s>>>(p->scal);
+  init_grams_r<R>(p, st, s);  // padded image of V, W^T W, V^T V
+  // pass 1: persistent blocks per compute unit
+  {
+    int best_c = p->p1_per_cu;
+    float best_t = 1e30f;
+    for (int c : {1, 2, 3, 4}) {
+      p->p1_per_cu = c;
+      const float t = time_it([&] { RT_SWITCH(p->tiles.rt, launch_pass1_rt, p, st->V, s); });
+      if (t < best_t) best_t = t, best_c = c;
+    }
+    p->p1_per_cu = best_c;
+  }
+  // T now holds the rows of the starting point: the Procrustes variants (smoothed, R > 16)
+  if (R > 16 && p->l > 0 && p->K > 0) {
+    int best_v = 0;
+    float best_t = 1e30f;
+    for (int v : {0, 1}) {
+      p->proc_variant = v;
+      const float t = time_it([&] { launch_procrustes_r<R>(p, st, s); });
+      if (t < best_t) best_t = t, best_v = v;
+    }
+    p->proc_variant = best_v;
+  }
+  // the row Grams (F_H's launch shape) and the pass-2 grid
+  {
+    int best_g = p->gram_blocks;
+    float best_t = 1e30f;
+    for (int g : {p->gmaxnb / 4, p->gmaxnb / 2, p->gmaxnb}) {
+      if (g < 1) continue;
+      p->gram_blocks = g;
+      const float t = time_it([&] {
+        gram<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, kSlotFH, nullptr, 0, 0, s);
+      });
+      if (t < best_t) best_t = t, best_g = g;
+    }
+    p->gram_blocks = best_g;
+  }
+  if (p->p2c || p->proj) {
+    int best_b = p->p2_blocks;
+    float best_t = 1e30f;
+    for (int b : {p->p2_blocks_cap / 4, p->p2_blocks_cap / 2, p->p2_blocks_cap}) {
+      if (b < 1) continue;
+      p->p2_blocks = b;
+      const float t = time_it([&] { RT2_SWITCH(R, p->tiles2.rt, launch_pass2c_rt, p, s); });
+      if (t < best_t) best_t = t, best_b = b;
+    }
+    p->p2_blocks = best_b;
+  }
+  COPA_HIP(hipStreamSynchronize(s));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  COPA_HIP(hipGetLastError());
+  return COPA_OK;
+}
+
 template <int R>
 void RankOps<R>::qtilde(copa_plan *p, float *Qt, hipStream_t s) {
   const unsigned nb = (unsigned)((p->S + 255) / 256);

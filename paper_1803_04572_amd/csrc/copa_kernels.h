@@ -213,7 +213,7 @@ inline void gram(copa_plan *p, const float *A, const float *B, int64_t rows, con
                  int wsel, int slot, const float *A2, int64_t rows2, int slot2, hipStream_t s) {
   // about two 64-row units per wave of the 4-wave blocks
   const int64_t units = (std::max<int64_t>(rows, A2 ? rows2 : 0) + 63) / 64;
-  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(p->gmaxnb, (units + 7) / 8));
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(p->gram_blocks, (units + 7) / 8));
   const dim3 grid(nb, A2 ? 2 : 1);
   double *p1 = gram_slot(p, slot), *p2 = A2 ? gram_slot(p, slot2) : nullptr;
   const int sr = p->slot_rows > 0 ? p->slot_rows : 1;
@@ -674,7 +674,7 @@ __global__ void __launch_bounds__(512)
 
 template <int RT>
 inline void launch_pass2p(const copa_plan *p, float *F, hipStream_t s) {
-  const int gx = std::min(p->pnchunks, p->p2_blocks_cap);
+  const int gx = std::min(p->pnchunks, p->p2_blocks);
   const dim3 grid((unsigned)gx, (unsigned)p->tiles2.nt);
   const size_t lds = ((size_t)p->J * row4(RT) + (size_t)kChunkRows * row4(RT) + 4) * sizeof(float);
   float *part = p->opt.deterministic ? p->fvpart : nullptr;
@@ -704,7 +704,7 @@ inline void launch_pass2p(const copa_plan *p, float *F, hipStream_t s) {
 // one more launch adds the slices to F in block order.
 template <int RT, bool SMOOTH>
 inline void launch_pass2c(const copa_plan *p, const float *Mrows, float *F, hipStream_t s) {
-  const int gx = std::min(p->nchunks, p->p2_blocks_cap);
+  const int gx = std::min(p->nchunks, p->p2_blocks);
   const dim3 grid((unsigned)gx, (unsigned)p->tiles2.nt);
   const size_t lds = ((size_t)p->J * row4(RT) + (size_t)kChunkRows * row4(RT) + 4) * sizeof(float);
   float *part = p->opt.deterministic ? p->fvpart : nullptr;

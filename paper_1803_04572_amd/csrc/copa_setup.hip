@@ -474,6 +474,8 @@ static copa_status plan_dims(const copa_tensor *X, const copa_options *opt, copa
   p->nchunks_cap = (int)std::min<int64_t>(INT32_MAX - 1, (p->S + kChunkRows - 1) / kChunkRows +
                                                           (p->l > 0 ? K / msub : 0) + 1);
   p->p2_blocks_cap = 2 * std::max(1, p->n_cu);
+  p->p2_blocks = p->p2_blocks_cap;
+  p->gram_blocks = p->gmaxnb;
   p->pchunks_cap = p->proj ? (int)std::min<int64_t>(INT32_MAX - 1, K / msub + 2) : 0;
   return COPA_OK;
 }
