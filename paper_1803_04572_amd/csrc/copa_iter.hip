@@ -179,7 +179,7 @@ static bool tune_from_cache(copa_plan *p) {
     while (!k.empty() && k.back() == ' ') k.pop_back();
     int a, b, c, d;
     if (k == key && std::sscanf(colon + 1, "%d %d %d %d", &a, &b, &c, &d) == 4 && a >= 1 &&
-        a <= 4 && (b == 0 || b == 1) && c >= 1 && c <= p->gmaxnb && d >= 1 &&
+        a <= 4 && b >= 0 && b <= 2 && c >= 1 && c <= p->gmaxnb && d >= 1 &&
         d <= p->p2_blocks_cap) {
       p->p1_per_cu = a, p->proc_variant = b, p->gram_blocks = c, p->p2_blocks = d;
       hit = true;  // the last matching line wins

@@ -1483,6 +1483,291 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Smoothed subjects with R > 16 in three launches, so that the l x l eigenproblems run without
+// LDS at several wavefronts per SIMD:
+//   k_proc_gram   A_k = T_k S_k H^T (FP32, into the M rows, which the W update writes later in
+//                 the iteration) and G_k = A_k A_k^T (FP64), entry-major per subject
+//   k_proc_eigen  warm-started Jacobi on G_k (thread per subject), B_k = E diag(f) E^T
+//   k_proc_q      Q_k = B_k A_k
+// Four wavefronts per 64 subjects in the first and last, a quarter of the columns each.
+template <int R, int N>
+__global__ void __launch_bounds__(256)
+    k_proc_gram(int64_t K, int l, const float *__restrict__ T, const float *__restrict__ H,
+                const float *__restrict__ W, float *__restrict__ A, double *__restrict__ Gk) {
+  constexpr int NT = N * (N + 1) / 2;
+  constexpr int RQ = (R + 3) / 4;
+  extern __shared__ double smem_d[];
+  double *sG = smem_d;                                    // [NT x 64]
+  float *sH = reinterpret_cast<float *>(sG + NT * 64);    // H
+  float *sX = sH + R * R;                                 // 64 per-subject blocks
+  const int lR = l * R, stride = lR + 1;
+  const float inv_lR = 1.0f / (float)lR;
+  auto at = [&](int f) {
+    int q = (int)((float)f * inv_lR);
+    const int r = f - q * lR;
+    q += (r >= lR) - (r < 0);
+    return f + q;
+  };
+  const int t = threadIdx.x, s = t & 63, w = t >> 6;
+  const int64_t k0 = (int64_t)blockIdx.x * 64;
+  const int nsub = (int)(K - k0 < 64 ? K - k0 : 64);
+  for (int e = t; e < R * R; e += 256) sH[e] = H[e];
+  {
+    const float *src = T + k0 * lR;
+    const int n = nsub * lR, total = 64 * lR;
+    for (int e0 = 0; e0 < total; e0 += 8 * 256) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        v[u] = e < n ? src[e] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        if (e < total) sX[at(e)] = v[u];
+      }
+    }
+  }
+  const int64_t k = k0 + (s < nsub ? s : 0);
+  float *x = sX + s * stride;
+  const int c_lo = w * RQ;
+  __syncthreads();
+  // a_i = (t_i * w) H^T on this wavefront's columns, every row of the subject
+  float a[N][RQ];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int cc = 0; cc < RQ; ++cc) a[i][cc] = 0.0f;
+    if (i < l) {
+#pragma unroll 2
+      for (int r = 0; r < R; ++r) {
+        const float y = x[i * R + r] * W[k * R + r];
+#pragma unroll
+        for (int cc = 0; cc < RQ; ++cc)
+          if (c_lo + cc < R) a[i][cc] = fmaf(y, sH[(c_lo + cc) * R + r], a[i][cc]);
+      }
+    }
+  }
+  // partial Gram in FP64 over these columns, added in wavefront order
+  {
+    double Gp[NT];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < RQ; ++cc) acc = fma((double)a[i][cc], (double)a[j][cc], acc);
+        Gp[triN<N>(i, j)] = acc;
+      }
+#pragma unroll 1
+    for (int ww = 0; ww < 4; ++ww) {
+      if (w == ww) {
+#pragma unroll
+        for (int e = 0; e < NT; ++e) sG[e * 64 + s] = (ww == 0 ? 0.0 : sG[e * 64 + s]) + Gp[e];
+      }
+      __syncthreads();
+    }
+  }
+  // A rows into the block (every wavefront has read Y), then both out coalesced
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if (i < l)
+#pragma unroll
+      for (int cc = 0; cc < RQ; ++cc)
+        if (c_lo + cc < R) x[i * R + c_lo + cc] = a[i][cc];
+  for (int e = t; e < NT * 64; e += 256) {
+    const int ent = e >> 6, sj = e & 63;
+    if (sj < nsub) Gk[(int64_t)ent * K + k0 + sj] = sG[e];
+  }
+  __syncthreads();
+  {
+    float *dst = A + k0 * lR;
+    const int n = nsub * lR;
+    for (int e0 = 0; e0 < n; e0 += 8 * 256) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        v[u] = e < n ? sX[at(e)] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        if (e < n) dst[e] = v[u];
+      }
+    }
+  }
+}
+
+template <int R, int N>
+__global__ void __launch_bounds__(256)
+    k_proc_eigen(int64_t K, int l, const int32_t *__restrict__ rk, double *__restrict__ Gk,
+                 float *__restrict__ Ew, double rtol, FitScalars *sc) {
+  constexpr int NT = N * (N + 1) / 2;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = k < K;
+  const int64_t kk = live ? k : 0;
+  double G[NT];
+#pragma unroll
+  for (int e = 0; e < NT; ++e) G[e] = Gk[(int64_t)e * K + kk];
+  double E[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) E[i][j] = (double)Ew[(int64_t)(i * kNMax + j) * K + kk];
+  orthonormalize<N>(E);
+  {
+    double Gn[NT];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      double ge[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int pp = 0; pp < N; ++pp) acc = fma(G[triN<N>(i, pp)], E[pp][q], acc);
+        ge[i] = acc;
+      }
+#pragma unroll
+      for (int pp = 0; pp <= q; ++pp) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc = fma(E[i][pp], ge[i], acc);
+        Gn[triN<N>(pp, q)] = acc;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < NT; ++e) G[e] = Gn[e];
+  }
+  jacobi_rr<N>(G, E);
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) Ew[(int64_t)(i * kNMax + j) * K + k] = (float)E[i][j];
+  }
+  double lmax = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) lmax = fmax(lmax, G[triN<N>(j, j)]);
+  double f[N];
+  int rank = 0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const double lv = G[triN<N>(j, j)];
+    const bool keep = lmax > 0.0 && lv > rtol * rtol * lmax;
+    f[j] = keep ? rsq_nr(lv) : 0.0;
+    rank += keep ? 1 : 0;
+  }
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) acc += E[i][q] * f[q] * E[j][q];
+        Gk[(int64_t)triN<N>(i, j) * K + k] = acc;
+      }
+    const int meff = rk[k];
+    if (rank < (meff < R ? meff : R)) atomicAdd(&sc->rank_def_slot[sc->cur & 1], 1);
+  }
+}
+
+template <int R, int N>
+__global__ void __launch_bounds__(256)
+    k_proc_q(int64_t K, int l, const float *__restrict__ A, const double *__restrict__ Bk,
+             float *__restrict__ Q) {
+  constexpr int NT = N * (N + 1) / 2;
+  constexpr int RQ = (R + 3) / 4;
+  extern __shared__ double smem_d[];
+  float *sX = reinterpret_cast<float *>(smem_d);
+  const int lR = l * R, stride = lR + 1;
+  const float inv_lR = 1.0f / (float)lR;
+  auto at = [&](int f) {
+    int q = (int)((float)f * inv_lR);
+    const int r = f - q * lR;
+    q += (r >= lR) - (r < 0);
+    return f + q;
+  };
+  const int t = threadIdx.x, s = t & 63, w = t >> 6;
+  const int64_t k0 = (int64_t)blockIdx.x * 64;
+  const int nsub = (int)(K - k0 < 64 ? K - k0 : 64);
+  {
+    const float *src = A + k0 * lR;
+    const int n = nsub * lR, total = 64 * lR;
+    for (int e0 = 0; e0 < total; e0 += 8 * 256) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        v[u] = e < n ? src[e] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        if (e < total) sX[at(e)] = v[u];
+      }
+    }
+  }
+  const int64_t k = k0 + (s < nsub ? s : 0);
+  double B[NT];
+#pragma unroll
+  for (int e = 0; e < NT; ++e) B[e] = Bk[(int64_t)e * K + k];
+  __syncthreads();
+  float *x = sX + s * stride;
+  const int c_lo = w * RQ;
+#pragma unroll 1
+  for (int cc = 0; cc < RQ; ++cc) {
+    const int c = c_lo + cc;
+    if (c < R) {
+      double v[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = i < l ? (double)x[i * R + c] : 0.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        if (i < l) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < N; ++j) acc = fma(B[triN<N>(i, j)], v[j], acc);
+          x[i * R + c] = (float)acc;
+        }
+    }
+  }
+  __syncthreads();
+  {
+    float *dst = Q + k0 * lR;
+    const int n = nsub * lR;
+    for (int e0 = 0; e0 < n; e0 += 8 * 256) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        v[u] = e < n ? sX[at(e)] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        if (e < n) dst[e] = v[u];
+      }
+    }
+  }
+}
+
+template <int R, int N>
+inline void launch_proc_split(copa_plan *p, const copa_state *st, hipStream_t s) {
+  constexpr int NT = N * (N + 1) / 2;
+  const int64_t K = p->K;
+  const unsigned nb = (unsigned)((K + 63) / 64);
+  const size_t lds1 = (size_t)NT * 64 * 8 + (size_t)R * R * 4 + (size_t)64 * (p->l * R + 1) * 4;
+  k_proc_gram<R, N><<<nb, 256, lds1, s>>>(K, p->l, p->T, st->H, st->W, p->M, p->pgb);
+  k_proc_eigen<R, N><<<(unsigned)((K + 255) / 256), 256, 0, s>>>(K, p->l, p->rk, p->pgb, p->Ew,
+                                                                  p->opt.rank_rtol, p->scal);
+  const size_t lds3 = (size_t)64 * (p->l * R + 1) * 4;
+  k_proc_q<R, N><<<nb, 256, lds3, s>>>(K, p->l, p->M, p->pgb, p->Q);
+}
+
 inline size_t procrustes_m_lds(int R, int l, int N) {
   return (size_t)R * R * 8 + (size_t)N * (N + 1) / 2 * 64 * 8 + (size_t)R * R * 4 +
          (size_t)64 * (l * R + 1) * 4;
@@ -2154,6 +2439,13 @@ static void launch_procrustes_r(copa_plan *p, const copa_state *st, hipStream_t 
             K, p->l, p->rk, p->T, p->Q, st->H, st->W, p->Ew, o.rank_rtol, p->scal);
       return;
     }
+    if (p->l > 0 && p->proc_variant == 2) {
+      if (p->l == 7)
+        launch_proc_split<R, 7>(p, st, s);
+      else
+        launch_proc_split<R, kLMax>(p, st, s);
+      return;
+    }
     if (p->l > 0) {
       if (p->l == 7)
         k_procrustes_m<R, 7><<<(unsigned)((K + 63) / 64), 256, procrustes_m_lds(R, 7, 7),
@@ -2304,7 +2596,7 @@ copa_status RankOps<R>::tune(copa_plan *p, const copa_state *st, hipStream_t s) 
   if (R > 16 && p->l > 0 && p->K > 0) {
     int best_v = 0;
     float best_t = 1e30f;
-    for (int v : {0, 1}) {
+    for (int v : {0, 1, 2}) {
       p->proc_variant = v;
       const float t = time_it([&] { launch_procrustes_r<R>(p, st, s); });
       if (t < best_t) best_t = t, best_v = v;

@@ -510,6 +510,7 @@ static copa_status carve_all(copa_plan *p, bool dry) {
     COPA_TRY(take(&p->C, S * kLMax));
     COPA_TRY(take(&p->rk, K));
     COPA_TRY(take(&p->Ew, (size_t)K * kNMax * kNMax));
+    if (R > 16) COPA_TRY(take(&p->pgb, (size_t)K * 36));
   } else {
     COPA_TRY(take(&p->big_list, K));
   }

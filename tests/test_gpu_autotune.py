@@ -50,3 +50,29 @@ def test_untuned_plan_keeps_default_shapes():
     assert p.query("pass1_blocks_per_cu") == 4 and p.query("procrustes_variant") == 0
     d = run_gpu(coh, 20, cfg["l"], 2, adjoint=False, deterministic=True)
     assert d["plan"].query("tuned") == 0  # fixed summation order: fixed shapes
+
+
+@pytest.mark.parametrize("cfg_name,R", [("c4", 20), ("c3", 40)])
+def test_every_procrustes_variant_on_trajectory(cfg_name, R, tmp_path, monkeypatch):
+    """Each of the three Procrustes kernels for smoothed R > 16, forced through the cache file,
+    follows the oracle's 20-iteration trajectory."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("COPA_TUNE_CACHE", str(cache))
+    with open(os.path.join(GOLDEN, f"fullsize_{cfg_name}_R{R}_K3000.json")) as fh:
+        ref = json.load(fh)
+    coh, cfg = synth.make_config(cfg_name, K=3000)
+    first = run_gpu(coh, R, cfg["l"], 1, adjoint=False)
+    key, shapes = cache.read_text().strip().splitlines()[0].split(":")
+    a, _, c, d = shapes.split()
+    for v in (0, 1, 2):
+        cache.write_text(f"{key}: {a} {v} {c} {d}\n")
+        g = run_gpu(coh, R, cfg["l"], ref["iters"], adjoint=False)
+        assert g["plan"].query("tuned") == 2 and g["plan"].query("procrustes_variant") == v
+        fit = np.abs(np.array(g["rep"]["fit_history"]) - np.array(ref["fit"])) / np.abs(ref["fit"])
+        print(f"procrustes variant {v} {cfg_name} R={R}: fit_rel={fit[-1]:.2e} "
+              f"hist_max={fit.max():.2e} rank_def={g['rep']['rank_deficient']}/"
+              f"{ref['rank_deficient'][-1]}", flush=True)
+        assert fit.max() <= 1e-5
+        assert abs(g["rep"]["rank_deficient"] - ref["rank_deficient"][-1]) <= \
+            ref["ambiguous_band"][-1]
+    del first
