@@ -11,8 +11,11 @@ Readings of points the paper leaves open (each is also a keyword argument where 
   * Procrustes (Section "General Framework", eq. solv_Q, Algorithm 1 truncated-SVD step): Q_k is
     the polar factor of A_k = X_k V S_k H^T, truncated to singular values > rtol * sigma_1
     (rtol = 1e-6); the zero matrix when sigma_1 == 0. For I_k < R this gives orthonormal rows.
-  * Block order H -> W -> V (Algorithm 1 names Z1=H, Z2=W, Z3=V); each mode's Gram G and MTTKRP F
-    use the auxiliary (constrained) value of the modes updated before it.
+  * Block order H -> W -> V (Algorithm 1 names Z1=H, Z2=W, Z3=V) by default; each mode's Gram G
+    and MTTKRP F use the auxiliary (constrained) value of the modes updated before it. The option
+    order="WHV" runs the blocks W -> H -> V instead: W's Gram and MTTKRP then take the H of the
+    previous outer iteration and H's take the new W. Both orders are block-coordinate sweeps over
+    the same blocks, so they share their fixed points; the iterates differ.
   * rho = trace(G) / R (Algorithm 1; the text's alternative is not used).
   * Auxiliary and dual variables persist across outer iterations; D starts at 0 and is not
     rescaled when rho changes.
@@ -269,6 +272,7 @@ class Options:
     lam_W: float = 0.0
     lam_V: float = 0.1
     rank_rtol: float = 1e-6
+    order: str = "HWV"     # block order of one outer iteration: "HWV" or "WHV"
 
 
 @dataclasses.dataclass
@@ -297,8 +301,25 @@ def copa_fit(prob, H0, W0, V0, opt: Options, D0=None):
         D_H, D_W, D_V = np.zeros_like(H), np.zeros_like(W), np.zeros_like(V)
     else:
         D_H, D_W, D_V = (np.array(a, dtype=np.float64) for a in D0)
+    if opt.order not in ("HWV", "WHV"):
+        raise ValueError(f"order must be 'HWV' or 'WHV', not {opt.order!r}")
     fits, objs, spars, rhos = [], [], [], []
     Qs, ranks, sigmas, F = [], [], [], {}
+
+    def block_H():
+        nonlocal H, D_H
+        G = (W.T @ W) * (V.T @ V)
+        F["H"] = mttkrp_H(Ys, V, W)
+        H, D_H, r = admm_update(G, F["H"], H, D_H, opt.prox_H, opt.lam_H, opt.inner_iters)
+        return r
+
+    def block_W():
+        nonlocal W, D_W
+        G = (H.T @ H) * (V.T @ V)
+        F["W"] = mttkrp_W(Ys, H, V)
+        W, D_W, r = admm_update(G, F["W"], W, D_W, opt.prox_W, opt.lam_W, opt.inner_iters)
+        return r
+
     for _ in range(opt.outer_iters):
         # Procrustes: Q_k from the truncated SVD of X'_k V S_k H^T, then Y_k = Q_k^T X'_k
         Qs, ranks, sigmas = [], [], []
@@ -309,14 +330,13 @@ def copa_fit(prob, H0, W0, V0, opt: Options, D0=None):
             ranks.append(r)
             sigmas.append(sv)
         Ys = slices_Y(prob, Qs)
-        # mode 1: H
-        G = (W.T @ W) * (V.T @ V)
-        F["H"] = mttkrp_H(Ys, V, W)
-        H, D_H, rH = admm_update(G, F["H"], H, D_H, opt.prox_H, opt.lam_H, opt.inner_iters)
-        # mode 2 of Algorithm 1: W (the diagonals of S_k)
-        G = (H.T @ H) * (V.T @ V)
-        F["W"] = mttkrp_W(Ys, H, V)
-        W, D_W, rW = admm_update(G, F["W"], W, D_W, opt.prox_W, opt.lam_W, opt.inner_iters)
+        # mode 1 of Algorithm 1: H; mode 2: W (the diagonals of S_k); in either order
+        if opt.order == "HWV":
+            rH = block_H()
+            rW = block_W()
+        else:
+            rW = block_W()
+            rH = block_H()
         # mode 3 of Algorithm 1: V
         G = (H.T @ H) * (W.T @ W)
         F["V"] = mttkrp_V(Ys, H, W)

@@ -12,6 +12,9 @@ contiguous shards held by worker processes:
     shared Gram G_W = H^T H * V^T V (same rho = trace(G_W) / R), then returns the pieces the V
     block needs with the new W: W^T W and F_V = sum_k Y_k^T H diag(W_k).
   * The V block (Z3) and the FIT (Section "Evaluation Metrics") follow from the summed pieces.
+  * In the block order W -> H -> V (Options.order == "WHV") the shards update their W rows first,
+    with the H of the previous outer iteration, and return F_H and W^T W with the new W; F_V is
+    asked for after the H block.
 
 Sums over shards run in shard order, so results differ from the one-process oracle by rounding
 only (a CPU test pins the two against each other).
@@ -51,10 +54,9 @@ class _Shard:
     def _Y(self, k):
         return self.Q[k].T @ co._dense(self.prob.Xh[k])
 
-    def procrustes_FH(self, H, V):
-        """Q_k of every subject, then this shard's F_H and W^T W (H block inputs)."""
+    def procrustes(self, H, V):
+        """Q_k of every subject of this shard (eq. solv_Q)."""
         self.band = 0
-        FH = np.zeros((H.shape[0], H.shape[0]))
         for k, Xh in enumerate(self.prob.Xh):
             A = Xh @ V @ np.diag(self.W[k]) @ H.T
             Q, r, s = co.procrustes(A, self.opt.rank_rtol)
@@ -62,19 +64,30 @@ class _Shard:
             if s.size and s[0] > 0:
                 rel = s / s[0]
                 self.band += int(np.any((rel >= 1e-7) & (rel <= 1e-5)))
+        return None
+
+    def FH(self, V):
+        """This shard's F_H = sum_k Y_k V diag(W_k) and W^T W (H block inputs)."""
+        R = V.shape[1]
+        FH = np.zeros((R, R))
+        for k in range(len(self.Q)):
             FH += co.mttkrp_H([self._Y(k)], V, self.W[k:k + 1])
         return FH, self.W.T @ self.W
 
     def update_W(self, H, V, G_W):
-        """W block on this shard's rows, then W^T W and F_V with the new W (V block inputs)."""
+        """W block on this shard's rows; returns the new W^T W and rho."""
         FW = np.array([co.mttkrp_W([self._Y(k)], H, V)[0] for k in range(len(self.Q))]) \
             if self.Q else np.zeros((0, H.shape[0]))
         self.W, self.D_W, rho = co.admm_update(G_W, FW, self.W, self.D_W, self.opt.prox_W,
                                                self.opt.lam_W, self.opt.inner_iters)
-        FV = np.zeros((V.shape[0], H.shape[0]))
+        return self.W.T @ self.W, rho
+
+    def FV(self, H, J):
+        """This shard's F_V = sum_k Y_k^T H diag(W_k) (V block input)."""
+        FV = np.zeros((J, H.shape[0]))
         for k in range(len(self.Q)):
             FV += co.mttkrp_V([self._Y(k)], H, self.W[k:k + 1])
-        return self.W.T @ self.W, FV, rho
+        return FV
 
     def fit_terms(self, H, V):
         """Sum_k ||X_k - U_k S_k V^T||^2 over this shard (dense reconstruction), the l1 norm of its
@@ -143,17 +156,31 @@ def copa_fit_sharded(coh, l, H0, W0, V0, opt: co.Options, workers=8, progress=No
     D_H, D_V = np.zeros_like(H), np.zeros_like(V)
     out = dict(fit=[], objective=[], sparsity=[], rho=[], rank_deficient=[], ambiguous_band=[])
     try:
-        for it in range(opt.outer_iters):
-            parts = ask("procrustes_FH", H, V)
+        def block_H():
+            nonlocal H, D_H
+            parts = ask("FH", V)
             FH = sum(p[0] for p in parts)
             WtW = sum(p[1] for p in parts)
             G = WtW * (V.T @ V)
-            H, D_H, rH = co.admm_update(G, FH, H, D_H, opt.prox_H, opt.lam_H, opt.inner_iters)
+            H, D_H, r = co.admm_update(G, FH, H, D_H, opt.prox_H, opt.lam_H, opt.inner_iters)
+            return r, WtW
+
+        def block_W():
             G = (H.T @ H) * (V.T @ V)
             parts = ask("update_W", H, V, G)
-            WtW = sum(p[0] for p in parts)
-            FV = sum(p[1] for p in parts)
-            rW = parts[0][2]
+            return parts[0][1], sum(p[0] for p in parts)
+
+        if opt.order not in ("HWV", "WHV"):
+            raise ValueError(f"order must be 'HWV' or 'WHV', not {opt.order!r}")
+        for it in range(opt.outer_iters):
+            ask("procrustes", H, V)
+            if opt.order == "HWV":
+                rH, _ = block_H()
+                rW, WtW = block_W()
+            else:
+                rW, _ = block_W()
+                rH, WtW = block_H()
+            FV = sum(ask("FV", H, V.shape[0]))
             G = (H.T @ H) * WtW
             V, D_V, rV = co.admm_update(G, FV, V, D_V, opt.prox_V, opt.lam_V, opt.inner_iters)
             parts = ask("fit_terms", H, V)

@@ -258,22 +258,27 @@ def _dense_cohort(Xks, J, days=None):
                         col=np.concatenate(rows_c), val=np.concatenate(rows_v), days=days)
 
 
-def _cp_als_reference(Xs, H, W, V):
-    """One PARAFAC2-ALS iteration (Procrustes by SVD, then one CP-ALS sweep H -> W -> V on the
-    dense tensor Y with least squares), written independently of the oracle."""
+def _cp_als_reference(Xs, H, W, V, order="HWV"):
+    """One PARAFAC2-ALS iteration (Procrustes by SVD, then one CP-ALS sweep on the dense tensor Y
+    with least squares on its unfoldings, H -> W -> V or W -> H -> V), written independently of
+    the oracle."""
     Qs = []
     for k, X in enumerate(Xs):
         A = X @ V @ np.diag(W[k]) @ H.T
         U, s, Vt = np.linalg.svd(A, full_matrices=False)
         Qs.append(U @ Vt)
     Y = np.stack([Q.T @ X for Q, X in zip(Qs, Xs)], axis=2)
-    H = np.linalg.lstsq(_khatri_rao(W, V), _unfold(Y, 0).T, rcond=None)[0].T
-    W = np.linalg.lstsq(_khatri_rao(V, H), _unfold(Y, 2).T, rcond=None)[0].T
+    for mode in order[:2]:
+        if mode == "H":
+            H = np.linalg.lstsq(_khatri_rao(W, V), _unfold(Y, 0).T, rcond=None)[0].T
+        else:
+            W = np.linalg.lstsq(_khatri_rao(V, H), _unfold(Y, 2).T, rcond=None)[0].T
     V = np.linalg.lstsq(_khatri_rao(W, H), _unfold(Y, 1).T, rcond=None)[0].T
     return H, W, V
 
 
-def test_one_iteration_reduces_to_parafac2_als():
+@pytest.mark.parametrize("order", ["HWV", "WHV"])
+def test_one_iteration_reduces_to_parafac2_als(order):
     rng = np.random.default_rng(15)
     R, J, K = 3, 6, 5
     Xs = [np.abs(_rand(rng, int(rng.integers(4, 8)), J)) for _ in range(K)]
@@ -281,12 +286,15 @@ def test_one_iteration_reduces_to_parafac2_als():
     prob = co.build_problem(coh, 0)
     H0, W0, V0 = np.eye(R) + 0.1 * _rand(rng, R, R), 0.5 + rng.random((K, R)), rng.random((J, R))
     opt = co.Options(R=R, outer_iters=1, inner_iters=4000, prox_H=co.PROX_NONE,
-                     prox_W=co.PROX_NONE, prox_V=co.PROX_NONE, lam_V=0.0)
+                     prox_W=co.PROX_NONE, prox_V=co.PROX_NONE, lam_V=0.0, order=order)
     res = co.copa_fit(prob, H0, W0, V0, opt)
-    Href, Wref, Vref = _cp_als_reference(Xs, H0, W0, V0)
+    Href, Wref, Vref = _cp_als_reference(Xs, H0, W0, V0, order)
     np.testing.assert_allclose(res.H, Href, rtol=1e-6, atol=1e-8)
     np.testing.assert_allclose(res.W, Wref, rtol=1e-6, atol=1e-8)
     np.testing.assert_allclose(res.V, Vref, rtol=1e-6, atol=1e-8)
+    # the two orders are different maps away from a fixed point
+    other = _cp_als_reference(Xs, H0, W0, V0, "WHV" if order == "HWV" else "HWV")
+    assert np.abs(other[1] - Wref).max() > 1e-3 and np.abs(other[0] - Href).max() > 1e-3
 
 
 def _planted_exact(rng, K, J, R, ik_lo=6, ik_hi=12):
@@ -302,14 +310,15 @@ def _planted_exact(rng, K, J, R, ik_lo=6, ik_hi=12):
     return H, V, W, Qs, Xs
 
 
-def test_planted_truth_is_exact_fixed_point():
+@pytest.mark.parametrize("order", ["HWV", "WHV"])
+def test_planted_truth_is_exact_fixed_point(order):
     rng = np.random.default_rng(16)
     K, J, R = 7, 9, 3
     H, V, W, Qs, Xs = _planted_exact(rng, K, J, R)
     coh = _dense_cohort(Xs, J)
     prob = co.build_problem(coh, 0)
     opt = co.Options(R=R, outer_iters=3, inner_iters=5, prox_H=co.PROX_NONE,
-                     prox_W=co.PROX_NONNEG, prox_V=co.PROX_L1, lam_V=0.0)
+                     prox_W=co.PROX_NONNEG, prox_V=co.PROX_L1, lam_V=0.0, order=order)
     res = co.copa_fit(prob, H, W, V, opt)
     np.testing.assert_allclose(res.H, H, atol=1e-10)
     np.testing.assert_allclose(res.W, W, atol=1e-10)
@@ -337,14 +346,14 @@ def test_noiseless_planted_from_random_init_reaches_near_zero_loss():
     assert good >= 3
 
 
-def test_fit_is_nondecreasing_without_penalties():
+@pytest.mark.parametrize("order", ["HWV", "WHV"])
+def test_fit_is_nondecreasing_without_penalties(order):
     """With only Procrustes + ADMM run to convergence, each block step cannot increase the loss."""
-    rng = np.random.default_rng(17)
     coh, _ = synth.planted_cohort(20, 15, 3, 4, 9, seed=3)
     prob = co.build_problem(coh, 0)
     H0, W0, V0 = synth.init_factors(coh.K, coh.J, 3, 0)
     opt = co.Options(R=3, outer_iters=8, inner_iters=400, prox_H=co.PROX_NONE,
-                     prox_W=co.PROX_NONE, prox_V=co.PROX_NONE, lam_V=0.0)
+                     prox_W=co.PROX_NONE, prox_V=co.PROX_NONE, lam_V=0.0, order=order)
     res = co.copa_fit(prob, H0, W0, V0, opt)
     assert np.all(np.diff(res.fit) >= -1e-9)
 
@@ -552,14 +561,15 @@ def test_subject_and_feature_permutation_equivariance():
 # ------------------------------------------------------------------ sharded oracle (full sizes)
 
 
-@pytest.mark.parametrize("cfg_name,K,R,l", [("c2", 120, 10, 7), ("c5", 90, 5, 0)])
-def test_sharded_oracle_equals_one_process(cfg_name, K, R, l):
+@pytest.mark.parametrize("cfg_name,K,R,l,order", [("c2", 120, 10, 7, "HWV"), ("c5", 90, 5, 0, "HWV"),
+                                                   ("c2", 120, 10, 7, "WHV")])
+def test_sharded_oracle_equals_one_process(cfg_name, K, R, l, order):
     """The sharded driver that writes the full-size reference trajectories runs the same steps as
     copa_fit: same FIT, objective, sparsity and factors up to summation order."""
     from oracle import fullsize
     coh, cfg = synth.make_config(cfg_name, K=K)
     H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
-    opt = co.Options(R=R, outer_iters=3)
+    opt = co.Options(R=R, outer_iters=3, order=order)
     ref = co.copa_fit(co.build_problem(coh, l), H0, W0, V0, opt)
     got = fullsize.copa_fit_sharded(coh, l, H0, W0, V0, opt, workers=3, want_Q=True)
     np.testing.assert_allclose(got["fit"], ref.fit, rtol=1e-12)
