@@ -37,7 +37,8 @@ CSRC = os.path.join(ROOT, "paper_1803_04572_amd", "csrc")
 # rocprofv3 kernel-name stem of each timed kernel
 ROCPROF_NAME = {"pass1": "k_pass1", "procrustes": "k_procrustes", "gram_FH": "k_rows_gram_fit",
                 "mode_H": "k_mode_H", "w_admm": "k_w_admm", "gram_WM": "k_rows_gram",
-                "pass2": "k_pass2c", "v_admm": "k_v_admm"}
+                "pass2": "k_pass2c", "v_admm": "k_v_admm", "w_first": "k_w_first",
+                "m_rows": "k_m_rows", "finish": "k_finish_whv"}
 
 
 def kernel_source_hash():
@@ -90,10 +91,14 @@ def algorithmic_bytes(coh, R, l, compact):
         "gram_WM": K * R * 4 + rows * R * 4,
         "pass2": x2 + rows * R * 4 + J * R * 4,
         "v_admm": J * R * 4 * 5,
+        # block order W -> H -> V
+        "w_first": rows * R * 4 * 2 + K * R * 4 * 5,
+        "m_rows": rows * R * 4 * 2 + K * R * 4,
+        "finish": R * R * 8 * 4,
     }
 
 
-def cpu_baseline(cfg_name, R, l, K_full, n_subjects, iters=3):
+def cpu_baseline(cfg_name, R, l, K_full, n_subjects, iters=3, order="HWV"):
     """The FP64 oracle, as it is, on a bounded sample of the same workload: `iters` outer
     iterations on a cohort of `n_subjects` drawn with the same recipe, its subjects split over the
     host's cores (the oracle's sharded driver, one BLAS thread per worker), scaled by subject
@@ -104,7 +109,7 @@ def cpu_baseline(cfg_name, R, l, K_full, n_subjects, iters=3):
     workers = max(1, min(16, os.cpu_count() or 1))
     coh, cfg = synth.make_config(cfg_name, K=min(n_subjects, K_full))
     H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
-    opt = co.Options(R=R, outer_iters=iters, inner_iters=cfg["inner"])
+    opt = co.Options(R=R, outer_iters=iters, inner_iters=cfg["inner"], order=order)
     marks = []
     fullsize.copa_fit_sharded(coh, l, H0, W0, V0, opt, workers=workers,
                               progress=lambda msg: marks.append(time.perf_counter()))
@@ -137,11 +142,12 @@ def load_or_make(workload, cache, progress):
     return coh, cfg
 
 
-def golden_check(workload, R, coh, fit_history, H, V, tol):
+def golden_check(workload, R, coh, fit_history, H, V, tol, order="HWV"):
     """Compares a fit started from the seeded initial point with the FP64 oracle's trajectory on
-    the same inputs, stored by tests/golden/make_fullsize_golden.py. None when no trajectory is
-    stored for this workload."""
-    path = os.path.join(ROOT, "tests", "golden", f"fullsize_{workload}_R{R}.json")
+    the same inputs and in the same block order, stored by tests/golden/make_fullsize_golden.py.
+    None when no trajectory is stored for this workload."""
+    stem = f"fullsize_{workload}_R{R}" + ("_WHV" if order == "WHV" else "")
+    path = os.path.join(ROOT, "tests", "golden", stem + ".json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -156,7 +162,7 @@ def golden_check(workload, R, coh, fit_history, H, V, tol):
            "fit_rel": float(rel[-1]), "fit_rel_max_history": float(rel.max()), "tol": tol,
            "passed": bool(rel[-1] <= tol), "oracle_file": os.path.relpath(path, ROOT)}
     if n == len(g["fit"]) and H is not None:
-        z = np.load(os.path.join(ROOT, "tests", "golden", f"fullsize_{workload}_R{R}.npz"))
+        z = np.load(os.path.join(ROOT, "tests", "golden", stem + ".npz"))
 
         def cong(A, B):
             num = np.abs(np.sum(A * B, axis=0))
@@ -180,6 +186,9 @@ def main():
     ap.add_argument("--precision", choices=("fp32", "mixed"), default="fp32",
                     help="mixed: bfloat16 records of the projected data, FP32 accumulation, one "
                          "FP32 refinement iteration per fit call")
+    ap.add_argument("--order", choices=("HWV", "WHV"), default="HWV",
+                    help="block order of an outer iteration: Algorithm 1's H -> W -> V, or "
+                         "W -> H -> V (same fixed points, different iterates)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (HBM counter scaling)")
@@ -207,7 +216,7 @@ def main():
     mixed = args.precision == "mixed"
     plan = copa.Plan.from_cohort(coh, R=R, l=l, inner_iters=cfg["inner"],
                                  precision=copa.PREC_MIXED if mixed else copa.PREC_FP32,
-                                 mixed_refine=1)
+                                 mixed_refine=1, order=args.order)
     progress("plan ready")
     H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
     init = plan.new_state(H0, W0, V0)
@@ -240,7 +249,8 @@ def main():
         hist = rc["fit_history"]
         Hf, Vf = chk["H"].double().cpu().numpy(), chk["V"].double().cpu().numpy()
         del chk
-    gate = golden_check(args.workload, R, coh, hist, Hf, Vf, tol=1e-4 if mixed else 1e-5)
+    gate = golden_check(args.workload, R, coh, hist, Hf, Vf, tol=1e-4 if mixed else 1e-5,
+                        order=args.order)
     progress(f"gate: {gate}")
 
     # the same number of steps again with HIP events around every kernel launch
@@ -256,6 +266,8 @@ def main():
     npairs = plan.query("pairs")
     shapes = {k: plan.query(k) for k in ("tuned", "pass1_blocks_per_cu", "procrustes_variant",
                                          "gram_blocks", "pass2_blocks")}
+    if args.order == "WHV":
+        shapes.update({k: plan.query(k) for k in ("wfirst_blocks", "mrows_blocks")})
     abytes = algorithmic_bytes(coh, R, l, compact)
     per_kernel = {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in timing.items()
                   if n > 0}
@@ -266,7 +278,7 @@ def main():
     dom = max((k for k in per_kernel if k in abytes), key=lambda k: per_kernel[k]["avg_us"])
     ach = per_kernel[dom]["GBps"]
     traffic = measured_traffic(dom, args.workload + ("" if args.R is None else f"_R{R}")
-                               + ("_mixed" if mixed else ""))
+                               + ("_mixed" if mixed else "") + ("_WHV" if args.order == "WHV" else ""))
     if args.copy_probe:
         # a plain elementwise kernel of known size for the HBM counters' scale: reads and writes
         # 256 MiB once per launch
@@ -282,7 +294,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         progress("cpu baseline")
-        cpu = cpu_baseline(args.workload, R, l, coh.K, n_subjects=40_000)
+        cpu = cpu_baseline(args.workload, R, l, coh.K, n_subjects=40_000, order=args.order)
 
     mttkrp = {k: {"GBps": round(per_kernel[k]["GBps"], 1),
                   "frac_hbm": round(per_kernel[k]["GBps"] / HBM_PEAK_GBS, 4)}
@@ -309,7 +321,7 @@ def main():
                    "streamed": (f"projected pairs C_k^T X_k ({npairs} records, "
                                 + ("16-byte bfloat16" if mixed else "32-byte FP32") + ")")
                    if npairs else "nonzeros and basis rows",
-                   "precision": args.precision},
+                   "precision": args.precision, "block_order": args.order},
         "gate": gate,
         "launch_shapes": shapes,
         "value_if_ungated": value,

@@ -91,6 +91,14 @@ typedef struct copa_tensor {
  *          and at most two nonzeros per visit row on average (COPA_EUNSUPPORTED otherwise).   */
 typedef enum { COPA_PREC_FP32 = 0, COPA_PREC_MIXED = 1 } copa_precision;
 
+/* Block order of one outer iteration (copa_options.order). Algorithm 1 updates its blocks
+ * Z1 = H, Z2 = W (the diagonals of S_k), Z3 = V in that order (HWV). WHV updates W first, with
+ * the H of the previous outer iteration, then H with the new W, then V: the same blocks and the
+ * same fixed points, different iterates. On the GPU it lets the W update share one pass over the
+ * Procrustes outputs with the H block's MTTKRP, instead of two passes and a written M row set
+ * that is read again.                                                                           */
+typedef enum { COPA_ORDER_HWV = 0, COPA_ORDER_WHV = 1 } copa_order;
+
 /* Fit options. R: target rank (this build: 1..64 from the list copa_rank_supported accepts).
  * inner_iters: ADMM steps per factor per outer iteration (>= 1). rank_rtol: Procrustes
  * truncation - singular values of X_k' V S_k H^T at or below rank_rtol * sigma_1 are dropped
@@ -124,6 +132,7 @@ typedef struct copa_options {
    * <compute units> : <four shapes>"; tuned shapes are appended there). Not with deterministic
    * = 1, whose fixed summation order needs fixed shapes. 0: fixed default shapes.            */
   int32_t autotune;
+  int32_t order;  /* copa_order; 0 = Algorithm 1's H -> W -> V                              */
 } copa_options;
 
 /* Fit state, device memory owned by the caller, FP32 row-major. In: the starting point
@@ -248,7 +257,7 @@ copa_status copa_stationarity(copa_plan *plan, const float *H, const float *V, c
  * copa_read_timing writes, per kernel id in [0, COPA_NUM_KERNELS), the summed milliseconds
  * (`ms`, host) and launch counts (`launches`, host) since the previous read, then resets them.
  * copa_kernel_name(id) names the kernel.                                                     */
-#define COPA_NUM_KERNELS 8
+#define COPA_NUM_KERNELS 11
 copa_status copa_set_timing(copa_plan *plan, int32_t enable);
 copa_status copa_read_timing(copa_plan *plan, double *ms, int64_t *launches);
 const char *copa_kernel_name(int32_t id);
@@ -264,7 +273,9 @@ const char *copa_kernel_name(int32_t id);
  *   COPA_QUERY_TUNED    0 launch shapes not tuned (yet), 1 timed on this plan, 2 read from the
  *                       tuning cache file,
  *   COPA_QUERY_PASS1_BLOCKS_PER_CU, COPA_QUERY_PROCRUSTES_VARIANT, COPA_QUERY_GRAM_BLOCKS,
- *   COPA_QUERY_PASS2_BLOCKS   the launch shapes in use (see copa_options.autotune).
+ *   COPA_QUERY_PASS2_BLOCKS   the launch shapes in use (see copa_options.autotune),
+ *   COPA_QUERY_WFIRST_BLOCKS, COPA_QUERY_MROWS_BLOCKS   block order W -> H -> V: blocks of the
+ *                       persistent W-block and M-row launches (0 before the first fit).
  * *out (host) receives the value. COPA_EINVAL for a NULL argument or an unknown `what`.       */
 #define COPA_QUERY_COMPACT 0
 #define COPA_QUERY_CHUNKS 1
@@ -275,6 +286,8 @@ const char *copa_kernel_name(int32_t id);
 #define COPA_QUERY_PROCRUSTES_VARIANT 6
 #define COPA_QUERY_GRAM_BLOCKS 7
 #define COPA_QUERY_PASS2_BLOCKS 8
+#define COPA_QUERY_WFIRST_BLOCKS 9
+#define COPA_QUERY_MROWS_BLOCKS 10
 copa_status copa_plan_query(const copa_plan *plan, int32_t what, int64_t *out);
 
 /* 1 if this build has kernels for rank R, else 0.                                           */

@@ -19,6 +19,15 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcopa.so"
 OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PROX_NONE, PROX_NONNEG, PROX_L1, PROX_L0, PROX_NONNEG_L1 = 0, 1, 2, 3, 4
 PREC_FP32, PREC_MIXED = 0, 1
+ORDER_HWV, ORDER_WHV = 0, 1
+
+
+def _order(order):
+    """Block order as copa_order: "HWV" / "WHV" or the integer."""
+    if isinstance(order, str):
+        return {"HWV": ORDER_HWV, "WHV": ORDER_WHV}[order.upper()]
+    return int(order)
+
 
 # every function declared in include/copa.h
 SYMBOLS = ("copa_workspace_bytes", "copa_plan_create", "copa_fit", "copa_mttkrp_last",
@@ -26,7 +35,7 @@ SYMBOLS = ("copa_workspace_bytes", "copa_plan_create", "copa_fit", "copa_mttkrp_
            "copa_loss_grad", "copa_plan_destroy", "copa_rank_supported", "copa_status_string",
            "copa_last_error", "copa_set_timing", "copa_read_timing", "copa_kernel_name",
            "copa_plan_query", "copa_set_graph", "copa_stationarity", "copa_loss_grad_static")
-NUM_KERNELS = 8
+NUM_KERNELS = 11
 
 
 class CopaTensor(ctypes.Structure):
@@ -41,7 +50,7 @@ class CopaOptions(ctypes.Structure):
                 ("lambda_W", c_double), ("lambda_V", c_double), ("rank_rtol", c_double),
                 ("basis_rtol", c_double), ("stop_tol", c_double), ("check_every", c_int32),
                 ("precision", c_int32), ("mixed_refine", c_int32), ("deterministic", c_int32),
-                ("adjoint", c_int32), ("autotune", c_int32)]
+                ("adjoint", c_int32), ("autotune", c_int32), ("order", c_int32)]
 
 
 class CopaState(ctypes.Structure):
@@ -142,9 +151,10 @@ class Plan:
                  prox=(PROX_NONE, PROX_NONNEG, PROX_L1), lam=(0.0, 0.0, 0.1), rank_rtol=1e-6,
                  basis_rtol=1e-10, stop_tol=0.0, check_every=10, basis=None,
                  precision=PREC_FP32, mixed_refine=1, deterministic=False, adjoint=False,
-                 autotune=True, workspace="library"):
+                 autotune=True, workspace="library", order="HWV"):
         """workspace: "library" (the library allocates it once) or "caller" (a torch uint8
-        tensor of copa_workspace_bytes bytes, kept by this object)."""
+        tensor of copa_workspace_bytes bytes, kept by this object). order: block order of an
+        outer iteration, "HWV" (Algorithm 1) or "WHV"."""
         import torch
         K = subj_ptr.numel() - 1
         S = row_ptr.numel() - 1
@@ -161,7 +171,7 @@ class Plan:
                         stop_tol=float(stop_tol), check_every=int(check_every),
                         precision=int(precision), mixed_refine=int(mixed_refine),
                         deterministic=int(bool(deterministic)), adjoint=int(bool(adjoint)),
-                        autotune=int(bool(autotune)))
+                        autotune=int(bool(autotune)), order=_order(order))
         self._ws = None
         ws_ptr, ws_bytes = None, 0
         if workspace == "caller":
@@ -186,7 +196,8 @@ class Plan:
                         mixed_refine=int(opts.get("mixed_refine", 1)),
                         deterministic=int(bool(opts.get("deterministic", False))),
                         adjoint=int(bool(opts.get("adjoint", False))),
-                        stop_tol=float(opts.get("stop_tol", 0.0)))
+                        stop_tol=float(opts.get("stop_tol", 0.0)),
+                        order=_order(opts.get("order", "HWV")))
         nb = ctypes.c_size_t(0)
         _check(lib().copa_workspace_bytes(ctypes.byref(t), ctypes.byref(o), ctypes.byref(nb)),
                "copa_workspace_bytes")
@@ -307,7 +318,7 @@ class Plan:
         pairs the passes stream; 0 when they stream nonzeros and basis rows)."""
         code = {"compact": 0, "chunks": 1, "waves": 2, "pairs": 3, "tuned": 4,
                 "pass1_blocks_per_cu": 5, "procrustes_variant": 6, "gram_blocks": 7,
-                "pass2_blocks": 8}[what]
+                "pass2_blocks": 8, "wfirst_blocks": 9, "mrows_blocks": 10}[what]
         out = c_int64(0)
         _check(lib().copa_plan_query(self._h, code, ctypes.byref(out)), "copa_plan_query")
         return int(out.value)

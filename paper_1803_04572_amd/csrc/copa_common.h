@@ -23,7 +23,7 @@ constexpr int kGramSlots = 6;      // F_H, W^TW, Psi, V^TV partials; adjoint G a
 __host__ __device__ constexpr int64_t gram_total_offset(int maxnb) { return (int64_t)maxnb; }
 constexpr int kChunkRows = 512;    // visit rows per chunk of the feature-sorted pass-2 layout
 constexpr int kMaxR = 64;
-constexpr int kNumKernels = 8;     // kernels of one outer iteration (see kernel_names)
+constexpr int kNumKernels = 11;    // kernels of one outer iteration (see kernel_names)
 constexpr int kTimingChunk = 64;   // iterations between event harvests when timing
 
 void set_error(const std::string &msg);
@@ -154,8 +154,11 @@ struct copa_plan {
   int32_t *gcount = nullptr;  // [8] last-block counters of the row Grams
   double *vpart = nullptr;  // [blocks x 4] V-ADMM scalar partials
   int n_vblocks = 0;
-  double *wpart = nullptr;  // [n_wblocks] |W|_1 partials of the W update
+  double *wpart = nullptr;  // [max(n_wblocks, wf_cap)] |W|_1 partials of the W update
   int n_wblocks = 0;        // W-update blocks: 4 wavefronts of 64 / R subjects
+  int wf_blocks = 0;        // order W -> H -> V: blocks of the persistent W-first launch,
+  int mr_blocks = 0;        // of the M-row launch (resident blocks per CU x CUs),
+  int wf_cap = 0;           // at most wf_cap <= gcap
   double *small = nullptr;  // FH, HtH, WtW, VtV, Psi : 5 x R x R
   copa::ModeParams *modes = nullptr;  // [3]
   copa::FitScalars *scal = nullptr;

@@ -73,8 +73,9 @@ Tiles choose_tiles2(int R, int64_t J, int lds_limit) {
   return Tiles{0, 0, 0};
 }
 
-const char *const kernel_names[kNumKernels] = {"pass1",  "procrustes", "gram_FH", "mode_H",
-                                               "w_admm", "gram_WM",    "pass2",   "v_admm"};
+const char *const kernel_names[kNumKernels] = {
+    "pass1", "procrustes", "gram_FH", "mode_H", "w_admm", "gram_WM", "pass2", "v_admm",
+    "w_first", "m_rows", "finish"};
 
 copa_status harvest_timing(copa_plan *p) {
   for (size_t e = 0; e < p->ev_kid.size(); ++e) {
@@ -418,6 +419,8 @@ copa_status copa_plan_query(const copa_plan *p, int32_t what, int64_t *out) {
     case COPA_QUERY_PROCRUSTES_VARIANT: *out = p->proc_variant; return COPA_OK;
     case COPA_QUERY_GRAM_BLOCKS: *out = p->gram_blocks; return COPA_OK;
     case COPA_QUERY_PASS2_BLOCKS: *out = p->p2_blocks; return COPA_OK;
+    case COPA_QUERY_WFIRST_BLOCKS: *out = p->wf_blocks; return COPA_OK;
+    case COPA_QUERY_MROWS_BLOCKS: *out = p->mr_blocks; return COPA_OK;
     case COPA_QUERY_WAVES: *out = p->n_waves; return COPA_OK;
     default: set_error("unknown query"); return COPA_EINVAL;
   }

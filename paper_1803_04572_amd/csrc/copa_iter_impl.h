@@ -1508,19 +1508,26 @@ __global__ void __launch_bounds__(256)
     q += (r >= lR) - (r < 0);
     return f + q;
   };
-  const int t = threadIdx.x, s = t & 63, w = t >> 6;
+  const int t = threadIdx.x, s = t & 63;
+  // (the wavefront index through readfirstlane: the H entries below are then wavefront-uniform
+  // loads, which go to scalar registers instead of LDS)
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int64_t k0 = (int64_t)blockIdx.x * 64;
   const int nsub = (int)(K - k0 < 64 ? K - k0 : 64);
-  for (int e = t; e < R * R; e += 256) sH[e] = H[e];
   {
+    // the 64 subjects' rows t_i * w_k, staged once
     const float *src = T + k0 * lR;
+    const float *wsrc = W + k0 * R;
     const int n = nsub * lR, total = 64 * lR;
     for (int e0 = 0; e0 < total; e0 += 8 * 256) {
       float v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + u * 256 + t;
-        v[u] = e < n ? src[e] : 0.0f;
+        const int sj = (int)((float)e * inv_lR);  // subject of element e (corrected below)
+        const int rem = e - sj * lR;
+        const int sjc = sj + (rem >= lR) - (rem < 0);
+        v[u] = e < n ? src[e] * wsrc[sjc * R + (e - sjc * lR) % R] : 0.0f;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -1529,23 +1536,38 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  const int64_t k = k0 + (s < nsub ? s : 0);
   float *x = sX + s * stride;
   const int c_lo = w * RQ;
   __syncthreads();
-  // a_i = (t_i * w) H^T on this wavefront's columns, every row of the subject
+  // a_i = (t_i * w) H^T on this wavefront's columns, every row of the subject: four entries of
+  // each H column at a time (scalar registers), applied to every row
+  constexpr bool kFullCols = R % 4 == 0;  // (then every wavefront's RQ columns exist)
   float a[N][RQ];
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
+  for (int i = 0; i < N; ++i)
 #pragma unroll
     for (int cc = 0; cc < RQ; ++cc) a[i][cc] = 0.0f;
-    if (i < l) {
-#pragma unroll 2
-      for (int r = 0; r < R; ++r) {
-        const float y = x[i * R + r] * W[k * R + r];
 #pragma unroll
-        for (int cc = 0; cc < RQ; ++cc)
-          if (c_lo + cc < R) a[i][cc] = fmaf(y, sH[(c_lo + cc) * R + r], a[i][cc]);
+  for (int r0 = 0; r0 < R; r0 += 4) {
+    float h[RQ][4];
+#pragma unroll
+    for (int cc = 0; cc < RQ; ++cc)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c_lo + cc, r = r0 + u;
+        h[cc][u] = (r < R && (kFullCols || c < R)) ? H[c * R + r] : 0.0f;
+      }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (i < l) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (r0 + u < R) {
+            const float y = x[i * R + r0 + u];
+#pragma unroll
+            for (int cc = 0; cc < RQ; ++cc) a[i][cc] = fmaf(y, h[cc][u], a[i][cc]);
+          }
+        }
       }
     }
   }
@@ -2005,8 +2027,8 @@ static void gram_fit(copa_plan *p, const float *A, const float *B, int64_t rows,
 // H^T H; then the W-mode system G_W = H^TH * V^TV for the W update.
 template <int R>
 __global__ void __launch_bounds__(256)
-    k_mode_H(const double *FHtot, double *small, ModeParams *modes, FitScalars *sc,
-             float *H, float *DH, int kind, double lam, int iters) {
+    k_mode_H(const double *FHtot, const double *WtWtot, double *small, ModeParams *modes,
+             FitScalars *sc, float *H, float *DH, int kind, double lam, int iters, int build_w) {
   constexpr int RR = R * R;
   constexpr int G = kWave / R;
   __shared__ double sFH[RR], sX[RR], sY[RR], sL[RR], sGi[RR];
@@ -2016,13 +2038,17 @@ __global__ void __launch_bounds__(256)
   __shared__ int sflag;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int g = lane / R, c = lane % R;
+  // W^T W: the stored one (H first) or the new W's total (W first)
   for (int e = t; e < RR; e += blockDim.x) {
     sFH[e] = FHtot[e];
-    sX[e] = small[kWtW * RR + e];
+    sX[e] = WtWtot ? WtWtot[e] : small[kWtW * RR + e];
     sY[e] = small[kVtV * RR + e];
   }
   __syncthreads();
-  for (int e = t; e < RR; e += blockDim.x) small[kFH * RR + e] = sFH[e];
+  for (int e = t; e < RR; e += blockDim.x) {
+    small[kFH * RR + e] = sFH[e];
+    if (WtWtot) small[kWtW * RR + e] = sX[e];
+  }
   bool ok = build_system<R>(sX, sY, sL, sGi, &srho, &sflag);
   if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
   const double rho = srho;
@@ -2048,6 +2074,7 @@ __global__ void __launch_bounds__(256)
     small[kHtH * RR + e] = v;
   }
   __syncthreads();
+  if (!build_w) return;  // (W first: the next W system needs the new V)
   ok = build_system<R>(sX, sY, sL, sGi, &srho, &sflag);
   if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
   for (int e = t; e < RR; e += blockDim.x) modes[1].Gi[e] = sGi[e];
@@ -2161,6 +2188,329 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
   }
   if (t == 0) l1part[blockIdx.x] = sred[0];
+}
+
+// ======================================================================= W block first
+// The inner ADMM steps of admm_lanes, the product with (G + rho I)^{-1} (sGi, LDS: lanes of one
+// column read the same word, the R columns adjacent words) in four partial sums, which shortens
+// the dependency chain of each step.
+template <int R>
+__device__ __forceinline__ void admm_lanes_reg(double F, float &Zb, float &D,
+                                               const double *__restrict__ sGi, double rho,
+                                               int kind, double lam, int iters, double *xrow,
+                                               int c) {
+  const double thr = lam / rho;
+  for (int it = 0; it < iters; ++it) {
+    xrow[c] = F + rho * ((double)Zb + (double)D);
+    __builtin_amdgcn_wave_barrier();
+    double zs[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < R; ++k) zs[k & 3] += xrow[k] * sGi[k * R + c];
+    const double z = (zs[0] + zs[1]) + (zs[2] + zs[3]);
+    __builtin_amdgcn_wave_barrier();
+    const double zb = prox_sel(z - (double)D, kind, lam, thr);
+    D = (float)((double)D + zb - z);
+    Zb = (float)zb;
+  }
+}
+
+// Adds the per-lane column accumulators acc[r] = X(r, c) of the 4 G lane groups of a block in a
+// fixed order (groups of a wavefront in turn through LDS, then the four wavefronts) and stores
+// the block's R x R partial. Whole block; red: 4 x R x R doubles of LDS.
+template <int R>
+__device__ __forceinline__ void block_columns_to_part(const double (&acc)[R], double (*red)[R * R],
+                                                      double *__restrict__ part) {
+  constexpr int G = kWave / R;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = lane / R, c = lane % R;
+  for (int gg = 0; gg < G; ++gg) {
+    if (g == gg) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        red[wave][r * R + c] = (gg == 0 ? 0.0 : red[wave][r * R + c]) + acc[r];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  for (int e = t; e < R * R; e += blockDim.x)
+    part[(int64_t)blockIdx.x * R * R + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+  __syncthreads();
+}
+
+// Block order W -> H -> V, one subject of the W block (R lanes, lane c holds column c): given
+// F_W(k, c) and column c of P_k, the inner ADMM steps on W's row k, its store, and the lane's
+// running sums of F_H(:, c) = sum_k P_k(:, c) w_k(c) and (W^T W)(:, c).
+template <int R>
+__device__ __forceinline__ void w_first_row(int64_t k, bool act, double F, const float (&pc)[R],
+                                            float Zb, float D, const double *__restrict__ sGi,
+                                            double rho, int kind, double lam, int iters,
+                                            double *xrow, int c, float *__restrict__ W,
+                                            float *__restrict__ DW, float *__restrict__ FW,
+                                            double (&fh)[R], double (&wtw)[R], double &l1) {
+  if (act) FW[k * R + c] = (float)F;
+  admm_lanes_reg<R>(F, Zb, D, sGi, rho, kind, lam, iters, xrow, c);
+  const double w = act ? (double)Zb : 0.0;
+  if (act) {
+    W[k * R + c] = Zb;
+    DW[k * R + c] = D;
+    l1 += fabs(w);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) fh[r] += (double)pc[r] * w;
+  // W^T W: the new row through this group's LDS slot
+  __builtin_amdgcn_wave_barrier();
+  xrow[c] = w;
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int r = 0; r < R; ++r) wtw[r] += xrow[r] * w;
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Block order W -> H -> V: the W block right after the Procrustes step, then the H block's
+// inputs. One subject per group of R lanes (lane c holds column c), each block striding over
+// groups of 4 G subjects:
+//   P_k = Q_k^T T_k (column c per lane), F_W(k, c) = sum_r H(r, c) P_k(r, c) with the H of the
+//   previous outer iteration, the inner ADMM steps on W's row k with the W system built from
+//   that H (modes[1]); then, with the new row w_k, the block's partials of
+//   F_H = sum_k P_k diag(w_k), of W^T W and of |W|_1.
+// The rows T_k and Q_k are read once; nothing per subject is written but W's row and F_W.
+// Smoothed plans (l rows per subject) load the next subject's rows while the current one is
+// processed.
+// (two wavefronts per SIMD where the registers allow it without spills: R <= 20)
+template <int R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R <= 20 ? 2 : 1)))
+    k_w_first(int64_t K, int l, const int32_t *__restrict__ subj, const int32_t *__restrict__ rk,
+              const float *__restrict__ T, const float *__restrict__ Q,
+              const float *__restrict__ H, float *__restrict__ W, float *__restrict__ DW,
+              float *__restrict__ FW, const ModeParams *__restrict__ modes, int kind, double lam,
+              int iters, double *__restrict__ l1part, double *__restrict__ fhpart,
+              double *__restrict__ wtwpart) {
+  constexpr int G = kWave / R;
+  __shared__ float xq[4][G + 1][kLMax][R];
+  __shared__ float xtq[4][G + 1][kLMax][R];
+  __shared__ double xch[4][G + 1][R];
+  __shared__ double red[4][R * R];
+  __shared__ double sGi[R * R];
+  __shared__ double sred[256];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = lane / R, c = lane % R;
+  double fh[R], wtw[R];
+  float hcol[R];
+  for (int e = t; e < R * R; e += blockDim.x) sGi[e] = modes[1].Gi[e];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    hcol[r] = H[r * R + c];
+    fh[r] = 0.0;
+    wtw[r] = 0.0;
+  }
+  const double rho = modes[1].rho;
+  __syncthreads();
+  float(&xg)[kLMax][R] = xq[wave][g];
+  float(&xt)[kLMax][R] = xtq[wave][g];
+  double *xrow = xch[wave][g];
+  double l1 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 4 * G;
+  const int64_t first = (int64_t)blockIdx.x * 4 * G + wave * G + g;
+  if (l > 0) {
+    // rows, W entry, dual and rank of subject kk (clamped to subject 0 past the end)
+    float qv[kLMax], tv[kLMax], Zb, D;
+    int m;
+    // (the kLMax row slots from the subject's first row: rows past its l belong to the next
+    // subject or to the buffers' slack rows, and are masked by the rank m <= l)
+    auto fetch = [&](int64_t kk, float(&q)[kLMax], float(&tt)[kLMax], float &zb, float &d,
+                     int &mm) {
+      const bool a = g < G && kk < K;
+      const int64_t kc = a ? kk : 0;
+      const float *qb = Q + kc * l * R + c, *tb = T + kc * l * R + c;
+#pragma unroll
+      for (int i = 0; i < kLMax; ++i) {
+        q[i] = qb[i * R];
+        tt[i] = tb[i * R];
+      }
+      zb = W[kc * R + c];
+      d = DW[kc * R + c];
+      mm = a ? rk[kc] : 0;
+    };
+    if (first - wave * G - g < K) fetch(first, qv, tv, Zb, D, m);
+    for (int64_t k = first; k - wave * G - g < K; k += stride) {
+      const bool act = g < G && k < K;
+      float qn[kLMax], tn[kLMax], Zn, Dn;
+      int mn;
+      fetch(k + stride, qn, tn, Zn, Dn, mn);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int i = 0; i < kLMax; ++i) {
+        xg[i][c] = qv[i];
+        xt[i][c] = tv[i];
+      }
+      __builtin_amdgcn_wave_barrier();
+      double F = 0.0;
+      float pc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) pc[r] = 0.0f;
+      // the rank-m rows two at a time (rows staged in LDS keep the registers for the sums)
+#pragma unroll 2
+      for (int i = 0; i < m; ++i) {
+        const float ti = xt[i][c];
+        float p = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float x = xg[i][r];
+          p = fmaf(x, hcol[r], p);
+          pc[r] = fmaf(x, ti, pc[r]);
+        }
+        F += (double)p * (double)ti;
+      }
+      w_first_row<R>(k, act, F, pc, Zb, D, sGi, rho, kind, lam, iters, xrow, c, W, DW, FW, fh,
+                     wtw, l1);
+#pragma unroll
+      for (int i = 0; i < kLMax; ++i) {
+        qv[i] = qn[i];
+        tv[i] = tn[i];
+      }
+      Zb = Zn;
+      D = Dn;
+      m = mn;
+    }
+  } else {
+    for (int64_t k = first; k - wave * G - g < K; k += stride) {
+      const bool act = g < G && k < K;
+      const int64_t kc = act ? k : 0;
+      const float Zb = W[kc * R + c], D = DW[kc * R + c];
+      const int64_t base = subj[kc];
+      const int m = act ? subj[kc + 1] - subj[kc] : 0;
+      double F = 0.0;
+      float pc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) pc[r] = 0.0f;
+      for (int i = 0; i < m; ++i) {
+        const float qv = Q[(base + i) * R + c], ti = T[(base + i) * R + c];
+        __builtin_amdgcn_wave_barrier();
+        xg[0][c] = qv;
+        __builtin_amdgcn_wave_barrier();
+        float p = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float x = xg[0][r];
+          p = fmaf(x, hcol[r], p);
+          pc[r] = fmaf(x, ti, pc[r]);
+        }
+        F += (double)p * (double)ti;
+      }
+      w_first_row<R>(k, act, F, pc, Zb, D, sGi, rho, kind, lam, iters, xrow, c, W, DW, FW, fh,
+                     wtw, l1);
+    }
+  }
+  __syncthreads();
+  block_columns_to_part<R>(fh, red, fhpart);
+  block_columns_to_part<R>(wtw, red, wtwpart);
+  sred[t] = l1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sred[t] += sred[t + w];
+    __syncthreads();
+  }
+  if (t == 0) l1part[blockIdx.x] = sred[0];
+}
+
+// Block order W -> H -> V, after the H block: the M rows M_i = (q_i H) * w_k of every row i
+// (subject k) for pass 2 and the block's partial of Psi = sum_i M_i^T M_i. Each group of R lanes
+// takes kMRows consecutive rows at a time (their loads in flight together), each block striding
+// over groups of 4 G kMRows rows.
+constexpr int kMRows = 8;
+template <int R>
+__global__ void __launch_bounds__(256)
+    k_m_rows(int64_t rows, int l, const int32_t *__restrict__ rowsubj,
+             const float *__restrict__ Q, const float *__restrict__ H,
+             const float *__restrict__ W, float *__restrict__ M, double *__restrict__ psipart) {
+  constexpr int G = kWave / R;
+  __shared__ float xq[4][G + 1][kMRows][R];
+  __shared__ double red[4][R * R];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = lane / R, c = lane % R;
+  double psi[R];
+  float hcol[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    hcol[r] = H[r * R + c];
+    psi[r] = 0.0;
+  }
+  float(&xr)[kMRows][R] = xq[wave][g];
+  const int64_t step = (int64_t)4 * G * kMRows;
+  for (int64_t i0 = (int64_t)blockIdx.x * step; i0 < rows; i0 += (int64_t)gridDim.x * step) {
+    const int64_t ib = i0 + (int64_t)(wave * G + g) * kMRows;
+    float q[kMRows], w[kMRows];
+#pragma unroll
+    for (int u = 0; u < kMRows; ++u) {
+      const int64_t i = ib + u;
+      const int64_t ic = g < G && i < rows ? i : 0;
+      const int64_t k = l > 0 ? ic / l : (int64_t)rowsubj[ic];
+      q[u] = Q[ic * R + c];
+      w[u] = W[k * R + c];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 0; u < kMRows; ++u) xr[u][c] = q[u];
+    __builtin_amdgcn_wave_barrier();
+    float mv[kMRows];
+#pragma unroll
+    for (int u = 0; u < kMRows; ++u) {
+      float p = 0.0f;
+#pragma unroll
+      for (int r = 0; r < R; ++r) p = fmaf(xr[u][r], hcol[r], p);
+      const int64_t i = ib + u;
+      const bool act = g < G && i < rows;
+      mv[u] = act ? p * w[u] : 0.0f;
+      if (act) M[i * R + c] = mv[u];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 0; u < kMRows; ++u) xr[u][c] = mv[u];
+    __builtin_amdgcn_wave_barrier();
+    // the kMRows rows' products summed in FP32, the running sum in FP64
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float s8 = 0.0f;
+#pragma unroll
+      for (int u = 0; u < kMRows; ++u) s8 = fmaf(xr[u][r], mv[u], s8);
+      psi[r] += (double)s8;
+    }
+  }
+  __syncthreads();
+  block_columns_to_part<R>(psi, red, psipart);
+}
+
+// Block order W -> H -> V, end of an outer iteration (with_fit) or of the set-up: the FIT and
+// objective of the iteration (fit_finalize, which also stores V^T V), then the W system of the
+// next W block, (H^T H * V^T V + rho I)^{-1} with H^T H of the current H in FP64. One block.
+template <int R>
+__global__ void __launch_bounds__(256)
+    k_finish_whv(FitArgs fa, int with_fit, const float *__restrict__ H, double *small,
+                 ModeParams *modes, FitScalars *sc) {
+  constexpr int RR = R * R;
+  __shared__ double red[6][256];
+  __shared__ double sVtV[RR], sX[RR], sL[RR], sGi[RR];
+  __shared__ double srho;
+  __shared__ int sflag;
+  const int t = threadIdx.x;
+  const int it = sc->cur;
+  if (with_fit) {
+    fit_finalize<R>(fa, it, H, small, sc, red, sVtV);
+  } else {
+    for (int e = t; e < RR; e += blockDim.x) sVtV[e] = small[kVtV * RR + e];
+  }
+  for (int e = t; e < RR; e += blockDim.x) {
+    const int a = e / R, b = e % R;
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) v += (double)H[i * R + a] * (double)H[i * R + b];
+    sX[e] = v;
+  }
+  __syncthreads();
+  const bool ok = build_system<R>(sX, sVtV, sL, sGi, &srho, &sflag);
+  if (t == 0 && !ok) atomicMin(&sc->fail_iter, it > 0 ? it : 0);
+  for (int e = t; e < RR; e += blockDim.x) modes[1].Gi[e] = sGi[e];
+  if (t == 0) modes[1].rho = srho;
 }
 
 // ======================================================================= mode V
@@ -2387,7 +2737,10 @@ static void launch_pass2_rt(copa_plan *p, hipStream_t s) {
   }
 
 
-enum { kidPass1, kidProcrustes, kidGramFH, kidModeH, kidWadmm, kidGramWM, kidPass2, kidVadmm };
+enum {
+  kidPass1, kidProcrustes, kidGramFH, kidModeH, kidWadmm, kidGramWM, kidPass2, kidVadmm,
+  kidWfirst, kidMrows, kidFinish
+};
 
 // Records a HIP event pair around one launch when the plan's timing is on.
 template <typename F>
@@ -2404,6 +2757,15 @@ static inline void timed(copa_plan *p, hipStream_t s, int kid, F &&launch) {
 }
 
 
+// Blocks of the persistent W-first launch over `units` subjects (at most wf_blocks) and of the
+// M-row launch over `units` groups of kMRows rows (at most wf_cap: its registers leave room for
+// more wavefronts).
+static int wf_grid(const copa_plan *p, int64_t units, bool mrows = false) {
+  const int64_t per = 4 * (kWave / p->R);
+  const int64_t cap = mrows ? p->mr_blocks : p->wf_blocks;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (units + per - 1) / per));
+}
+
 static FitArgs fit_args(const copa_plan *p) {
   const copa_options &o = p->opt;
   FitArgs fa;
@@ -2411,7 +2773,7 @@ static FitArgs fit_args(const copa_plan *p) {
   fa.vtvpart = gram_slot(p, kSlotVtV);
   fa.nvb = p->n_vblocks;
   fa.wl1part = p->wpart;
-  fa.nwb = p->n_wblocks;
+  fa.nwb = p->opt.order == COPA_ORDER_WHV ? wf_grid(p, p->K) : p->n_wblocks;
   fa.normX2 = p->normX2;
   fa.J = p->J;
   fa.proxV = o.prox_V;
@@ -2490,8 +2852,8 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
     gram_fit<R>(p, p->Q, p->T, p->rows_total, st->W, p->l > 0 ? 1 : 2, kSlotFH, fa, st->H, s);
   });
   timed(p, s, kidModeH, [&] {
-    k_mode_H<R><<<1, 256, 0, s>>>(gram_total(p, kSlotFH), p->small, p->modes, p->scal,
-                                  st->H, st->D_H, o.prox_H, o.lambda_H, o.inner_iters);
+    k_mode_H<R><<<1, 256, 0, s>>>(gram_total(p, kSlotFH), nullptr, p->small, p->modes, p->scal,
+                                  st->H, st->D_H, o.prox_H, o.lambda_H, o.inner_iters, 1);
   });
   timed(p, s, kidWadmm, [&] {
     k_w_admm<R><<<(unsigned)p->n_wblocks, 256, 0, s>>>(K, p->l, p->subj, p->rk, p->T, p->Q, p->M, st->H, st->W,
@@ -2516,6 +2878,55 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   });
 }
 
+// One outer iteration in the block order W -> H -> V: the W block runs right after the
+// Procrustes step with the previous H (F_H and W^T W of the new W come out of the same launch),
+// then the H block, the M rows and Psi, pass 2 and the V block; the FIT of the iteration and the
+// next W system close it.
+template <int R>
+static void iteration_whv_r(copa_plan *p, const copa_state *st, hipStream_t s) {
+  const copa_options &o = p->opt;
+  const int64_t K = p->K;
+  timed(p, s, kidPass1, [&] { RT_SWITCH(p->tiles.rt, launch_pass1_rt, p, st->V, s); });
+  if (K > 0) timed(p, s, kidProcrustes, [&] { launch_procrustes_r<R>(p, st, s); });
+  timed(p, s, kidWfirst, [&] {
+    const int nb = wf_grid(p, K);
+    k_w_first<R><<<(unsigned)nb, 256, 0, s>>>(
+        K, p->l, p->subj, p->rk, p->T, p->Q, st->H, st->W, st->D_W, p->FW, p->modes, o.prox_W,
+        o.lambda_W, o.inner_iters, p->wpart, gram_slot(p, kSlotFH), gram_slot(p, kSlotWtW));
+    k_gram_reduce<R * R><<<dim3((R * R + 3) / 4, 2), 256, 0, s>>>(
+        gram_slot(p, kSlotFH), gram_total(p, kSlotFH), gram_slot(p, kSlotWtW),
+        gram_total(p, kSlotWtW), nb);
+  });
+  timed(p, s, kidModeH, [&] {
+    k_mode_H<R><<<1, 256, 0, s>>>(gram_total(p, kSlotFH), gram_total(p, kSlotWtW), p->small,
+                                  p->modes, p->scal, st->H, st->D_H, o.prox_H, o.lambda_H,
+                                  o.inner_iters, 0);
+  });
+  timed(p, s, kidMrows, [&] {
+    const int nb = wf_grid(p, (p->rows_total + kMRows - 1) / kMRows, true);
+    k_m_rows<R><<<(unsigned)nb, 256, 0, s>>>(p->rows_total, p->l, p->rowsubj, p->Q, st->H,
+                                             st->W, p->M, gram_slot(p, kSlotPsi));
+    k_gram_reduce<R * R><<<dim3((R * R + 3) / 4, 1), 256, 0, s>>>(
+        gram_slot(p, kSlotPsi), gram_total(p, kSlotPsi), nullptr, nullptr, nb);
+  });
+  timed(p, s, kidPass2, [&] {
+    if (p->p2c || p->proj) {
+      RT2_SWITCH(R, p->tiles2.rt, launch_pass2c_rt, p, s);
+    } else {
+      RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s);
+    }
+  });
+  timed(p, s, kidVadmm, [&] {
+    k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(
+        p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, row4(p->tiles.rt),
+        gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->scal, o.prox_V,
+        o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV));
+  });
+  timed(p, s, kidFinish, [&] {
+    k_finish_whv<R><<<1, 256, 0, s>>>(fit_args(p), 1, st->H, p->small, p->modes, p->scal);
+  });
+}
+
 template <int R>
 static void init_grams_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   constexpr int RR = R * R;
@@ -2529,6 +2940,22 @@ static void init_grams_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   gram<R>(p, st->W, st->W, p->K, nullptr, 0, kSlotWtW, st->V, p->J, kSlotVtV, s);
   k_init_small<R><<<1, 256, 0, s>>>(gram_total(p, kSlotWtW), gram_total(p, kSlotVtV), 1,
                                     p->small);
+  if (p->opt.order == COPA_ORDER_WHV) {
+    if (p->wf_blocks == 0) {
+      // persistent grids of as many blocks as stay resident (a fixed count for a given build
+      // and device, so that the fixed-order mode's summation order is fixed too)
+      int b1 = 0, b2 = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_w_first<R>, 256, 0) != hipSuccess)
+        b1 = 1;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_m_rows<R>, 256, 0) != hipSuccess)
+        b2 = 1;
+      const int ncu = std::max(1, p->n_cu);
+      p->wf_blocks = std::max(1, std::min(p->wf_cap, std::max(1, b1) * ncu));
+      p->mr_blocks = std::max(1, std::min(p->wf_cap, std::max(1, b2) * ncu));
+    }
+    // the first W system
+    k_finish_whv<R><<<1, 256, 0, s>>>(fit_args(p), 0, st->H, p->small, p->modes, p->scal);
+  }
 }
 
 // Per-rank entry points of the iteration; each rank is instantiated in one of the
@@ -2545,11 +2972,16 @@ struct RankOps {
 // keep every other translation unit from instantiating the kernels)
 template <int R>
 void RankOps<R>::iteration(copa_plan *p, const copa_state *st, hipStream_t s) {
-  iteration_r<R>(p, st, s);
+  if (p->opt.order == COPA_ORDER_WHV)
+    iteration_whv_r<R>(p, st, s);
+  else
+    iteration_r<R>(p, st, s);
 }
 template <int R>
 void RankOps<R>::fit(copa_plan *p, const copa_state *st, hipStream_t s) {
-  k_fit<R><<<1, 256, 0, s>>>(fit_args(p), st->H, p->small, p->scal);
+  // (the W -> H -> V iteration takes its own FIT at its end)
+  if (p->opt.order != COPA_ORDER_WHV)
+    k_fit<R><<<1, 256, 0, s>>>(fit_args(p), st->H, p->small, p->scal);
 }
 template <int R>
 void RankOps<R>::init_grams(copa_plan *p, const copa_state *st, hipStream_t s) {

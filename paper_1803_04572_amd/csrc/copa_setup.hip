@@ -463,7 +463,11 @@ static copa_status plan_dims(const copa_tensor *X, const copa_options *opt, copa
     p->n_vblocks =
         (int)std::max<int64_t>(1, std::min<int64_t>((p->J + rb - 1) / rb, 4 * std::max(1, p->n_cu)));
   }
-  p->gcap = std::max(p->gmaxnb, p->n_vblocks);
+  // order W -> H -> V: persistent W-first and M-row launches, at most 4 blocks per compute unit
+  p->wf_cap = p->opt.order == COPA_ORDER_WHV ? 4 * std::max(1, p->n_cu) : 0;
+  p->wf_blocks = 0;  // set from the kernels' occupancy at the first fit
+  p->mr_blocks = 0;
+  p->gcap = std::max(std::max(p->gmaxnb, p->n_vblocks), p->wf_cap);
   p->gstride = ((int64_t)p->gcap + 1) * R * R;
   {
     const int64_t per_block = 4 * (kWave / R);
@@ -514,9 +518,10 @@ static copa_status carve_all(copa_plan *p, bool dry) {
   } else {
     COPA_TRY(take(&p->big_list, K));
   }
-  COPA_TRY(take(&p->T, p->rows_total * R));
-  COPA_TRY(take(&p->Q, p->rows_total * R));
-  COPA_TRY(take(&p->M, p->rows_total * R));
+  // (kLMax rows of slack past the end: kernels may load a subject's kLMax row slots whole)
+  COPA_TRY(take(&p->T, (p->rows_total + kLMax) * R));
+  COPA_TRY(take(&p->Q, (p->rows_total + kLMax) * R));
+  COPA_TRY(take(&p->M, (p->rows_total + kLMax) * R));
   COPA_TRY(take(&p->FW, K * R));
   COPA_TRY(take(&p->FV, J * R));
   COPA_TRY(take(&p->Vp, (size_t)p->tiles.nt * J * row4(p->tiles.rt)));
@@ -554,7 +559,7 @@ static copa_status carve_all(copa_plan *p, bool dry) {
   if ((p->p2c || p->proj) && p->opt.deterministic)
     COPA_TRY(take(&p->fvpart, (size_t)p->p2_blocks_cap * J * R));
   COPA_TRY(take(&p->vpart, (size_t)p->n_vblocks * 4));
-  COPA_TRY(take(&p->wpart, (size_t)p->n_wblocks));
+  COPA_TRY(take(&p->wpart, (size_t)std::max(p->n_wblocks, p->wf_cap)));
   COPA_TRY(take(&p->small, 8 * R * R));
   COPA_TRY(take(&p->modes, 3));
   COPA_TRY(take(&p->scal, 1));
@@ -1117,6 +1122,10 @@ static copa_status check_args(const copa_tensor *X, const copa_options *opt, boo
   }
   if (opt->mixed_refine < 0) {
     set_error("mixed_refine must be >= 0");
+    return COPA_EINVAL;
+  }
+  if (opt->order != COPA_ORDER_HWV && opt->order != COPA_ORDER_WHV) {
+    set_error("unknown block order");
     return COPA_EINVAL;
   }
   return COPA_OK;

@@ -2,8 +2,9 @@
 for the GPU path at that size). Calls only the oracle and the seeded input generators.
 
     python tests/golden/make_fullsize_golden.py c4 [--R 20] [--iters 20] [--workers 8] [--K K]
+                                                   [--order WHV]
 
-Output: tests/golden/fullsize_<cfg>_R<R>[_K<K>].json (FIT, objective, sparsity, rho, rank counts
+Output: tests/golden/fullsize_<cfg>_R<R>[_K<K>][_WHV].json (FIT, objective, sparsity, rho, rank counts
 per outer iteration) and .npz (final H, V in FP64). The run starts from the seeded initial point
 (seed 0) with the workload's constraints: H free, W nonnegative, l1 (lambda 0.1) on V, 5 ADMM steps.
 """
@@ -31,6 +32,7 @@ def main():
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--K", type=int, default=None)
+    ap.add_argument("--order", default="HWV", choices=["HWV", "WHV"])
     args = ap.parse_args()
     t0 = time.time()
 
@@ -43,12 +45,14 @@ def main():
     l = cfg["l"]
     progress(f"{args.cfg}: K={coh.K} J={coh.J} S={coh.S} nnz={coh.nnz} R={R} l={l}")
     H0, W0, V0 = synth.init_factors(coh.K, coh.J, R, 0)
-    opt = co.Options(R=R, outer_iters=iters, inner_iters=cfg["inner"])
+    opt = co.Options(R=R, outer_iters=iters, inner_iters=cfg["inner"], order=args.order)
     out = fullsize.copa_fit_sharded(coh, l, H0, W0, V0, opt, workers=args.workers,
                                     progress=progress)
-    tag = f"fullsize_{args.cfg}_R{R}" + (f"_K{coh.K}" if args.K else "")
+    tag = (f"fullsize_{args.cfg}_R{R}" + (f"_K{coh.K}" if args.K else "")
+           + ("_WHV" if args.order == "WHV" else ""))
     meta = dict(cfg=args.cfg, K=coh.K, J=coh.J, S=coh.S, nnz=coh.nnz, R=R, l=l, iters=iters,
-                inner=cfg["inner"], seed_init=0, prox=[opt.prox_H, opt.prox_W, opt.prox_V],
+                inner=cfg["inner"], order=opt.order, seed_init=0,
+                prox=[opt.prox_H, opt.prox_W, opt.prox_V],
                 lam=[opt.lam_H, opt.lam_W, opt.lam_V], rank_rtol=opt.rank_rtol,
                 normX2=out["normX2"], fit=out["fit"], objective=out["objective"],
                 sparsity=out["sparsity"], rho=out["rho"], rank_deficient=out["rank_deficient"],

@@ -46,11 +46,11 @@ def run_gpu(coh, R, l, iters, seed=0, inner=5, prox=(co.PROX_NONE, co.PROX_NONNE
 
 
 def run_oracle(coh, R, l, iters, seed=0, inner=5, prox=(co.PROX_NONE, co.PROX_NONNEG, co.PROX_L1),
-               lam=(0.0, 0.0, 0.1), init=None):
+               lam=(0.0, 0.0, 0.1), init=None, order="HWV"):
     prob = co.build_problem(coh, l)
     H0, W0, V0 = init if init is not None else synth.init_factors(coh.K, coh.J, R, seed)
     opt = co.Options(R=R, outer_iters=iters, inner_iters=inner, prox_H=prox[0], prox_W=prox[1],
-                     prox_V=prox[2], lam_H=lam[0], lam_W=lam[1], lam_V=lam[2])
+                     prox_V=prox[2], lam_H=lam[0], lam_W=lam[1], lam_V=lam[2], order=order)
     return co.copa_fit(prob, H0, W0, V0, opt), prob
 
 
