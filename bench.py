@@ -35,7 +35,9 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "outer AO-ADMM iters/sec + MTTKRP HBM GB/s at fixed fit vs FP64 oracle"
 CSRC = os.path.join(ROOT, "paper_1803_04572_amd", "csrc")
 # rocprofv3 kernel-name stem of each timed kernel
-ROCPROF_NAME = {"pass1": "k_pass1", "procrustes": "k_procrustes", "gram_FH": "k_rows_gram_fit",
+# (the Procrustes step of smoothed plans with R > 16 may be three launches: their sum)
+ROCPROF_NAME = {"pass1": "k_pass1", "procrustes": ("k_procrustes", "k_proc_gram", "k_proc_eigen",
+                                                   "k_proc_q"), "gram_FH": "k_rows_gram_fit",
                 "mode_H": "k_mode_H", "w_admm": "k_w_admm", "gram_WM": "k_rows_gram",
                 "pass2": "k_pass2c", "v_admm": "k_v_admm", "w_first": "k_w_first",
                 "m_rows": "k_m_rows", "finish": "k_finish_whv"}
@@ -61,9 +63,19 @@ def measured_traffic(kernel, workload):
     m = re.search(r"^# source_hash=(\w+)", text, re.M)
     if not m or m.group(1) != kernel_source_hash():
         return None
-    m = re.search(r"^kernel=%s\S* .*bytes_per_launch=(\d+)" % re.escape(ROCPROF_NAME[kernel]),
-                  text, re.M)
-    return int(m.group(1)) if m else None
+    stems = ROCPROF_NAME[kernel]
+    stems = (stems,) if isinstance(stems, str) else stems
+    found = []  # (dispatches, bytes per launch) of every kernel of the step
+    for line in text.splitlines():
+        mm = re.match(r"^kernel=(\S+) .*dispatches=(\d+) .*bytes_per_launch=(\d+)", line)
+        if mm and any(re.match(re.escape(st) + r"([<_]|$)", mm.group(1)) for st in stems):
+            found.append((int(mm.group(2)), int(mm.group(3))))
+    if not found:
+        return None
+    # the kernels the timed iterations ran are those with the most dispatches (the tuner runs
+    # the other candidates a few times)
+    top = max(d for d, _ in found)
+    return sum(b for d, b in found if d == top)
 
 
 def algorithmic_bytes(coh, R, l, compact):

@@ -1485,64 +1485,81 @@ __global__ void __launch_bounds__(256)
 
 // Smoothed subjects with R > 16 in three launches, so that the l x l eigenproblems run without
 // LDS at several wavefronts per SIMD:
-//   k_proc_gram   A_k = T_k S_k H^T (FP32, into the M rows, which the W update writes later in
-//                 the iteration) and G_k = A_k A_k^T (FP64), entry-major per subject
+//   k_proc_gram   A_k = T_k S_k H^T (FP32) and G_k = A_k A_k^T (FP64), entry-major per subject
 //   k_proc_eigen  warm-started Jacobi on G_k (thread per subject), B_k = E diag(f) E^T
-//   k_proc_q      Q_k = B_k A_k
+//   k_proc_q      A_k again from T_k (cheaper than storing it), then Q_k = B_k A_k
 // Four wavefronts per 64 subjects in the first and last, a quarter of the columns each.
-template <int R, int N>
-__global__ void __launch_bounds__(256)
-    k_proc_gram(int64_t K, int l, const float *__restrict__ T, const float *__restrict__ H,
-                const float *__restrict__ W, float *__restrict__ A, double *__restrict__ Gk) {
-  constexpr int NT = N * (N + 1) / 2;
-  constexpr int RQ = (R + 3) / 4;
-  extern __shared__ double smem_d[];
-  double *sG = smem_d;                                    // [NT x 64]
-  float *sH = reinterpret_cast<float *>(sG + NT * 64);    // H
-  float *sX = sH + R * R;                                 // 64 per-subject blocks
+
+// Stages the rows t_i * w_k of the subjects k0 .. k0 + nsub - 1 (l R floats each) into LDS
+// blocks of l R + 1 floats (the padding lets one lane per subject read its block without bank
+// conflicts). When R % 4 == 0 a row is whole float4s, so eight float4 loads per thread are in
+// flight at a time. Whole block.
+template <int R>
+__device__ __forceinline__ void stage_scaled_rows(const float *__restrict__ T,
+                                                  const float *__restrict__ W, int64_t k0,
+                                                  int nsub, int l, float *sX) {
   const int lR = l * R, stride = lR + 1;
-  const float inv_lR = 1.0f / (float)lR;
-  auto at = [&](int f) {
-    int q = (int)((float)f * inv_lR);
-    const int r = f - q * lR;
-    q += (r >= lR) - (r < 0);
-    return f + q;
-  };
-  const int t = threadIdx.x, s = t & 63;
-  // (the wavefront index through readfirstlane: the H entries below are then wavefront-uniform
-  // loads, which go to scalar registers instead of LDS)
-  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int64_t k0 = (int64_t)blockIdx.x * 64;
-  const int nsub = (int)(K - k0 < 64 ? K - k0 : 64);
-  {
-    // the 64 subjects' rows t_i * w_k, staged once
-    const float *src = T + k0 * lR;
-    const float *wsrc = W + k0 * R;
-    const int n = nsub * lR, total = 64 * lR;
-    for (int e0 = 0; e0 < total; e0 += 8 * 256) {
-      float v[8];
+  const int t = threadIdx.x;
+  const bool aligned = (((uintptr_t)T | (uintptr_t)W) & 15) == 0;
+  if (R % 4 == 0 && aligned) {
+    constexpr int R4 = (R + 3) / 4, U = 8;
+    const int lR4 = l * R4;
+    const float4 *src = reinterpret_cast<const float4 *>(T + k0 * lR);
+    const float4 *wsrc = reinterpret_cast<const float4 *>(W + k0 * R);
+    const int n4 = nsub * lR4;
+    for (int e0 = 0; e0 < n4; e0 += U * 256) {
+      float4 v[U], w[U];
+      int sj[U], off[U];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int e = e0 + u * 256 + t;
-        const int sj = (int)((float)e * inv_lR);  // subject of element e (corrected below)
-        const int rem = e - sj * lR;
-        const int sjc = sj + (rem >= lR) - (rem < 0);
-        v[u] = e < n ? src[e] * wsrc[sjc * R + (e - sjc * lR) % R] : 0.0f;
+        const int ec = e < n4 ? e : 0;
+        sj[u] = ec / lR4;
+        off[u] = ec - sj[u] * lR4;
+        v[u] = src[ec];
+        w[u] = wsrc[sj[u] * R4 + off[u] % R4];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256 + t;
-        if (e < total) sX[at(e)] = v[u];
+      for (int u = 0; u < U; ++u) {
+        if (e0 + u * 256 + t < n4) {
+          float *d = sX + sj[u] * stride + off[u] * 4;
+          d[0] = v[u].x * w[u].x;
+          d[1] = v[u].y * w[u].y;
+          d[2] = v[u].z * w[u].z;
+          d[3] = v[u].w * w[u].w;
+        }
       }
     }
+  } else {
+    const float *src = T + k0 * lR;
+    const float *wsrc = W + k0 * R;
+    const int n = nsub * lR;
+    for (int e0 = 0; e0 < n; e0 += 8 * 256) {
+      float v[8];
+      int sj[8], off[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + t;
+        const int ec = e < n ? e : 0;
+        sj[u] = ec / lR;
+        off[u] = ec - sj[u] * lR;
+        v[u] = src[ec] * wsrc[sj[u] * R + off[u] % R];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e0 + u * 256 + t < n) sX[sj[u] * stride + off[u]] = v[u];
+    }
   }
-  float *x = sX + s * stride;
-  const int c_lo = w * RQ;
-  __syncthreads();
-  // a_i = (t_i * w) H^T on this wavefront's columns, every row of the subject: four entries of
-  // each H column at a time (scalar registers), applied to every row
+}
+
+// a_i = (t_i * w) H^T on the columns c_lo .. c_lo + RQ - 1, every row i < l of the lane's subject
+// (x: its staged block): four entries of each H column at a time (wavefront-uniform, so scalar
+// registers), applied to every row. c_lo must be wavefront-uniform.
+template <int R, int N>
+__device__ __forceinline__ void a_columns(const float *x, const float *__restrict__ H, int c_lo,
+                                          int l, float (&a)[N][(R + 3) / 4]) {
+  constexpr int RQ = (R + 3) / 4;
   constexpr bool kFullCols = R % 4 == 0;  // (then every wavefront's RQ columns exist)
-  float a[N][RQ];
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
@@ -1571,6 +1588,27 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
+}
+
+template <int R, int N>
+__global__ void __launch_bounds__(256)
+    k_proc_gram(int64_t K, int l, const float *__restrict__ T, const float *__restrict__ H,
+                const float *__restrict__ W, double *__restrict__ Gk) {
+  constexpr int NT = N * (N + 1) / 2;
+  constexpr int RQ = (R + 3) / 4;
+  extern __shared__ double smem_d[];
+  double *sG = smem_d;                                    // [NT x 64]
+  float *sX = reinterpret_cast<float *>(sG + NT * 64);    // 64 per-subject blocks
+  const int lR = l * R, stride = lR + 1;
+  const int t = threadIdx.x, s = t & 63;
+  // (the wavefront index through readfirstlane: the H entries are then wavefront-uniform loads)
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int64_t k0 = (int64_t)blockIdx.x * 64;
+  const int nsub = (int)(K - k0 < 64 ? K - k0 : 64);
+  stage_scaled_rows<R>(T, W, k0, nsub, l, sX);
+  __syncthreads();
+  float a[N][RQ];
+  a_columns<R, N>(sX + s * stride, H, w * RQ, l, a);
   // partial Gram in FP64 over these columns, added in wavefront order
   {
     double Gp[NT];
@@ -1592,34 +1630,9 @@ __global__ void __launch_bounds__(256)
       __syncthreads();
     }
   }
-  // A rows into the block (every wavefront has read Y), then both out coalesced
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-    if (i < l)
-#pragma unroll
-      for (int cc = 0; cc < RQ; ++cc)
-        if (c_lo + cc < R) x[i * R + c_lo + cc] = a[i][cc];
   for (int e = t; e < NT * 64; e += 256) {
     const int ent = e >> 6, sj = e & 63;
     if (sj < nsub) Gk[(int64_t)ent * K + k0 + sj] = sG[e];
-  }
-  __syncthreads();
-  {
-    float *dst = A + k0 * lR;
-    const int n = nsub * lR;
-    for (int e0 = 0; e0 < n; e0 += 8 * 256) {
-      float v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256 + t;
-        v[u] = e < n ? sX[at(e)] : 0.0f;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256 + t;
-        if (e < n) dst[e] = v[u];
-      }
-    }
   }
 }
 
@@ -1699,8 +1712,8 @@ __global__ void __launch_bounds__(256)
 
 template <int R, int N>
 __global__ void __launch_bounds__(256)
-    k_proc_q(int64_t K, int l, const float *__restrict__ A, const double *__restrict__ Bk,
-             float *__restrict__ Q) {
+    k_proc_q(int64_t K, int l, const float *__restrict__ T, const float *__restrict__ H,
+             const float *__restrict__ W, const double *__restrict__ Bk, float *__restrict__ Q) {
   constexpr int NT = N * (N + 1) / 2;
   constexpr int RQ = (R + 3) / 4;
   extern __shared__ double smem_d[];
@@ -1713,46 +1726,32 @@ __global__ void __launch_bounds__(256)
     q += (r >= lR) - (r < 0);
     return f + q;
   };
-  const int t = threadIdx.x, s = t & 63, w = t >> 6;
+  const int t = threadIdx.x, s = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int64_t k0 = (int64_t)blockIdx.x * 64;
   const int nsub = (int)(K - k0 < 64 ? K - k0 : 64);
-  {
-    const float *src = A + k0 * lR;
-    const int n = nsub * lR, total = 64 * lR;
-    for (int e0 = 0; e0 < total; e0 += 8 * 256) {
-      float v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256 + t;
-        v[u] = e < n ? src[e] : 0.0f;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256 + t;
-        if (e < total) sX[at(e)] = v[u];
-      }
-    }
-  }
   const int64_t k = k0 + (s < nsub ? s : 0);
   double B[NT];
 #pragma unroll
   for (int e = 0; e < NT; ++e) B[e] = Bk[(int64_t)e * K + k];
+  stage_scaled_rows<R>(T, W, k0, nsub, l, sX);
   __syncthreads();
   float *x = sX + s * stride;
   const int c_lo = w * RQ;
-#pragma unroll 1
+  float a[N][RQ];
+  a_columns<R, N>(x, H, c_lo, l, a);
+  __syncthreads();  // (every wavefront has read the rows; the block now takes Q in their place)
+#pragma unroll
   for (int cc = 0; cc < RQ; ++cc) {
     const int c = c_lo + cc;
-    if (c < R) {
-      double v[N];
-#pragma unroll
-      for (int i = 0; i < N; ++i) v[i] = i < l ? (double)x[i * R + c] : 0.0;
+    if (R % 4 == 0 || c < R) {
 #pragma unroll
       for (int i = 0; i < N; ++i)
         if (i < l) {
           double acc = 0.0;
 #pragma unroll
-          for (int j = 0; j < N; ++j) acc = fma(B[triN<N>(i, j)], v[j], acc);
+          for (int j = 0; j < N; ++j)
+            if (j < l) acc = fma(B[triN<N>(i, j)], (double)a[j][cc], acc);
           x[i * R + c] = (float)acc;
         }
     }
@@ -1782,12 +1781,12 @@ inline void launch_proc_split(copa_plan *p, const copa_state *st, hipStream_t s)
   constexpr int NT = N * (N + 1) / 2;
   const int64_t K = p->K;
   const unsigned nb = (unsigned)((K + 63) / 64);
-  const size_t lds1 = (size_t)NT * 64 * 8 + (size_t)R * R * 4 + (size_t)64 * (p->l * R + 1) * 4;
-  k_proc_gram<R, N><<<nb, 256, lds1, s>>>(K, p->l, p->T, st->H, st->W, p->M, p->pgb);
+  const size_t lds1 = (size_t)NT * 64 * 8 + (size_t)64 * (p->l * R + 1) * 4;
+  k_proc_gram<R, N><<<nb, 256, lds1, s>>>(K, p->l, p->T, st->H, st->W, p->pgb);
   k_proc_eigen<R, N><<<(unsigned)((K + 255) / 256), 256, 0, s>>>(K, p->l, p->rk, p->pgb, p->Ew,
                                                                   p->opt.rank_rtol, p->scal);
   const size_t lds3 = (size_t)64 * (p->l * R + 1) * 4;
-  k_proc_q<R, N><<<nb, 256, lds3, s>>>(K, p->l, p->M, p->pgb, p->Q);
+  k_proc_q<R, N><<<nb, 256, lds3, s>>>(K, p->l, p->T, st->H, st->W, p->pgb, p->Q);
 }
 
 inline size_t procrustes_m_lds(int R, int l, int N) {
