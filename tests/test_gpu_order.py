@@ -137,3 +137,29 @@ def test_whv_constraint_variants():
     g = run_gpu(coh, R, l, iters, prox=prox, lam=lam, init=init, order="WHV")
     o, prob = run_oracle(coh, R, l, iters, prox=prox, lam=lam, init=init, order="WHV")
     check_fit("whv constraints", coh, g, o, prob, R)
+
+
+@pytest.mark.parametrize("cfg_name,R", [("c4", 20), ("c3", 40)])
+def test_whv_every_procrustes_variant_on_trajectory(cfg_name, R, tmp_path, monkeypatch):
+    """Each Procrustes kernel for smoothed R > 16, forced through the tuning cache file, in the
+    W -> H -> V order, follows the oracle's 20-iteration trajectory in this order."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("COPA_TUNE_CACHE", str(cache))
+    with open(os.path.join(GOLDEN, f"fullsize_{cfg_name}_R{R}_K3000_WHV.json")) as fh:
+        ref = json.load(fh)
+    coh, cfg = synth.make_config(cfg_name, K=3000)
+    first = run_gpu(coh, R, cfg["l"], 1, adjoint=False, order="WHV")
+    key, shapes = cache.read_text().strip().splitlines()[0].split(":")
+    a, _, c, d = shapes.split()
+    for v in (0, 1, 2):
+        cache.write_text(f"{key}: {a} {v} {c} {d}\n")
+        g = run_gpu(coh, R, cfg["l"], ref["iters"], adjoint=False, order="WHV")
+        assert g["plan"].query("tuned") == 2 and g["plan"].query("procrustes_variant") == v
+        fit = np.abs(np.array(g["rep"]["fit_history"]) - np.array(ref["fit"])) / np.abs(ref["fit"])
+        print(f"whv procrustes variant {v} {cfg_name} R={R}: fit_rel={fit[-1]:.2e} "
+              f"hist_max={fit.max():.2e} rank_def={g['rep']['rank_deficient']}/"
+              f"{ref['rank_deficient'][-1]}", flush=True)
+        assert fit.max() <= FIT_RTOL
+        assert abs(g["rep"]["rank_deficient"] - ref["rank_deficient"][-1]) <= \
+            ref["ambiguous_band"][-1]
+    del first
