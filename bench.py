@@ -37,11 +37,10 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "outer AO-ADMM iters/sec + MTTKRP HBM GB/s at fixed fit vs FP64 oracle"
 CSRC = os.path.join(ROOT, "paper_1803_04572_amd", "csrc")
 # rocprofv3 kernel-name stem of each timed kernel
-# (the Procrustes step of smoothed plans with R > 16 may be three launches: their sum)
-ROCPROF_NAME = {"pass1": ("k_pass1", "k_pass1p"),
-                "procrustes": ("k_procrustes", "k_proc_gram", "k_proc_eigen", "k_proc_q"),
+ROCPROF_NAME = {"pass1": ("k_pass1", "k_pass1p"), "procrustes": "k_procrustes",
+                "proc_gram": "k_proc_gram", "proc_eigen": "k_proc_eigen", "proc_q": "k_proc_q",
                 "gram_FH": "k_rows_gram_fit",
-                "mode_H": "k_mode_H", "w_admm": "k_w_admm", "gram_WM": "k_rows_gram",
+                "mode_H": "k_mode_H", "w_admm": "k_w_admm", "gram_WM": "k_rows_gram<",
                 "pass2": ("k_pass2", "k_pass2c", "k_pass2p"), "v_admm": "k_v_admm", "w_first": "k_w_first",
                 "m_rows": "k_m_rows", "finish": "k_finish_whv"}
 
@@ -71,7 +70,9 @@ def measured_traffic(kernel, workload):
     found = []  # (dispatches, bytes per launch) of every kernel of the step
     for line in text.splitlines():
         mm = re.match(r"^kernel=(\S+) .*dispatches=(\d+) .*bytes_per_launch=(\d+)", line)
-        if mm and any(re.match(re.escape(st) + r"([<_]|$)", mm.group(1)) for st in stems):
+        # (a stem ending in "<" names one template exactly; otherwise its variants count too)
+        if mm and any(re.match(re.escape(st) + ("" if st.endswith("<") else r"([<_]|$)"),
+                               mm.group(1)) for st in stems):
             found.append((int(mm.group(2)), int(mm.group(3))))
     if not found:
         return None
@@ -91,15 +92,23 @@ def algorithmic_bytes(coh, R, l, compact):
         per-subject l x l transform (4 l^2 B per subject); the library streams stored FP32 basis
         rows instead, which moves more than this;
       * the per-subject row spaces T, Q, M (rows = K l smoothed, S plain; R floats per row),
-        W and V, read and written as each kernel needs them."""
+        W and V, read and written as each kernel needs them;
+      * the three-launch Procrustes step: its launches' own inputs and outputs (the FP64 l x l
+        Gram and B_k, l (l + 1) / 2 doubles per subject each), not the warm start."""
     K, J, S, nnz = coh.K, coh.J, coh.S, coh.nnz
     rows = K * l if l > 0 else S
+    nt = l * (l + 1) // 2  # FP64 entries of a subject's l x l Gram (three-launch Procrustes)
     basis = (S * 4 + K * l * l * 4) if l > 0 else 0
     x1 = nnz * (4 if compact else 8) + (S + 1) * 4 + (K + 1) * 4 + basis
     x2 = nnz * 8 + S * 4 + basis
     return {
         "pass1": x1 + J * R * 4 + rows * R * 4,
         "procrustes": rows * R * 4 * 2 + K * R * 4 + R * R * 4,
+        # the three launches of the Procrustes step for smoothed R > 16: T and W in, the FP64 Gram
+        # out; the Gram in, B_k out; T, W and B_k in, Q out
+        "proc_gram": rows * R * 4 + K * R * 4 + K * nt * 8,
+        "proc_eigen": K * nt * 8 * 2,
+        "proc_q": rows * R * 4 * 2 + K * R * 4 + K * nt * 8,
         "gram_FH": rows * R * 4 * 2 + K * R * 4,
         "mode_H": R * R * 8 * 3,
         "w_admm": rows * R * 4 * 3 + K * R * 4 * 5,

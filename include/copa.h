@@ -257,7 +257,7 @@ copa_status copa_stationarity(copa_plan *plan, const float *H, const float *V, c
  * copa_read_timing writes, per kernel id in [0, COPA_NUM_KERNELS), the summed milliseconds
  * (`ms`, host) and launch counts (`launches`, host) since the previous read, then resets them.
  * copa_kernel_name(id) names the kernel.                                                     */
-#define COPA_NUM_KERNELS 11
+#define COPA_NUM_KERNELS 14
 copa_status copa_set_timing(copa_plan *plan, int32_t enable);
 copa_status copa_read_timing(copa_plan *plan, double *ms, int64_t *launches);
 const char *copa_kernel_name(int32_t id);

@@ -35,7 +35,7 @@ SYMBOLS = ("copa_workspace_bytes", "copa_plan_create", "copa_fit", "copa_mttkrp_
            "copa_loss_grad", "copa_plan_destroy", "copa_rank_supported", "copa_status_string",
            "copa_last_error", "copa_set_timing", "copa_read_timing", "copa_kernel_name",
            "copa_plan_query", "copa_set_graph", "copa_stationarity", "copa_loss_grad_static")
-NUM_KERNELS = 11
+NUM_KERNELS = 14
 
 
 class CopaTensor(ctypes.Structure):

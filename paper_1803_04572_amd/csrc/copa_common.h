@@ -23,7 +23,7 @@ constexpr int kGramSlots = 6;      // F_H, W^TW, Psi, V^TV partials; adjoint G a
 __host__ __device__ constexpr int64_t gram_total_offset(int maxnb) { return (int64_t)maxnb; }
 constexpr int kChunkRows = 512;    // visit rows per chunk of the feature-sorted pass-2 layout
 constexpr int kMaxR = 64;
-constexpr int kNumKernels = 11;    // kernels of one outer iteration (see kernel_names)
+constexpr int kNumKernels = 14;    // kernels of one outer iteration (see kernel_names)
 constexpr int kTimingChunk = 64;   // iterations between event harvests when timing
 
 void set_error(const std::string &msg);

@@ -75,7 +75,7 @@ Tiles choose_tiles2(int R, int64_t J, int lds_limit) {
 
 const char *const kernel_names[kNumKernels] = {
     "pass1", "procrustes", "gram_FH", "mode_H", "w_admm", "gram_WM", "pass2", "v_admm",
-    "w_first", "m_rows", "finish"};
+    "w_first", "m_rows", "finish", "proc_gram", "proc_eigen", "proc_q"};
 
 copa_status harvest_timing(copa_plan *p) {
   for (size_t e = 0; e < p->ev_kid.size(); ++e) {

@@ -1776,18 +1776,28 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <int R, int N>
-inline void launch_proc_split(copa_plan *p, const copa_state *st, hipStream_t s) {
+// The three launches; `each` wraps every launch (per-kernel timing in the iteration, a plain call
+// in the tuner).
+template <int R, int N, typename F>
+inline void launch_proc_split(copa_plan *p, const copa_state *st, hipStream_t s, F &&each) {
   constexpr int NT = N * (N + 1) / 2;
   const int64_t K = p->K;
   const unsigned nb = (unsigned)((K + 63) / 64);
   const size_t lds1 = (size_t)NT * 64 * 8 + (size_t)64 * (p->l * R + 1) * 4;
-  k_proc_gram<R, N><<<nb, 256, lds1, s>>>(K, p->l, p->T, st->H, st->W, p->pgb);
-  k_proc_eigen<R, N><<<(unsigned)((K + 255) / 256), 256, 0, s>>>(K, p->l, p->rk, p->pgb, p->Ew,
-                                                                  p->opt.rank_rtol, p->scal);
+  each(0, [&] { k_proc_gram<R, N><<<nb, 256, lds1, s>>>(K, p->l, p->T, st->H, st->W, p->pgb); });
+  each(1, [&] {
+    k_proc_eigen<R, N><<<(unsigned)((K + 255) / 256), 256, 0, s>>>(K, p->l, p->rk, p->pgb, p->Ew,
+                                                                    p->opt.rank_rtol, p->scal);
+  });
   const size_t lds3 = (size_t)64 * (p->l * R + 1) * 4;
-  k_proc_q<R, N><<<nb, 256, lds3, s>>>(K, p->l, p->T, st->H, st->W, p->pgb, p->Q);
+  each(2, [&] {
+    k_proc_q<R, N><<<nb, 256, lds3, s>>>(K, p->l, p->T, st->H, st->W, p->pgb, p->Q);
+  });
 }
+struct PlainLaunch {
+  template <typename L>
+  void operator()(int, L &&launch) const { launch(); }
+};
 
 inline size_t procrustes_m_lds(int R, int l, int N) {
   return (size_t)R * R * 8 + (size_t)N * (N + 1) / 2 * 64 * 8 + (size_t)R * R * 4 +
@@ -2738,7 +2748,7 @@ static void launch_pass2_rt(copa_plan *p, hipStream_t s) {
 
 enum {
   kidPass1, kidProcrustes, kidGramFH, kidModeH, kidWadmm, kidGramWM, kidPass2, kidVadmm,
-  kidWfirst, kidMrows, kidFinish
+  kidWfirst, kidMrows, kidFinish, kidProcGram, kidProcEigen, kidProcQ
 };
 
 // Records a HIP event pair around one launch when the plan's timing is on.
@@ -2802,9 +2812,9 @@ static void launch_procrustes_r(copa_plan *p, const copa_state *st, hipStream_t 
     }
     if (p->l > 0 && p->proc_variant == 2) {
       if (p->l == 7)
-        launch_proc_split<R, 7>(p, st, s);
+        launch_proc_split<R, 7>(p, st, s, PlainLaunch{});
       else
-        launch_proc_split<R, kLMax>(p, st, s);
+        launch_proc_split<R, kLMax>(p, st, s, PlainLaunch{});
       return;
     }
     if (p->l > 0) {
@@ -2839,12 +2849,31 @@ static void launch_procrustes_r(copa_plan *p, const copa_state *st, hipStream_t 
 
 // One outer iteration; pass 1 advances the device iteration index and the later kernels read it,
 // so the same launches serve every iteration (and one captured graph replays them).
+// The Procrustes step of an iteration, timed per launch (the three-launch form as three kernels).
+template <int R>
+static void procrustes_step(copa_plan *p, const copa_state *st, hipStream_t s) {
+  if (p->K == 0) return;
+  if constexpr (R > 16) {
+    if (p->l > 0 && p->proc_variant == 2) {
+      auto each = [&](int part, auto &&launch) {
+        timed(p, s, part == 0 ? kidProcGram : part == 1 ? kidProcEigen : kidProcQ, launch);
+      };
+      if (p->l == 7)
+        launch_proc_split<R, 7>(p, st, s, each);
+      else
+        launch_proc_split<R, kLMax>(p, st, s, each);
+      return;
+    }
+  }
+  timed(p, s, kidProcrustes, [&] { launch_procrustes_r<R>(p, st, s); });
+}
+
 template <int R>
 static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   const copa_options &o = p->opt;
   const int64_t K = p->K;
   timed(p, s, kidPass1, [&] { RT_SWITCH(p->tiles.rt, launch_pass1_rt, p, st->V, s); });
-  if (K > 0) timed(p, s, kidProcrustes, [&] { launch_procrustes_r<R>(p, st, s); });
+  procrustes_step<R>(p, st, s);
   timed(p, s, kidGramFH, [&] {
     // one more block of the same launch takes the FIT of the previous outer iteration
     const FitArgs fa = fit_args(p);
@@ -2886,7 +2915,7 @@ static void iteration_whv_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   const copa_options &o = p->opt;
   const int64_t K = p->K;
   timed(p, s, kidPass1, [&] { RT_SWITCH(p->tiles.rt, launch_pass1_rt, p, st->V, s); });
-  if (K > 0) timed(p, s, kidProcrustes, [&] { launch_procrustes_r<R>(p, st, s); });
+  procrustes_step<R>(p, st, s);
   timed(p, s, kidWfirst, [&] {
     const int nb = wf_grid(p, K);
     k_w_first<R><<<(unsigned)nb, 256, 0, s>>>(
