@@ -32,16 +32,17 @@ def _same(a, b):
     return all(np.array_equal(a[k], b[k]) for k in a)
 
 
-def test_caller_workspace_equals_library_workspace():
+@pytest.mark.parametrize("order", ["HWV", "WHV"])
+def test_caller_workspace_equals_library_workspace(order):
     """A plan laid out in a caller-provided workspace gives bitwise the same fit (fixed-order
     mode) as one whose workspace the library allocated."""
     from paper_1803_04572_amd import copa
     coh, _ = synth.make_config("c2", K=700)
     init = synth.init_factors(coh.K, coh.J, 10, 0)
-    a = copa.Plan.from_cohort(coh, R=10, l=7, deterministic=True)
-    b = copa.Plan.from_cohort(coh, R=10, l=7, deterministic=True, workspace="caller")
+    a = copa.Plan.from_cohort(coh, R=10, l=7, deterministic=True, order=order)
+    b = copa.Plan.from_cohort(coh, R=10, l=7, deterministic=True, workspace="caller", order=order)
     assert b._ws.numel() == copa.Plan.workspace_bytes(coh.K, coh.J, coh.S, coh.nnz, 7, 10,
-                                                      deterministic=True)
+                                                      deterministic=True, order=order)
     ra, sa, qa = _fit(a, init, 6)
     rb, sb, qb = _fit(b, init, 6)
     assert ra["fit_history"] == rb["fit_history"]
@@ -163,17 +164,18 @@ def test_adjoint_needs_its_workspace():
     torch.cuda.synchronize()
 
 
-def test_stop_checks_do_not_change_the_trajectory():
+@pytest.mark.parametrize("order", ["HWV", "WHV"])
+def test_stop_checks_do_not_change_the_trajectory(order):
     """Fits that pause every few iterations for the stationarity check follow the plain fit's
     trajectory bit for bit (fixed-order mode)."""
     from paper_1803_04572_amd import copa
     coh, _ = synth.make_config("c5", K=200)
     R = 10
     init = synth.init_factors(coh.K, coh.J, R, 0)
-    plain = copa.Plan.from_cohort(coh, R=R, l=0, deterministic=True)
+    plain = copa.Plan.from_cohort(coh, R=R, l=0, deterministic=True, order=order)
     ra, sa, _ = _fit(plain, init, 12)
     stop = copa.Plan.from_cohort(coh, R=R, l=0, deterministic=True, stop_tol=1e-30,
-                                 check_every=4)
+                                 check_every=4, order=order)
     rb, sb, _ = _fit(stop, init, 12)
     assert rb["iters_done"] == 12
     assert rb["fit_history"] == ra["fit_history"]

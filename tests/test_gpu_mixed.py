@@ -61,3 +61,18 @@ def test_mixed_precision_needs_projected_pairs():
     with pytest.raises(copa.CopaError) as e:
         copa.Plan.from_cohort(coh, R=10, l=7, precision=copa.PREC_MIXED)
     assert e.value.status == copa.EUNSUPPORTED
+
+
+def test_mixed_precision_whv_trajectory():
+    """Mixed precision in the block order W -> H -> V (both record precisions' iteration graphs
+    run that order) against the oracle's trajectory in that order."""
+    from paper_1803_04572_amd import copa
+    tag = "fullsize_c4_R20_K3000_WHV"
+    with open(os.path.join(GOLDEN, tag + ".json")) as fh:
+        ref = json.load(fh)
+    coh, cfg = synth.make_config("c4", K=3000)
+    g = run_gpu(coh, 20, cfg["l"], ref["iters"], precision=copa.PREC_MIXED, mixed_refine=1,
+                adjoint=False, order="WHV")
+    fit = np.abs(np.array(g["rep"]["fit_history"]) - np.array(ref["fit"])) / np.abs(ref["fit"])
+    print(f"mixed-precision {tag}: fit_rel={fit[-1]:.3e} hist_max={fit.max():.3e}", flush=True)
+    assert fit.max() <= MIXED_FIT_RTOL

@@ -136,10 +136,12 @@ def test_basis_sizes_parity(R, l):
     check_fit(f"basis l={l} R={R}", coh, g, o, prob, R)
 
 
+@pytest.mark.parametrize("order", ["HWV", "WHV"])
 @pytest.mark.parametrize("l", [7, 0])
-def test_subjects_without_visits(l):
+def test_subjects_without_visits(l, order):
     """Subjects with no visit rows (I_k = 0) among the others: they contribute nothing to any
-    MTTKRP and their W rows follow the ADMM steps with F_W = 0, as in the oracle."""
+    MTTKRP and their W rows follow the ADMM steps with F_W = 0, as in the oracle (either block
+    order)."""
     base, _ = synth.make_config("c2", K=200)
     ik = np.diff(base.subj_ptr)
     ik2 = np.insert(ik, [0, 5, 5, 77, 200], 0)  # empty subjects first, in a run, inside, last
@@ -147,9 +149,9 @@ def test_subjects_without_visits(l):
     coh = synth.Cohort(K=ik2.size, J=base.J, subj_ptr=subj_ptr, row_ptr=base.row_ptr,
                        col=base.col, val=base.val, days=base.days)
     R = 10
-    g = run_gpu(coh, R, l, 8)
-    o, prob = run_oracle(coh, R, l, 8)
-    check_fit(f"empty subjects l={l}", coh, g, o, prob, R)
+    g = run_gpu(coh, R, l, 8, order=order)
+    o, prob = run_oracle(coh, R, l, 8, order=order)
+    check_fit(f"empty subjects l={l} order={order}", coh, g, o, prob, R)
     np.testing.assert_allclose(g["W"][ik2 == 0], o.W[ik2 == 0], rtol=1e-4, atol=1e-6)
 
 
