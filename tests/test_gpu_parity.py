@@ -263,3 +263,16 @@ def test_invalid_csr_is_rejected_on_device():
                   torch.as_tensor(bad).cuda(), torch.as_tensor(coh.val).cuda(),
                   torch.as_tensor(coh.days).cuda(), coh.J, 7, 5)
     assert e.value.status == copa.EINVAL and "outside" in str(e.value)
+
+
+@pytest.mark.parametrize("R,l,order", [(1, 7, "HWV"), (3, 0, "HWV"), (12, 7, "HWV"),
+                                       (16, 7, "HWV"), (16, 0, "HWV"), (24, 7, "HWV"),
+                                       (32, 7, "HWV"), (32, 0, "HWV"), (3, 7, "WHV"),
+                                       (16, 7, "WHV"), (32, 7, "WHV"), (6, 0, "WHV")])
+def test_rank_coverage(R, l, order):
+    """Ranks the library builds beyond the workloads' (R = 1 .. 32, one subject per lane up to a
+    wavefront per subject), smoothed and plain, in both block orders, against the oracle."""
+    coh, _ = synth.make_config("c2", K=300)
+    g = run_gpu(coh, R, l, 6, order=order)
+    o, prob = run_oracle(coh, R, l, 6, order=order)
+    check_fit(f"rank R={R} l={l} order={order}", coh, g, o, prob, R)
