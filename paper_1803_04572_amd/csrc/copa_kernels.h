@@ -551,7 +551,27 @@ __global__ void __launch_bounds__(512)
     float pre[PF][PW];
 #pragma unroll
     for (int u = 0; u < PF; ++u) fetch_rec<BF, PW>(recs, feat_hi, a + u < b ? a + u : 0, pre[u]);
-    {
+    if (RT % 4 == 0 && RT == R && (((uintptr_t)M) & 15) == 0) {
+      // the chunk's M block is nsub l whole rows, contiguous: float4 loads, up to eight per
+      // thread in flight at once (rows of RT floats are RT / 4 float4s, RTP == RT)
+      constexpr int R4 = RT / 4, U = 8;
+      const int n4 = nsub * l * R4;
+      const float4 *Mb4 = reinterpret_cast<const float4 *>(M + (int64_t)k0 * l * R);
+      float4 *sM4 = reinterpret_cast<float4 *>(sM);
+      for (int e0 = 0; e0 < n4; e0 += U * nt) {
+        float4 mv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = e0 + u * nt + t;
+          mv[u] = Mb4[e < n4 ? e : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = e0 + u * nt + t;
+          if (e < n4) sM4[e] = mv[u];
+        }
+      }
+    } else {
       // the chunk's M block (nsub l rows of RT floats), 4 loads in flight per thread
       const int nm = nsub * l * RT;
       const float *Mb = M + (int64_t)k0 * l * R + c0;
