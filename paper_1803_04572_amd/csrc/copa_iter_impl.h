@@ -2353,23 +2353,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R <= 2
         xt[i][c] = tv[i];
       }
       __builtin_amdgcn_wave_barrier();
-      double F = 0.0;
       float pc[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) pc[r] = 0.0f;
-      // the rank-m rows two at a time (rows staged in LDS keep the registers for the sums)
-#pragma unroll 2
+      // P_k(:, c) from the rank-m rows (staged in LDS, which keeps the registers for the sums);
+      // then F_W(k, c) = sum_r H(r, c) P_k(r, c)
+#pragma unroll 1
       for (int i = 0; i < m; ++i) {
         const float ti = xt[i][c];
-        float p = 0.0f;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const float x = xg[i][r];
-          p = fmaf(x, hcol[r], p);
-          pc[r] = fmaf(x, ti, pc[r]);
-        }
-        F += (double)p * (double)ti;
+        for (int r = 0; r < R; ++r) pc[r] = fmaf(xg[i][r], ti, pc[r]);
       }
+      double F = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) F += (double)hcol[r] * (double)pc[r];
       w_first_row<R>(k, act, F, pc, Zb, D, sGi, rho, kind, lam, iters, xrow, c, W, DW, FW, fh,
                      wtw, l1);
 #pragma unroll
@@ -2388,7 +2385,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R <= 2
       const float Zb = W[kc * R + c], D = DW[kc * R + c];
       const int64_t base = subj[kc];
       const int m = act ? subj[kc + 1] - subj[kc] : 0;
-      double F = 0.0;
       float pc[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) pc[r] = 0.0f;
@@ -2397,15 +2393,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R <= 2
         __builtin_amdgcn_wave_barrier();
         xg[0][c] = qv;
         __builtin_amdgcn_wave_barrier();
-        float p = 0.0f;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const float x = xg[0][r];
-          p = fmaf(x, hcol[r], p);
-          pc[r] = fmaf(x, ti, pc[r]);
-        }
-        F += (double)p * (double)ti;
+        for (int r = 0; r < R; ++r) pc[r] = fmaf(xg[0][r], ti, pc[r]);
       }
+      double F = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) F += (double)hcol[r] * (double)pc[r];
       w_first_row<R>(k, act, F, pc, Zb, D, sGi, rho, kind, lam, iters, xrow, c, W, DW, FW, fh,
                      wtw, l1);
     }
