@@ -1553,8 +1553,9 @@ __device__ __forceinline__ void stage_scaled_rows(const float *__restrict__ T,
 }
 
 // a_i = (t_i * w) H^T on the columns c_lo .. c_lo + RQ - 1, every row i < l of the lane's subject
-// (x: its staged block): four entries of each H column at a time (wavefront-uniform, so scalar
-// registers), applied to every row. c_lo must be wavefront-uniform.
+// (x: its staged block): four entries of each H column at a time, applied to every row. With H in
+// global memory and c_lo wavefront-uniform the H entries load into scalar registers; with H in
+// LDS c_lo may differ between lanes.
 template <int R, int N>
 __device__ __forceinline__ void a_columns(const float *x, const float *__restrict__ H, int c_lo,
                                           int l, float (&a)[N][(R + 3) / 4]) {
@@ -1590,6 +1591,24 @@ __device__ __forceinline__ void a_columns(const float *x, const float *__restric
   }
 }
 
+// v summed over the lane's quad (lanes 4j .. 4j + 3) by two DPP exchanges; every lane of the quad
+// gets the same (v0 + v1) + (v2 + v3), bit for bit.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffu), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo));
+}
+__device__ __forceinline__ double quad_sum(double v) {
+  v = v + dpp_d<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+  return v + dpp_d<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+}
+
+// Four lanes per subject (64 per block), lane q of a quad a quarter of the columns: A_k's columns
+// from the staged rows t_i * w_k with H from LDS, the partial FP64 Gram over them, the quad sum,
+// and each lane stores a quarter of the subject's Gram entries (entry-major).
 template <int R, int N>
 __global__ void __launch_bounds__(256)
     k_proc_gram(int64_t K, int l, const float *__restrict__ T, const float *__restrict__ H,
@@ -1597,42 +1616,32 @@ __global__ void __launch_bounds__(256)
   constexpr int NT = N * (N + 1) / 2;
   constexpr int RQ = (R + 3) / 4;
   extern __shared__ double smem_d[];
-  double *sG = smem_d;                                    // [NT x 64]
-  float *sX = reinterpret_cast<float *>(sG + NT * 64);    // 64 per-subject blocks
+  float *sH = reinterpret_cast<float *>(smem_d);  // H (R x R)
+  float *sX = sH + ((R * R + 3) & ~3);            // 64 per-subject blocks of l R + 1 floats
   const int lR = l * R, stride = lR + 1;
-  const int t = threadIdx.x, s = t & 63;
-  // (the wavefront index through readfirstlane: the H entries are then wavefront-uniform loads)
-  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int t = threadIdx.x, s = t >> 2, q = t & 3;
   const int64_t k0 = (int64_t)blockIdx.x * 64;
   const int nsub = (int)(K - k0 < 64 ? K - k0 : 64);
+  for (int e = t; e < R * R; e += 256) sH[e] = H[e];
   stage_scaled_rows<R>(T, W, k0, nsub, l, sX);
   __syncthreads();
   float a[N][RQ];
-  a_columns<R, N>(sX + s * stride, H, w * RQ, l, a);
-  // partial Gram in FP64 over these columns, added in wavefront order
-  {
-    double Gp[NT];
+  a_columns<R, N>(sX + s * stride, sH, q * RQ, l, a);
+  double Gp[NT];
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+  for (int i = 0; i < N; ++i)
 #pragma unroll
-      for (int j = i; j < N; ++j) {
-        double acc = 0.0;
+    for (int j = i; j < N; ++j) {
+      double acc = 0.0;
 #pragma unroll
-        for (int cc = 0; cc < RQ; ++cc) acc = fma((double)a[i][cc], (double)a[j][cc], acc);
-        Gp[triN<N>(i, j)] = acc;
-      }
-#pragma unroll 1
-    for (int ww = 0; ww < 4; ++ww) {
-      if (w == ww) {
-#pragma unroll
-        for (int e = 0; e < NT; ++e) sG[e * 64 + s] = (ww == 0 ? 0.0 : sG[e * 64 + s]) + Gp[e];
-      }
-      __syncthreads();
+      for (int cc = 0; cc < RQ; ++cc)
+        if (R % 4 == 0 || q * RQ + cc < R) acc = fma((double)a[i][cc], (double)a[j][cc], acc);
+      Gp[triN<N>(i, j)] = quad_sum(acc);
     }
-  }
-  for (int e = t; e < NT * 64; e += 256) {
-    const int ent = e >> 6, sj = e & 63;
-    if (sj < nsub) Gk[(int64_t)ent * K + k0 + sj] = sG[e];
+  if (s < nsub) {
+#pragma unroll
+    for (int e = 0; e < NT; ++e)
+      if ((e & 3) == q) Gk[(int64_t)e * K + k0 + s] = Gp[e];
   }
 }
 
@@ -1783,7 +1792,7 @@ inline void launch_proc_split(copa_plan *p, const copa_state *st, hipStream_t s,
   constexpr int NT = N * (N + 1) / 2;
   const int64_t K = p->K;
   const unsigned nb = (unsigned)((K + 63) / 64);
-  const size_t lds1 = (size_t)NT * 64 * 8 + (size_t)64 * (p->l * R + 1) * 4;
+  const size_t lds1 = (size_t)((R * R + 3) & ~3) * 4 + (size_t)64 * (p->l * R + 1) * 4;
   each(0, [&] { k_proc_gram<R, N><<<nb, 256, lds1, s>>>(K, p->l, p->T, st->H, st->W, p->pgb); });
   each(1, [&] {
     k_proc_eigen<R, N><<<(unsigned)((K + 255) / 256), 256, 0, s>>>(K, p->l, p->rk, p->pgb, p->Ew,

@@ -103,15 +103,22 @@ def check_fit(tag, coh, g, o, prob, R, fit_rtol=None, cong_min=None, spars_entri
                              stacked_U(o.Qtilde, o.H)))
     J = g["V"].shape[0]
     dz = abs(rep["sparsity_V"] - o.sparsity[-1]) * J * R
+    # the zero pattern of V: an entry zero on one side only must lie within rounding of the
+    # prox threshold, i.e. be tiny on the other side (FP32 and FP64 decide such ties differently)
+    zg, zo = g["V"] == 0.0, o.V == 0.0
+    odd = zg != zo
+    vmax = max(np.abs(o.V).max(), 1e-30)
+    odd_mag = max(np.abs(g["V"][odd]).max(initial=0.0), np.abs(o.V[odd]).max(initial=0.0)) / vmax
     band = ambiguous_band(o.sigmas)
     rd_o = rank_deficient(o, prob, R)
     print(tag, f"fit_gpu={rep['fit']:.9f} fit_oracle={o.fit[-1]:.9f} fit_rel={hist[-1]:.2e} "
           f"hist_max={hist.max():.2e} obj_max={obj.max():.2e} spars={rep['sparsity_V']:.4f}/"
-          f"{o.sparsity[-1]:.4f} rank_def={rep['rank_deficient']}/{rd_o} band={band} "
+          f"{o.sparsity[-1]:.4f} zero_pattern_diff={int(odd.sum())} (max rel {odd_mag:.1e}) "
+          f"rank_def={rep['rank_deficient']}/{rd_o} band={band} "
           + " ".join(f"cong_{k}={v:.7f}" for k, v in cong.items()), flush=True)
     assert hist[-1] <= fit_rtol and hist.max() <= 10 * fit_rtol
     assert obj.max() <= 10 * fit_rtol
-    assert dz <= spars_entries + 1e-9
+    assert dz <= spars_entries + 1e-9 or (odd_mag <= 1e-5 and odd.mean() <= 0.01)
     assert abs(rep["rank_deficient"] - rd_o) <= band
     assert min(cong.values()) >= cong_min
     assert np.isclose(rep["sparsity_V"], float(np.mean(g["V"] == 0.0)))
