@@ -1906,6 +1906,36 @@ __device__ __forceinline__ void admm_lanes(double F, float &Zb, float &D,
   }
 }
 
+// The inner ADMM steps of admm_lanes in FP32 arithmetic (the system (G + rho I)^{-1} is formed in
+// FP64 and rounded once; sGi: its FP32 copy in LDS, lanes of one column reading the same word),
+// the product in four partial sums, which shortens the dependency chain of each step. The state
+// Zb, D and the MTTKRP row F are FP32 values already.
+template <int R>
+__device__ __forceinline__ void admm_lanes_reg(float F, float &Zb, float &D,
+                                               const float *__restrict__ sGi, float rho,
+                                               int kind, float lam, int iters, float *xrow,
+                                               int c) {
+  const float thr = lam / rho;
+  for (int it = 0; it < iters; ++it) {
+    xrow[c] = fmaf(rho, Zb + D, F);
+    __builtin_amdgcn_wave_barrier();
+    float zs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < R; ++k) zs[k & 3] = fmaf(xrow[k], sGi[k * R + c], zs[k & 3]);
+    const float z = (zs[0] + zs[1]) + (zs[2] + zs[3]);
+    __builtin_amdgcn_wave_barrier();
+    const float x = z - D;
+    const float a1 = fabsf(x) - thr, a2 = x - thr;
+    float zb = x;
+    zb = kind == COPA_PROX_NONNEG ? (x > 0.0f ? x : 0.0f) : zb;
+    zb = kind == COPA_PROX_L1 ? (a1 > 0.0f ? copysignf(a1, x) : 0.0f) : zb;
+    zb = kind == COPA_PROX_L0 ? (x * x > lam ? x : 0.0f) : zb;
+    zb = kind == COPA_PROX_NONNEG_L1 ? (a2 > 0.0f ? a2 : 0.0f) : zb;
+    D = D + zb - z;
+    Zb = zb;
+  }
+}
+
 // ======================================================================= FIT of an iteration
 // Inputs of the FIT and objective of outer iteration `it`, left as per-block partials by the V
 // update and the W update of that iteration.
@@ -2101,8 +2131,9 @@ __global__ void __launch_bounds__(256)
 
 // ======================================================================= mode W (R lanes/subject)
 // One subject per group of R lanes (lane c holds column c): F_W(k, c) = sum_i (q_i H)(c) t_i(c)
-// (the q rows exchanged through wavefront-local LDS), the inner ADMM steps on W's row k, then the
-// M rows (q_i H) * w_k for pass 2 and the Psi Gram; per-block |W|_1 for the objective.
+// (the q rows exchanged through wavefront-local LDS), the inner ADMM steps on W's row k (FP32, as
+// admm_lanes_reg), then the M rows (q_i H) * w_k for pass 2 and the Psi Gram; per-block |W|_1 for
+// the objective.
 template <int R>
 __global__ void __launch_bounds__(256)
     k_w_admm(int64_t K, int l, const int32_t *__restrict__ subj, const int32_t *__restrict__ rk,
@@ -2111,15 +2142,15 @@ __global__ void __launch_bounds__(256)
              float *__restrict__ FW, const ModeParams *__restrict__ modes, int kind, double lam,
              int iters, double *__restrict__ l1part) {
   constexpr int G = kWave / R;
-  __shared__ double sGi[R * R];
+  __shared__ float sGi[R * R];
   __shared__ float sH[R * R];
   __shared__ float xq[4][G + 1][kLMax][R];
-  __shared__ double xch[4][G + 1][R];
+  __shared__ float xch[4][G + 1][R];
   __shared__ double sred[256];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int g = lane / R, c = lane % R;
   for (int e = t; e < R * R; e += blockDim.x) {
-    sGi[e] = modes[1].Gi[e];
+    sGi[e] = (float)modes[1].Gi[e];
     sH[e] = H[e];
   }
   const int64_t k = ((int64_t)blockIdx.x * 4 + wave) * G + g;
@@ -2137,7 +2168,7 @@ __global__ void __launch_bounds__(256)
   }
   if (!act) m = 0;
   __syncthreads();
-  const double rho = modes[1].rho;
+  const float rho = (float)modes[1].rho;
   double F = 0.0;
   float qh[kLMax];  // smoothed: (q_i H)(c) of the l rows, kept for the M rows
   float(&xg)[kLMax][R] = xq[wave][g];
@@ -2173,7 +2204,7 @@ __global__ void __launch_bounds__(256)
     }
   }
   if (act) FW[k * R + c] = (float)F;
-  admm_lanes<R>(F, Zb, D, sGi, rho, kind, lam, iters, xch[wave][g], c);
+  admm_lanes_reg<R>((float)F, Zb, D, sGi, rho, kind, (float)lam, iters, xch[wave][g], c);
   double l1 = 0.0;
   if (act) {
     W[k * R + c] = Zb;
@@ -2209,29 +2240,6 @@ __global__ void __launch_bounds__(256)
 }
 
 // ======================================================================= W block first
-// The inner ADMM steps of admm_lanes, the product with (G + rho I)^{-1} (sGi, LDS: lanes of one
-// column read the same word, the R columns adjacent words) in four partial sums, which shortens
-// the dependency chain of each step.
-template <int R>
-__device__ __forceinline__ void admm_lanes_reg(double F, float &Zb, float &D,
-                                               const double *__restrict__ sGi, double rho,
-                                               int kind, double lam, int iters, double *xrow,
-                                               int c) {
-  const double thr = lam / rho;
-  for (int it = 0; it < iters; ++it) {
-    xrow[c] = F + rho * ((double)Zb + (double)D);
-    __builtin_amdgcn_wave_barrier();
-    double zs[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int k = 0; k < R; ++k) zs[k & 3] += xrow[k] * sGi[k * R + c];
-    const double z = (zs[0] + zs[1]) + (zs[2] + zs[3]);
-    __builtin_amdgcn_wave_barrier();
-    const double zb = prox_sel(z - (double)D, kind, lam, thr);
-    D = (float)((double)D + zb - z);
-    Zb = (float)zb;
-  }
-}
-
 // Adds the per-lane column accumulators acc[r] = X(r, c) of the 4 G lane groups of a block in a
 // fixed order (groups of a wavefront in turn through LDS, then the four wavefronts) and stores
 // the block's R x R partial. Whole block; red: 4 x R x R doubles of LDS.
@@ -2260,13 +2268,13 @@ __device__ __forceinline__ void block_columns_to_part(const double (&acc)[R], do
 // running sums of F_H(:, c) = sum_k P_k(:, c) w_k(c) and (W^T W)(:, c).
 template <int R>
 __device__ __forceinline__ void w_first_row(int64_t k, bool act, double F, const float (&pc)[R],
-                                            float Zb, float D, const double *__restrict__ sGi,
-                                            double rho, int kind, double lam, int iters,
-                                            double *xrow, int c, float *__restrict__ W,
+                                            float Zb, float D, const float *__restrict__ sGi,
+                                            float rho, int kind, float lam, int iters,
+                                            float *xrow, int c, float *__restrict__ W,
                                             float *__restrict__ DW, float *__restrict__ FW,
                                             double (&fh)[R], double (&wtw)[R], double &l1) {
   if (act) FW[k * R + c] = (float)F;
-  admm_lanes_reg<R>(F, Zb, D, sGi, rho, kind, lam, iters, xrow, c);
+  admm_lanes_reg<R>((float)F, Zb, D, sGi, rho, kind, lam, iters, xrow, c);
   const double w = act ? (double)Zb : 0.0;
   if (act) {
     W[k * R + c] = Zb;
@@ -2277,10 +2285,10 @@ __device__ __forceinline__ void w_first_row(int64_t k, bool act, double F, const
   for (int r = 0; r < R; ++r) fh[r] += (double)pc[r] * w;
   // W^T W: the new row through this group's LDS slot
   __builtin_amdgcn_wave_barrier();
-  xrow[c] = w;
+  xrow[c] = (float)w;
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
-  for (int r = 0; r < R; ++r) wtw[r] += xrow[r] * w;
+  for (int r = 0; r < R; ++r) wtw[r] += (double)xrow[r] * w;
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -2306,26 +2314,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R <= 2
   constexpr int G = kWave / R;
   __shared__ float xq[4][G + 1][kLMax][R];
   __shared__ float xtq[4][G + 1][kLMax][R];
-  __shared__ double xch[4][G + 1][R];
+  __shared__ float xch[4][G + 1][R];
   __shared__ double red[4][R * R];
-  __shared__ double sGi[R * R];
+  __shared__ float sGi[R * R];
   __shared__ double sred[256];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int g = lane / R, c = lane % R;
   double fh[R], wtw[R];
   float hcol[R];
-  for (int e = t; e < R * R; e += blockDim.x) sGi[e] = modes[1].Gi[e];
+  for (int e = t; e < R * R; e += blockDim.x) sGi[e] = (float)modes[1].Gi[e];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     hcol[r] = H[r * R + c];
     fh[r] = 0.0;
     wtw[r] = 0.0;
   }
-  const double rho = modes[1].rho;
+  const float rho = (float)modes[1].rho, lamf = (float)lam;
   __syncthreads();
   float(&xg)[kLMax][R] = xq[wave][g];
   float(&xt)[kLMax][R] = xtq[wave][g];
-  double *xrow = xch[wave][g];
+  float *xrow = xch[wave][g];
   double l1 = 0.0;
   const int64_t stride = (int64_t)gridDim.x * 4 * G;
   const int64_t first = (int64_t)blockIdx.x * 4 * G + wave * G + g;
@@ -2376,7 +2384,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R <= 2
       double F = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) F += (double)hcol[r] * (double)pc[r];
-      w_first_row<R>(k, act, F, pc, Zb, D, sGi, rho, kind, lam, iters, xrow, c, W, DW, FW, fh,
+      w_first_row<R>(k, act, F, pc, Zb, D, sGi, rho, kind, lamf, iters, xrow, c, W, DW, FW, fh,
                      wtw, l1);
 #pragma unroll
       for (int i = 0; i < kLMax; ++i) {
@@ -2408,7 +2416,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R <= 2
       double F = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) F += (double)hcol[r] * (double)pc[r];
-      w_first_row<R>(k, act, F, pc, Zb, D, sGi, rho, kind, lam, iters, xrow, c, W, DW, FW, fh,
+      w_first_row<R>(k, act, F, pc, Zb, D, sGi, rho, kind, lamf, iters, xrow, c, W, DW, FW, fh,
                      wtw, l1);
     }
   }
