@@ -215,6 +215,9 @@ def main():
                          "1's H -> W -> V (same fixed points, different iterates)")
     ap.add_argument("--both-orders", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the other block order (reported under other_order)")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="fixed-order mode: every reduction in a fixed order, bitwise "
+                         "reproducible runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (HBM counter scaling)")
@@ -249,7 +252,8 @@ def main():
         same steps again with HIP events around every kernel launch."""
         plan = copa.Plan.from_cohort(coh, R=R, l=l, inner_iters=cfg["inner"],
                                      precision=copa.PREC_MIXED if mixed else copa.PREC_FP32,
-                                     mixed_refine=1, order=order)
+                                     mixed_refine=1, order=order,
+                                     deterministic=args.deterministic)
         progress(f"plan ready (order {order})")
         init = plan.new_state(H0, W0, V0)
         state = plan.new_state(H0, W0, V0)
@@ -366,7 +370,8 @@ def main():
                    "streamed": (f"projected pairs C_k^T X_k ({npairs} records, "
                                 + ("16-byte bfloat16" if mixed else "32-byte FP32") + ")")
                    if npairs else "nonzeros and basis rows",
-                   "precision": args.precision, "block_order": args.order},
+                   "precision": args.precision, "block_order": args.order,
+                   "deterministic": args.deterministic},
         "gate": gate,
         "launch_shapes": shapes,
         "value_if_ungated": value,

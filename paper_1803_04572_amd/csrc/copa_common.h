@@ -180,7 +180,7 @@ struct copa_plan {
   int64_t t_cnt[copa::kNumKernels] = {};
   // launch shapes (set by the autotuner at the first copa_fit, else the defaults below)
   int p1_per_cu = 4;         // pass-1 persistent blocks per compute unit (LDS permitting)
-  int proc_variant = 0;      // smoothed R > 16 Procrustes: 0 lane-per-subject blocks, 1 four-wavefront
+  int proc_variant = 2;      // smoothed R > 16 Procrustes: 0 lane-per-subject blocks, 1 four-wavefront
                              // blocks, 2 three launches (Gram, eigenproblems without LDS, Q)
   double *pgb = nullptr;     // [36 x K] per-subject Gram, then B, of the three-launch Procrustes
   int p2_blocks = 0;         // pass-2 grid width (<= p2_blocks_cap)

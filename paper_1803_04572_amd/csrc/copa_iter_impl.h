@@ -235,13 +235,15 @@ __global__ void __launch_bounds__(256)
 // of C_k^T X_k. Same persistent blocks, LDS-staged tiles, lane groups and reduce-scatter as
 // k_pass1; a lane streams every G-th pair of its subject, four records in flight, with no
 // dependent loads (a pair carries its feature id).
-template <int RT, int PW, bool BF>
+template <int RT, int PW, bool BF, int LC = 0>
 __global__ void __launch_bounds__(256)
     k_pass1p(const WaveEntry *__restrict__ waves, int n_waves, const int32_t *__restrict__ order,
              const int32_t *__restrict__ pp, const void *__restrict__ recs,
-             const float *__restrict__ Vp, int64_t J, int R, int l, int cg,
+             const float *__restrict__ Vp, int64_t J, int R, int l_in, int cg,
              float *__restrict__ T, float *__restrict__ FV, FitScalars *sc) {
   constexpr int RTP = row4(RT);
+  constexpr int LM = LC > 0 ? LC : kLMax;  // basis functions held (LC: l fixed at compile time)
+  const int l = LC > 0 ? LC : l_in;
   extern __shared__ float4 smem4[];
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) sc->cur += 1;
   if (blockIdx.y == 0)
@@ -277,9 +279,9 @@ __global__ void __launch_bounds__(256)
     const bool active = sidx < cnt;
     const int k = active ? order[we.first + sidx] : 0;
     const int p0 = active ? pp[k] : 0, p1 = active ? pp[k + 1] : 0;
-    float acc[kLMax][RT];
+    float acc[LM][RT];
 #pragma unroll
-    for (int a = 0; a < kLMax; ++a)
+    for (int a = 0; a < LM; ++a)
 #pragma unroll
       for (int r = 0; r < RT; ++r) acc[a][r] = 0.0f;
     auto take = [&](const float (&f)[PW]) {
@@ -287,7 +289,7 @@ __global__ void __launch_bounds__(256)
       float v[RT];
       lds_row<RT>(sV + j * RTP, v);
 #pragma unroll
-      for (int a = 0; a < kLMax; ++a)
+      for (int a = 0; a < LM; ++a)
         if (a < l)
 #pragma unroll
           for (int r = 0; r < RT; ++r) acc[a][r] += f[a] * v[r];
@@ -300,7 +302,7 @@ __global__ void __launch_bounds__(256)
       for (int u = 0; u < 4; ++u)
         if (q + u * G < p1) take(f[u]);
     }
-    constexpr int E = kLMax * RT;
+    constexpr int E = LM * RT;
     float *dst = T + (int64_t)k * l * R + c0;
     auto scatter_store = [&](auto gc) {
       constexpr int Gc = decltype(gc)::value;
@@ -2688,10 +2690,19 @@ static void launch_pass1_rt(copa_plan *p, const float *, hipStream_t s) {
                                               p->row, p->col, p->val, p->xc, p->C, p->Vp, p->J, \
                                               p->R, p->l, cg, p->T, p->FV, p->scal)
   if (p->proj) {
-    if (p->use_bf)
+    // the common basis size l = 7 has its own instances (fewer accumulators, no row guards)
+    if (p->use_bf && p->l == 7)
+      k_pass1p<RT, 8, true, 7><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1, p->pp,
+                                                         p->pairs1h, p->Vp, p->J, p->R, p->l, cg,
+                                                         p->T, p->FV, p->scal);
+    else if (p->use_bf)
       k_pass1p<RT, 8, true><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1, p->pp,
                                                       p->pairs1h, p->Vp, p->J, p->R, p->l, cg,
                                                       p->T, p->FV, p->scal);
+    else if (p->pw == 8 && p->l == 7)
+      k_pass1p<RT, 8, false, 7><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1,
+                                                          p->pp, p->pairs1, p->Vp, p->J, p->R,
+                                                          p->l, cg, p->T, p->FV, p->scal);
     else if (p->pw == 8)
       k_pass1p<RT, 8, false><<<grid, block, lds, s>>>(p->waves1, p->n_waves1, p->order1, p->pp,
                                                        p->pairs1, p->Vp, p->J, p->R, p->l, cg,
@@ -2755,6 +2766,16 @@ static void launch_pass2_rt(copa_plan *p, hipStream_t s) {
     default: RT_SWITCH(rt, FN, __VA_ARGS__); break;                                          \
   }
 
+
+// Pass 2 in the plan's form: feature-sorted chunks (pairs or rows) or the unchunked row pass.
+template <int R>
+static void launch_pass2_any(copa_plan *p, hipStream_t s) {
+  if (p->p2c || p->proj) {
+    RT2_SWITCH(R, p->tiles2.rt, launch_pass2c_rt, p, s);
+  } else {
+    RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s);
+  }
+}
 
 enum {
   kidPass1, kidProcrustes, kidGramFH, kidModeH, kidWadmm, kidGramWM, kidPass2, kidVadmm,
@@ -2901,13 +2922,7 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   timed(p, s, kidGramWM, [&] {
     gram<R>(p, st->W, st->W, K, nullptr, 0, kSlotWtW, p->M, p->rows_total, kSlotPsi, s);
   });
-  timed(p, s, kidPass2, [&] {
-    if (p->p2c || p->proj) {
-      RT2_SWITCH(R, p->tiles2.rt, launch_pass2c_rt, p, s);
-    } else {
-      RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s);
-    }
-  });
+  timed(p, s, kidPass2, [&] { launch_pass2_any<R>(p, s); });
   timed(p, s, kidVadmm, [&] {
     k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(
         p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, row4(p->tiles.rt),
@@ -2947,13 +2962,7 @@ static void iteration_whv_r(copa_plan *p, const copa_state *st, hipStream_t s) {
     k_gram_reduce<R * R><<<dim3((R * R + 3) / 4, 1), 256, 0, s>>>(
         gram_slot(p, kSlotPsi), gram_total(p, kSlotPsi), nullptr, nullptr, nb);
   });
-  timed(p, s, kidPass2, [&] {
-    if (p->p2c || p->proj) {
-      RT2_SWITCH(R, p->tiles2.rt, launch_pass2c_rt, p, s);
-    } else {
-      RT_SWITCH(p->tiles.rt, launch_pass2_rt, p, s);
-    }
-  });
+  timed(p, s, kidPass2, [&] { launch_pass2_any<R>(p, s); });
   timed(p, s, kidVadmm, [&] {
     k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(
         p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, row4(p->tiles.rt),
@@ -3093,7 +3102,7 @@ copa_status RankOps<R>::tune(copa_plan *p, const copa_state *st, hipStream_t s) 
     for (int b : {p->p2_blocks_cap / 4, p->p2_blocks_cap / 2, p->p2_blocks_cap}) {
       if (b < 1) continue;
       p->p2_blocks = b;
-      const float t = time_it([&] { RT2_SWITCH(R, p->tiles2.rt, launch_pass2c_rt, p, s); });
+      const float t = time_it([&] { launch_pass2_any<R>(p, s); });
       if (t < best_t) best_t = t, best_b = b;
     }
     p->p2_blocks = best_b;

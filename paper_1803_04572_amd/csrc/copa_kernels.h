@@ -452,15 +452,36 @@ __global__ void __launch_bounds__(512)
   }
 }
 
-// F[e] += sum over blocks b = 0, 1, ... of part[b][e], in that order (fixed-order mode).
-static __global__ void __launch_bounds__(256)
+// F[e] += the sum over blocks b of part[b][e] in a fixed order (fixed-order mode): 64 entries per
+// block of 512 threads, thread group g = 0..7 sums the slices b = g, g + 8, ... in that order (eight
+// loads in flight), and the eight group sums are added as a fixed tree.
+constexpr int kFvSumThreads = 512;
+static __global__ void __launch_bounds__(kFvSumThreads)
     k_fv_sum(const float *__restrict__ part, int nb, int64_t n, float *__restrict__ F) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    float acc = F[e];
-    for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * n + e];
-    F[e] = acc;
+  __shared__ float red[8][64];
+  const int t = threadIdx.x, c = t & 63, g = t >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + c;
+  float acc = 0.0f;
+  if (e < n) {
+    int b = g;
+    for (; b + 56 < nb; b += 64) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + 8 * u) * n + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; b < nb; b += 8) acc += part[(int64_t)b * n + e];
   }
+  red[g][c] = acc;
+  __syncthreads();
+  if (g == 0 && e < n)
+    F[e] += ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) +
+            ((red[4][c] + red[5][c]) + (red[6][c] + red[7][c]));
+}
+
+inline void launch_fv_sum(const float *part, int nb, int64_t n, float *F, hipStream_t s) {
+  k_fv_sum<<<(unsigned)((n + 63) / 64), kFvSumThreads, 0, s>>>(part, nb, n, F);
 }
 
 // ------------------------------------------------------------------ projected pairs
@@ -712,8 +733,7 @@ inline void launch_pass2p(const copa_plan *p, float *F, hipStream_t s) {
                                                     part);
   if (part) {
     const int64_t n = p->J * p->R;
-    k_fv_sum<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256)), 256, 0,
-               s>>>(part, gx, n, F);
+    launch_fv_sum(part, gx, n, F, s);
   }
 }
 
@@ -733,8 +753,7 @@ inline void launch_pass2c(const copa_plan *p, const float *Mrows, float *F, hipS
                                              SMOOTH ? p->l : 0, F, part);
   if (part) {
     const int64_t n = p->J * p->R;
-    k_fv_sum<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256)), 256, 0,
-               s>>>(part, gx, n, F);
+    launch_fv_sum(part, gx, n, F, s);
   }
 }
 

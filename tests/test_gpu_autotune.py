@@ -47,7 +47,7 @@ def test_untuned_plan_keeps_default_shapes():
     g = run_gpu(coh, 20, cfg["l"], 2, adjoint=False, autotune=False)
     p = g["plan"]
     assert p.query("tuned") == 0
-    assert p.query("pass1_blocks_per_cu") == 4 and p.query("procrustes_variant") == 0
+    assert p.query("pass1_blocks_per_cu") == 4 and p.query("procrustes_variant") == 2
     d = run_gpu(coh, 20, cfg["l"], 2, adjoint=False, deterministic=True)
     assert d["plan"].query("tuned") == 0  # fixed summation order: fixed shapes
 
