@@ -539,13 +539,14 @@ __device__ __forceinline__ void fetch_rec(const void *__restrict__ recs,
 // eight wave slices on feature boundaries; each lane sums a contiguous run of its wave's slice
 // feature by feature, and the segmented scan over lanes of k_pass2c joins runs that share a
 // feature, so each feature is added to the block's LDS copy of F_V by one lane.
-template <int RT, int PW, bool BF>
+template <int RT, int PW, bool BF, int LC = 0>
 __global__ void __launch_bounds__(512)
     k_pass2p(int nchunks, const int32_t *__restrict__ cq, const int32_t *__restrict__ cinfo,
              const int32_t *__restrict__ wsplit, const void *__restrict__ recs,
              const uint16_t *__restrict__ feat_hi, const float *__restrict__ M, int64_t J, int R,
-             int l, float *__restrict__ FV, float *__restrict__ part) {
+             int l_in, float *__restrict__ FV, float *__restrict__ part) {
   constexpr int RTP = row4(RT);
+  const int l = LC > 0 ? LC : l_in;  // LC: the basis size fixed at compile time
   constexpr int PF = 4;  // records per lane loaded ahead of the chunk's M staging
   extern __shared__ float4 smem4[];
   float *sF = reinterpret_cast<float *>(smem4);
@@ -719,10 +720,19 @@ inline void launch_pass2p(const copa_plan *p, float *F, hipStream_t s) {
   const dim3 grid((unsigned)gx, (unsigned)p->tiles2.nt);
   const size_t lds = ((size_t)p->J * row4(RT) + (size_t)kChunkRows * row4(RT) + 4) * sizeof(float);
   float *part = p->opt.deterministic ? p->fvpart : nullptr;
-  if (p->use_bf)
+  // the common basis size l = 7 has its own instances (no row guards)
+  if (p->use_bf && p->l == 7)
+    k_pass2p<RT, 8, true, 7><<<grid, 512, lds, s>>>(p->pnchunks, p->pcq, p->pcinfo, p->pwsplit,
+                                                     p->pairs2h, p->feat2h, p->M, p->J, p->R,
+                                                     p->l, F, part);
+  else if (p->use_bf)
     k_pass2p<RT, 8, true><<<grid, 512, lds, s>>>(p->pnchunks, p->pcq, p->pcinfo, p->pwsplit,
                                                   p->pairs2h, p->feat2h, p->M, p->J, p->R, p->l,
                                                   F, part);
+  else if (p->pw == 8 && p->l == 7)
+    k_pass2p<RT, 8, false, 7><<<grid, 512, lds, s>>>(p->pnchunks, p->pcq, p->pcinfo, p->pwsplit,
+                                                      p->pairs2, nullptr, p->M, p->J, p->R, p->l,
+                                                      F, part);
   else if (p->pw == 8)
     k_pass2p<RT, 8, false><<<grid, 512, lds, s>>>(p->pnchunks, p->pcq, p->pcinfo, p->pwsplit,
                                                    p->pairs2, nullptr, p->M, p->J, p->R, p->l, F,
