@@ -2242,6 +2242,15 @@ __global__ void __launch_bounds__(256)
 }
 
 // ======================================================================= W block first
+// F_W(k, c) = sum_r H(r, c) P_k(r, c) for lane c: FP32 products of FP32 data in four partial sums.
+template <int R>
+__device__ __forceinline__ float column_dot(const float (&hcol)[R], const float (&pc)[R]) {
+  float fs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int r = 0; r < R; ++r) fs[r & 3] = fmaf(hcol[r], pc[r], fs[r & 3]);
+  return (fs[0] + fs[1]) + (fs[2] + fs[3]);
+}
+
 // Adds the per-lane column accumulators acc[r] = X(r, c) of the 4 G lane groups of a block in a
 // fixed order (groups of a wavefront in turn through LDS, then the four wavefronts) and stores
 // the block's R x R partial. Whole block; red: 4 x R x R doubles of LDS.
@@ -2383,9 +2392,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R <= 2
 #pragma unroll
         for (int r = 0; r < R; ++r) pc[r] = fmaf(xg[i][r], ti, pc[r]);
       }
-      double F = 0.0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) F += (double)hcol[r] * (double)pc[r];
+      const double F = column_dot<R>(hcol, pc);
       w_first_row<R>(k, act, F, pc, Zb, D, sGi, rho, kind, lamf, iters, xrow, c, W, DW, FW, fh,
                      wtw, l1);
 #pragma unroll
@@ -2415,9 +2422,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R <= 2
 #pragma unroll
         for (int r = 0; r < R; ++r) pc[r] = fmaf(xg[0][r], ti, pc[r]);
       }
-      double F = 0.0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) F += (double)hcol[r] * (double)pc[r];
+      const double F = column_dot<R>(hcol, pc);
       w_first_row<R>(k, act, F, pc, Zb, D, sGi, rho, kind, lamf, iters, xrow, c, W, DW, FW, fh,
                      wtw, l1);
     }
