@@ -184,6 +184,7 @@ struct copa_plan {
                              // blocks, 2 three launches (Gram, eigenproblems without LDS, Q)
   double *pgb = nullptr;     // [36 x K] per-subject Gram, then B, of the three-launch Procrustes
   int p2_blocks = 0;         // pass-2 grid width (<= p2_blocks_cap)
+  bool vtv_reduce = false;   // the V blocks' V^T V partials are added by k_gram_reduce (many, large)
   int gram_blocks = 0;       // row-Gram blocks (<= gmaxnb)
   int tuned = 0;             // 0 not yet, 1 timed on this plan, 2 read from the cache file
   float tune_ms = 0.0f;      // time the tuner took

@@ -1943,7 +1943,8 @@ __device__ __forceinline__ void admm_lanes_reg(float F, float &Zb, float &D,
 // update and the W update of that iteration.
 struct FitArgs {
   const double *vpart;    // [nvb x 4] <F_V, V>, |V|_1, zeros
-  const double *vtvpart;  // [nvb x R x R] V^T V
+  const double *vtvpart;  // [nvtv x R x R] V^T V: the V blocks' partials, or their sum (nvtv 1)
+  int nvtv;
   int nvb;
   const double *wl1part;  // [nwb] |W|_1
   int nwb;
@@ -1963,7 +1964,7 @@ __device__ __forceinline__ void fit_finalize(const FitArgs &fa, int it, const fl
                                              double *sVtV) {
   constexpr int RR = R * R;
   const int t = threadIdx.x;
-  block_reduce_parts<RR>(fa.vtvpart, fa.nvb, sVtV, red[0]);
+  block_reduce_parts<RR>(fa.vtvpart, fa.nvtv, sVtV, red[0]);
   double dot = 0.0, l1 = 0.0, zeros = 0.0, wl1 = 0.0, hl1 = 0.0, quad = 0.0;
   for (int b = t; b < fa.nvb; b += blockDim.x) {
     dot += fa.vpart[b * 4 + 0];
@@ -2815,7 +2816,9 @@ static FitArgs fit_args(const copa_plan *p) {
   const copa_options &o = p->opt;
   FitArgs fa;
   fa.vpart = p->vpart;
-  fa.vtvpart = gram_slot(p, kSlotVtV);
+  // many large V^T V partials are added by a launch of their own right after the V update
+  fa.vtvpart = p->vtv_reduce ? gram_total(p, kSlotVtV) : gram_slot(p, kSlotVtV);
+  fa.nvtv = p->vtv_reduce ? 1 : p->n_vblocks;
   fa.nvb = p->n_vblocks;
   fa.wl1part = p->wpart;
   fa.nwb = p->opt.order == COPA_ORDER_WHV ? wf_grid(p, p->K) : p->n_wblocks;
@@ -2933,6 +2936,9 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
         p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, row4(p->tiles.rt),
         gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->scal, o.prox_V,
         o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV));
+    if (p->vtv_reduce)
+      k_gram_reduce<R * R><<<dim3((R * R + 3) / 4, 1), 256, 0, s>>>(
+          gram_slot(p, kSlotVtV), gram_total(p, kSlotVtV), nullptr, nullptr, p->n_vblocks);
   });
 }
 
@@ -2973,6 +2979,9 @@ static void iteration_whv_r(copa_plan *p, const copa_state *st, hipStream_t s) {
         p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, row4(p->tiles.rt),
         gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->scal, o.prox_V,
         o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV));
+    if (p->vtv_reduce)
+      k_gram_reduce<R * R><<<dim3((R * R + 3) / 4, 1), 256, 0, s>>>(
+          gram_slot(p, kSlotVtV), gram_total(p, kSlotVtV), nullptr, nullptr, p->n_vblocks);
   });
   timed(p, s, kidFinish, [&] {
     k_finish_whv<R><<<1, 256, 0, s>>>(fit_args(p), 1, st->H, p->small, p->modes, p->scal);

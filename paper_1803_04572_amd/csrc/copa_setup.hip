@@ -463,6 +463,8 @@ static copa_status plan_dims(const copa_tensor *X, const copa_options *opt, copa
     p->n_vblocks =
         (int)std::max<int64_t>(1, std::min<int64_t>((p->J + rb - 1) / rb, 4 * std::max(1, p->n_cu)));
   }
+  // V^T V partials beyond 64k doubles in all: a multi-block reduction instead of the FIT block's
+  p->vtv_reduce = (int64_t)p->n_vblocks * R * R > 65536;
   // order W -> H -> V: persistent W-first and M-row launches, at most 4 blocks per compute unit
   p->wf_cap = p->opt.order == COPA_ORDER_WHV ? 4 * std::max(1, p->n_cu) : 0;
   p->wf_blocks = 0;  // set from the kernels' occupancy at the first fit
