@@ -1822,64 +1822,68 @@ inline size_t procrustes_l_lds(int R, int l) {
 
 // ======================================================================= ADMM helpers
 // sGi <- (X * Y + rho I)^{-1} (Hadamard product, FP64, full R x R), rho = trace(X * Y) / R
-// (Algorithm 1). The first wavefront runs Gauss-Jordan elimination on [G + rho I | I], lane i
-// holding row i; at step j lane j puts the live part of its row in LDS and every lane reads it
-// back (wavefront-local, in order). No pivoting is needed because the matrix is symmetric
-// positive definite, and the rho shift bounds its condition number by R + 1, so the explicit
-// inverse is as accurate as triangular solves and turns every later ADMM step into one
-// matrix-vector product. Whole block (sL: R x R LDS scratch). Returns false (and leaves
-// Gi = I, rho = 1) when a pivot is not positive and finite.
+// (Algorithm 1), by Gauss-Jordan elimination on [G + rho I | I] with the whole block: sL holds
+// the left part and sGi the right part, and at step j every thread forms the new values of its
+// entries of the R live columns (left columns j + 1 .. R - 1, right columns 0 .. j) from the old
+// pivot row, then all write them. No pivoting is needed because the matrix is symmetric positive
+// definite, and the rho shift bounds its condition number by R + 1, so the explicit inverse is as
+// accurate as triangular solves and turns every later ADMM step into one matrix-vector product.
+// Blocks of 256 threads. Returns false (and leaves Gi = I, rho = 1) when a pivot is not positive
+// and finite.
 template <int R>
 __device__ __forceinline__ bool build_system(const double *__restrict__ X,
                                              const double *__restrict__ Y, double *sL,
                                              double *sGi, double *srho, int *sflag) {
-  static_assert(R <= kWave, "one row per lane");
-  __shared__ double spiv[R + 1];
+  constexpr int RR = R * R;
+  constexpr int NU = (RR + 255) / 256;  // entries per thread and step
   const int t = threadIdx.x;
-  for (int e = t; e < R * R; e += blockDim.x) sL[e] = X[e] * Y[e];
+  for (int e = t; e < RR; e += blockDim.x) {
+    sL[e] = X[e] * Y[e];
+    sGi[e] = e / R == e % R ? 1.0 : 0.0;
+  }
   __syncthreads();
-  if (t < kWave) {
-    const int row = t < R ? t : 0;
-    double tr = 0.0;
+  double tr = 0.0;
+  for (int i = 0; i < R; ++i) tr += sL[i * R + i];
+  const double rho = tr / R;
+  bool ok = isfinite(rho) && rho > 0.0;
+  __syncthreads();  // every thread has read the diagonal
+  if (t < R) sL[t * R + t] += rho;
+  __syncthreads();
+  for (int j = 0; j < R; ++j) {
+    const double piv = sL[j * R + j];
+    ok = ok && piv > 0.0 && isfinite(piv);
+    const double inv = rcp_nr(piv > 0.0 ? piv : 1.0);
+    const int na = R - 1 - j;  // live left columns
+    double nv[NU];
 #pragma unroll
-    for (int i = 0; i < R; ++i) tr += sL[i * R + i];
-    const double rho = tr / R;
-    bool ok = isfinite(rho) && rho > 0.0;
-    double a[R], b[R];
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      a[c] = sL[row * R + c] + (c == row ? rho : 0.0);
-      b[c] = c == row ? 1.0 : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      // live part of pivot row j: a[j..R-1] and b[0..j] (R + 1 values)
-      if (t == j) {
-#pragma unroll
-        for (int c = j; c < R; ++c) spiv[c - j] = a[c];
-#pragma unroll
-        for (int c = 0; c <= j; ++c) spiv[R - j + c] = b[c];
+    for (int u = 0; u < NU; ++u) {
+      const int e = t + 256 * u;
+      if (e < RR) {
+        const int r = e / R, k = e - (e / R) * R;
+        double *M = k < na ? sL : sGi;
+        const int col = k < na ? j + 1 + k : k - na;
+        const double old = M[r * R + col], pv = M[j * R + col];
+        nv[u] = r == j ? old * inv : old - (sL[r * R + j] * inv) * pv;
       }
-      __builtin_amdgcn_wave_barrier();
-      const double piv = spiv[0];
-      ok = ok && piv > 0.0 && isfinite(piv);
-      const double inv = rcp_nr(piv > 0.0 ? piv : 1.0);
-      const bool me = t == j;
-      const double f = me ? 0.0 : a[j] * inv;
-#pragma unroll
-      for (int c = j + 1; c < R; ++c) a[c] = me ? a[c] * inv : a[c] - f * spiv[c - j];
-#pragma unroll
-      for (int c = 0; c <= j; ++c) b[c] = me ? b[c] * inv : b[c] - f * spiv[R - j + c];
-      __builtin_amdgcn_wave_barrier();
     }
-    if (t < R) {
+    __syncthreads();
 #pragma unroll
-      for (int c = 0; c < R; ++c) sGi[t * R + c] = ok ? b[c] : (c == t ? 1.0 : 0.0);
+    for (int u = 0; u < NU; ++u) {
+      const int e = t + 256 * u;
+      if (e < RR) {
+        const int r = e / R, k = e - (e / R) * R;
+        double *M = k < na ? sL : sGi;
+        const int col = k < na ? j + 1 + k : k - na;
+        M[r * R + col] = nv[u];
+      }
     }
-    if (t == 0) {
-      *srho = ok ? rho : 1.0;
-      *sflag = ok ? 0 : 1;
-    }
+    __syncthreads();
+  }
+  if (!ok)
+    for (int e = t; e < RR; e += blockDim.x) sGi[e] = e / R == e % R ? 1.0 : 0.0;
+  if (t == 0) {
+    *srho = ok ? rho : 1.0;
+    *sflag = ok ? 0 : 1;
   }
   __syncthreads();
   return *sflag == 0;
@@ -2075,7 +2079,8 @@ static void gram_fit(copa_plan *p, const float *A, const float *B, int64_t rows,
 
 // ======================================================================= mode H (one block)
 // G_H = W^TW * V^TV, rho, (G_H + rho I)^{-1}; inner ADMM on the R rows of H (R lanes per row);
-// H^T H; then the W-mode system G_W = H^TH * V^TV for the W update.
+// H^T H; then either the W-mode system G_W = H^TH * V^TV for the W update that follows (H first),
+// or, with the new W's W^T W given (W first), the V-mode system G_V = H^TH * W^TW into modes[2].
 template <int R>
 __global__ void __launch_bounds__(256)
     k_mode_H(const double *FHtot, const double *WtWtot, double *small, ModeParams *modes,
@@ -2125,7 +2130,16 @@ __global__ void __launch_bounds__(256)
     small[kHtH * RR + e] = v;
   }
   __syncthreads();
-  if (!build_w) return;  // (W first: the next W system needs the new V)
+  if (!build_w) {
+    // W first: the next W system needs the new V, the V system of this iteration is known
+    for (int e = t; e < RR; e += blockDim.x) sY[e] = WtWtot[e];
+    __syncthreads();
+    ok = build_system<R>(sX, sY, sL, sGi, &srho, &sflag);
+    if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
+    for (int e = t; e < RR; e += blockDim.x) modes[2].Gi[e] = sGi[e];
+    if (t == 0) modes[2].rho = srho;
+    return;
+  }
   ok = build_system<R>(sX, sY, sL, sGi, &srho, &sflag);
   if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
   for (int e = t; e < RR; e += blockDim.x) modes[1].Gi[e] = sGi[e];
@@ -2541,43 +2555,57 @@ __global__ void __launch_bounds__(256)
 }
 
 // ======================================================================= mode V
-// Every block: G_V = H^TH * W^TW, rho, (G_V + rho I)^{-1}; then its V rows, R lanes per row
-// (inner ADMM, l1 prox), the padded V tile copy for the next pass 1, and per-block partials of
-// <F_V, V>, |V|_1, zeros and V^T V for the FIT (added by the next launch that needs them).
+// The V system of an outer iteration, G_V = H^TH * W^TW, rho and (G_V + rho I)^{-1}, into
+// modes[2] (one block), built once for all blocks of k_v_admm.
+template <int R>
+__global__ void __launch_bounds__(256)
+    k_v_system(const double *__restrict__ WtWtot, const double *__restrict__ small,
+               ModeParams *modes, FitScalars *sc) {
+  constexpr int RR = R * R;
+  __shared__ double sX[RR], sY[RR], sL[RR], sGi[RR];
+  __shared__ double srho;
+  __shared__ int sflag;
+  const int t = threadIdx.x;
+  for (int e = t; e < RR; e += blockDim.x) {
+    sX[e] = small[kHtH * RR + e];
+    sY[e] = WtWtot[e];
+  }
+  __syncthreads();
+  const bool ok = build_system<R>(sX, sY, sL, sGi, &srho, &sflag);
+  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
+  for (int e = t; e < RR; e += blockDim.x) modes[2].Gi[e] = sGi[e];
+  if (t == 0) modes[2].rho = srho;
+}
+
+// Every block: the V system from modes[2]; then its V rows, R lanes per row (inner ADMM, l1
+// prox), the padded V tile copy for the next pass 1, and per-block partials of <F_V, V>, |V|_1,
+// zeros and V^T V for the FIT (added by the next launch that needs them).
 template <int R>
 __global__ void __launch_bounds__(256)
     k_v_admm(int64_t J, const float *__restrict__ FV, float *__restrict__ V,
              float *__restrict__ DV, float *__restrict__ Vp, int rt, int rtp,
              const double *__restrict__ WtWtot, const double *__restrict__ Psitot, double *small,
-             FitScalars *sc, int kind, double lam, int iters, double *__restrict__ vpart,
-             double *__restrict__ vtvpart) {
+             const ModeParams *__restrict__ modes, int kind, double lam, int iters,
+             double *__restrict__ vpart, double *__restrict__ vtvpart) {
   constexpr int RR = R * R;
   constexpr int G = kWave / R;
   constexpr int RB = 4 * G;  // rows per block pass
-  __shared__ double sW[RR], sPsi[RR], sHH[RR], sL[RR], sGi[RR];
+  __shared__ double sGi[RR];
   __shared__ double xch[4][G + 1][R];
   __shared__ float sV[RB][R];
   __shared__ double red[3][256];
-  __shared__ double srho;
-  __shared__ int sflag;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int g = lane / R, c = lane % R;
   const int slot = wave * G + g;
-  for (int e = t; e < RR; e += blockDim.x) {
-    sW[e] = WtWtot[e];
-    sPsi[e] = Psitot[e];
-    sHH[e] = small[kHtH * RR + e];
-  }
-  __syncthreads();
+  for (int e = t; e < RR; e += blockDim.x) sGi[e] = modes[2].Gi[e];
   if (blockIdx.x == 0) {
     for (int e = t; e < RR; e += blockDim.x) {
-      small[kWtW * RR + e] = sW[e];
-      small[kPsi * RR + e] = sPsi[e];
+      small[kWtW * RR + e] = WtWtot[e];
+      small[kPsi * RR + e] = Psitot[e];
     }
   }
-  const bool ok = build_system<R>(sHH, sW, sL, sGi, &srho, &sflag);
-  if (t == 0 && !ok) atomicMin(&sc->fail_iter, sc->cur);
-  const double rho = srho;
+  __syncthreads();
+  const double rho = modes[2].rho;
   double dot = 0.0, l1 = 0.0, zeros = 0.0;
   double vtv[(RR + 255) / 256];
 #pragma unroll
@@ -2932,9 +2960,10 @@ static void iteration_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   });
   timed(p, s, kidPass2, [&] { launch_pass2_any<R>(p, s); });
   timed(p, s, kidVadmm, [&] {
+    k_v_system<R><<<1, 256, 0, s>>>(gram_total(p, kSlotWtW), p->small, p->modes, p->scal);
     k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(
         p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, row4(p->tiles.rt),
-        gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->scal, o.prox_V,
+        gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->modes, o.prox_V,
         o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV));
     if (p->vtv_reduce)
       k_gram_reduce<R * R><<<dim3((R * R + 3) / 4, 1), 256, 0, s>>>(
@@ -2977,7 +3006,7 @@ static void iteration_whv_r(copa_plan *p, const copa_state *st, hipStream_t s) {
   timed(p, s, kidVadmm, [&] {
     k_v_admm<R><<<p->n_vblocks, 256, 0, s>>>(
         p->J, p->FV, st->V, st->D_V, p->Vp, p->tiles.rt, row4(p->tiles.rt),
-        gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->scal, o.prox_V,
+        gram_total(p, kSlotWtW), gram_total(p, kSlotPsi), p->small, p->modes, o.prox_V,
         o.lambda_V, o.inner_iters, p->vpart, gram_slot(p, kSlotVtV));
     if (p->vtv_reduce)
       k_gram_reduce<R * R><<<dim3((R * R + 3) / 4, 1), 256, 0, s>>>(
